@@ -1,0 +1,98 @@
+/*
+ * idp_ref.h -- CPU oracle for one limited SSP-RK stage of the sparse
+ * invariant-domain-preserving (IDP) nodal DG method with subcell convex
+ * limiting (Pazner, "Sparse invariant domain preserving discontinuous
+ * Galerkin methods with subcell convex limiting", arXiv 2004.08503).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, FP64
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * It shares no code, header, table or helper with the GPU library.
+ *
+ * Every routine is single-threaded, allocates with malloc, works on host
+ * pointers and is compiled with -ffp-contract=off (no fused multiply-add).
+ *
+ * Mesh: periodic Cartesian box [0,lx) x [0,ly) split into nx x ny elements
+ * (ny = 1 in 1-D).  Each element carries the (p+1)^d tensor Gauss-Lobatto
+ * nodes.  State layout: u[c][e][b][a], i.e. component c outermost, element
+ * e = ey*nx + ex, then the y node index b, then the x node index a fastest.
+ * The number of nodes is Nn = nx*ny*(p+1)^d and an array holds nc*Nn
+ * doubles, nc = 1 for the scalar laws and d+2 for Euler.
+ */
+#ifndef IDP_REF_H
+#define IDP_REF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2 };
+
+/* Limiter modes: SUBCELL is the subcell convex limiter (Sec. 4.1.3 and
+ * 4.2.2); TARGET returns the unlimited high-order update (eq. ho-update);
+ * LOW returns the low-order IDP update (eq. lo-update / idp-fe). */
+enum { IDP_REF_SUBCELL = 0, IDP_REF_TARGET = 1, IDP_REF_LOW = 2 };
+
+typedef struct {
+  int dim;          /* 1 or 2 */
+  int nx, ny;       /* elements per direction (ny = 1 when dim = 1) */
+  double lx, ly;    /* box lengths */
+  int p;            /* polynomial degree, 1..8 */
+  int eq;           /* IDP_REF_ADVECTION / _BURGERS / _EULER */
+  double vel[2];    /* advection velocity, or Burgers direction vector v */
+  double gamma;     /* ratio of specific heats (Euler) */
+  int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW */
+} idp_ref_desc;
+
+/* Optional per-node outputs of one forward-Euler sub-step.  Any pointer may
+ * be NULL.  Sizes: nc*Nn for uL and uH; dim*nc*Nn for rH, rL and rbar laid
+ * out [k][c][node]; Nn for the rest.  rbar[k][c][i] is the antidiffusive
+ * subcell flux at the subcell face on the +e_k side of node i (zero when
+ * that face is an element face).  umin/umax bound the limited component
+ * (u for scalar laws, rho for Euler); kmin is the Euler entropy bound
+ * K_min = min p*rho^-gamma over the stencil; alpha_z is the Zalesak
+ * coefficient; alpha is the final nodal provisional coefficient. */
+typedef struct {
+  double *uL, *uH, *rH, *rL, *rbar;
+  double *umin, *umax, *kmin, *alpha_z, *alpha;
+} idp_ref_trace;
+
+/* Returns 0 on success, -1 on a bad argument. */
+int idp_ref_check(const idp_ref_desc* d);
+long idp_ref_num_nodes(const idp_ref_desc* d);
+int idp_ref_num_comp(const idp_ref_desc* d);
+
+/* O0 tables: Gauss-Lobatto nodes/weights on [0,1] (sum w = 1), the weighted
+ * differentiation matrix D[a][c] = w_a phi_c'(xi_a) and the sparsified
+ * first-order matrix Dhat, both (p+1)x(p+1) row-major. */
+int idp_ref_gl(int p, double* xi, double* w);
+int idp_ref_dmat(int p, double* D);
+int idp_ref_dhat(int p, double* Dh);
+
+/* Pointwise physics: F[k*nc + c] for k < dim; lambda for the 1-D Riemann
+ * problem with left state uL, right state uR along the unit vector n. */
+int idp_ref_flux(const idp_ref_desc* d, const double* u, double* F);
+double idp_ref_lambda(const idp_ref_desc* d, const double* uL,
+                      const double* uR, const double* n);
+
+/* One forward-Euler sub-step out = FE(u, dt) with the limiter mode of d. */
+int idp_ref_fe(const idp_ref_desc* d, const double* u, double* out,
+               double dt, idp_ref_trace* tr);
+
+/* One SSP-RK3 stage (Shu-Osher form): out = a_s*u_n + b_s*FE(u_s, dt) with
+ * (a_s, b_s) = (0,1), (3/4,1/4), (1/3,2/3) for stage = 0, 1, 2.  u_n may be
+ * NULL for stage 0.  out may alias u_n but not u_s. */
+int idp_ref_stage(const idp_ref_desc* d, const double* u_n, const double* u_s,
+                  double* out, double dt, int stage);
+
+/* Three stages in place. */
+int idp_ref_step(const idp_ref_desc* d, double* u, double dt);
+
+/* Largest dt allowed by the low-order CFL condition (eq. cfl-low):
+ * min_i m_i / (2 sum_{j != i} dhat_ij).  +inf when no dissipation. */
+int idp_ref_max_dt(const idp_ref_desc* d, const double* u, double* dt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,204 @@
+"""Seeded synthetic workloads for the IDP DG stage.
+
+This module only builds problem descriptions and initial states; it holds
+none of the method's arithmetic and imports neither the GPU binding nor the
+oracle, so both sides can take their inputs from it.
+
+All problems are periodic on [0,1]^d, FP64, in the state layout
+``u[c][e][b][a]`` (component, element e = ey*nx + ex, y node, x node).
+Node coordinates use the Gauss-Lobatto points of the element, computed here
+with numpy's Legendre class (a third, independent source of the points).
+
+Workload recipes (the paper's test problems are analytic; there is no
+dataset):
+  * ``advection_1d``  -- u_t + u_x = 0, 64 elements, p = 3, sin(2 pi x) plus
+    a unit pulse on [0.3, 0.5]; dt = 0.2 of the low-order CFL bound.
+  * ``burgers_2d``    -- u_t + (u^2/2)_x + (u^2/2)_y = 0 on 128^2, p = 3:
+    0.5 + 0.5 sin(2 pi x) sin(2 pi y) + 0.05 U(-1,1) per node + a step of 0.5
+    on the elements whose centre has x > 0.5.
+  * ``euler_2d``      -- Euler, gamma = 1.4, 256^2, p = 4: four quadrants
+    (by element centre) with (rho, p) ~ U[0.1, 1.5]^2 and v ~ U[-0.8, 0.8]^2
+    per quadrant, node density times (1 + 0.01 U(-1,1)).
+  * ``batch_mix``     -- many Euler solves of uneven n in [32, 256] and p in
+    {2..6}, each with its own quadrant data.
+"""
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+ADVECTION, BURGERS, EULER = 0, 1, 2
+SUBCELL, TARGET, LOW = 0, 1, 2
+EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
+LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW}
+
+
+@dataclass
+class Problem:
+    dim: int
+    nx: int
+    ny: int
+    p: int
+    eq: int
+    lx: float = 1.0
+    ly: float = 1.0
+    vel: Tuple[float, float] = (1.0, 1.0)
+    gamma: float = 1.4
+    limiter: int = SUBCELL
+
+    @property
+    def nc(self) -> int:
+        return self.dim + 2 if self.eq == EULER else 1
+
+    @property
+    def nodes_per_element(self) -> int:
+        return (self.p + 1) ** self.dim
+
+    @property
+    def num_nodes(self) -> int:
+        return self.nx * self.ny * self.nodes_per_element
+
+    def replace(self, **kw) -> "Problem":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Problem(**d)
+
+
+@dataclass
+class Workload:
+    name: str
+    prob: Problem
+    u0: np.ndarray            # (nc, Nn) float64
+    cfl: float                # dt = cfl * (low-order CFL bound)
+    steps: int
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+
+def gl_points(p: int) -> np.ndarray:
+    """Gauss-Lobatto points on [0,1] (end points and roots of P_p')."""
+    inner = np.polynomial.legendre.Legendre.basis(p).deriv().roots()
+    x = np.concatenate([[-1.0], np.sort(inner.real), [1.0]])
+    return 0.5 * (x + 1.0)
+
+
+def node_coords(prob: Problem):
+    """Physical node coordinates (x, y) in state order; y is None in 1-D."""
+    xi = gl_points(prob.p)
+    hx = prob.lx / prob.nx
+    n1 = prob.p + 1
+    if prob.dim == 1:
+        ex = np.arange(prob.nx)[:, None]
+        x = (ex + xi[None, :]) * hx
+        return x.reshape(-1), None, (ex[:, 0] + 0.5) * hx
+    hy = prob.ly / prob.ny
+    ey, ex = np.meshgrid(np.arange(prob.ny), np.arange(prob.nx), indexing="ij")
+    ey = ey.reshape(-1)[:, None, None]
+    ex = ex.reshape(-1)[:, None, None]
+    b = np.arange(n1)[None, :, None]
+    a = np.arange(n1)[None, None, :]
+    x = (ex + xi[a]) * hx + 0.0 * b
+    y = (ey + xi[b]) * hy + 0.0 * a
+    return x.reshape(-1), y.reshape(-1), None
+
+
+def _element_centres(prob: Problem):
+    n1 = prob.p + 1
+    hx = prob.lx / prob.nx
+    if prob.dim == 1:
+        return ((np.arange(prob.nx) + 0.5) * hx).repeat(n1), None
+    hy = prob.ly / prob.ny
+    ey, ex = np.meshgrid(np.arange(prob.ny), np.arange(prob.nx), indexing="ij")
+    xc = ((ex.reshape(-1) + 0.5) * hx).repeat(n1 * n1)
+    yc = ((ey.reshape(-1) + 0.5) * hy).repeat(n1 * n1)
+    return xc, yc
+
+
+def advection_1d(nx: int = 64, p: int = 3, limiter: int = SUBCELL) -> Workload:
+    prob = Problem(dim=1, nx=nx, ny=1, p=p, eq=ADVECTION, vel=(1.0, 0.0),
+                   limiter=limiter)
+    x, _, _ = node_coords(prob)
+    xc, _ = _element_centres(prob)
+    # a node on an element face takes the value from inside its own element
+    xe = xc + (x - xc) * (1.0 - 1e-9)
+    u = np.sin(2 * np.pi * x) + ((xe >= 0.3) & (xe <= 0.5)).astype(np.float64)
+    return Workload("advection_1d", prob, u[None, :].copy(), cfl=0.2, steps=200)
+
+
+def burgers_2d(n: int = 128, p: int = 3, seed: int = 2,
+               limiter: int = SUBCELL) -> Workload:
+    prob = Problem(dim=2, nx=n, ny=n, p=p, eq=BURGERS, vel=(1.0, 1.0),
+                   limiter=limiter)
+    rng = np.random.default_rng(seed)
+    x, y, _ = node_coords(prob)
+    xc, _ = _element_centres(prob)
+    u = 0.5 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    u = u + 0.05 * rng.uniform(-1.0, 1.0, size=u.shape)
+    u = u + 0.5 * (xc > 0.5)
+    return Workload("burgers_2d", prob, u[None, :].copy(), cfl=0.5, steps=100,
+                    seed=seed)
+
+
+def euler_quadrants(prob: Problem, rng) -> np.ndarray:
+    """Four-quadrant piecewise-constant Riemann data with 1% density noise,
+    returned in conserved variables (rho, rho v, rho E)."""
+    g = prob.gamma
+    rho_p = rng.uniform(0.1, 1.5, size=(4, 2))
+    vel = rng.uniform(-0.8, 0.8, size=(4, 2))
+    xc, yc = _element_centres(prob)
+    if prob.dim == 1:
+        q = (xc > 0.5).astype(int)
+    else:
+        q = (xc > 0.5).astype(int) + 2 * (yc > 0.5).astype(int)
+    rho = rho_p[q, 0] * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=q.shape))
+    pr = rho_p[q, 1]
+    d = prob.dim
+    u = np.empty((d + 2, q.size))
+    u[0] = rho
+    kin = np.zeros(q.size)
+    for k in range(d):
+        u[1 + k] = rho * vel[q, k]
+        kin += vel[q, k] ** 2
+    u[d + 1] = pr / (g - 1.0) + 0.5 * rho * kin
+    return u
+
+
+def euler_2d(n: int = 256, p: int = 4, seed: int = 3,
+             limiter: int = SUBCELL) -> Workload:
+    prob = Problem(dim=2, nx=n, ny=n, p=p, eq=EULER, gamma=1.4, limiter=limiter)
+    rng = np.random.default_rng(seed)
+    u = euler_quadrants(prob, rng)
+    return Workload("euler_2d", prob, u, cfl=0.5, steps=50, seed=seed)
+
+
+def euler_1d(n: int = 64, p: int = 3, seed: int = 5,
+             limiter: int = SUBCELL) -> Workload:
+    prob = Problem(dim=1, nx=n, ny=1, p=p, eq=EULER, gamma=1.4, limiter=limiter)
+    rng = np.random.default_rng(seed)
+    u = euler_quadrants(prob, rng)
+    return Workload("euler_1d", prob, u, cfl=0.5, steps=50, seed=seed)
+
+
+def batch_mix(count: int = 64, n_range=(32, 256), p_choices=(2, 3, 4, 5, 6),
+              seed: int = 4) -> List[Workload]:
+    """Independent Euler solves of uneven mesh size and degree."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        p = int(rng.choice(p_choices))
+        prob = Problem(dim=2, nx=n, ny=n, p=p, eq=EULER, gamma=1.4)
+        u = euler_quadrants(prob, np.random.default_rng([seed, s]))
+        out.append(Workload("euler_2d_batch", prob, u, cfl=0.5, steps=50,
+                            seed=seed, meta={"index": s}))
+    return out
+
+
+def small_cases():
+    """A handful of small problems spanning the equations, dimensions and
+    a ragged element count, for parity checks."""
+    return [
+        advection_1d(),
+        burgers_2d(n=16, p=3),
+        euler_2d(n=16, p=4),
+    ]
