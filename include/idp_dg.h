@@ -1,0 +1,151 @@
+/*
+ * idp_dg.h -- C ABI of the MI355X (gfx950) library for one explicit,
+ * limited SSP Runge-Kutta stage of the sparse invariant-domain-preserving
+ * (IDP) nodal discontinuous Galerkin method with subcell convex limiting of
+ * Pazner, "Sparse invariant domain preserving discontinuous Galerkin
+ * methods with subcell convex limiting" (arXiv 2004.08503).
+ *
+ * One stage computes, for every node i of a periodic Cartesian mesh of
+ * tensor-product Gauss-Lobatto elements:
+ *   - the high-order target residual r^H: the strong-form DG spectral
+ *     element operator with the local Lax-Friedrichs flux (Sec. 2,
+ *     eq. dg-strong, eq. ho-update);
+ *   - the sparse low-order residual r^L with graph viscosity (Sec. 3,
+ *     eq. dg-idp, eq. lo-update) and the low-order state u^L;
+ *   - the antidiffusive subcell fluxes rbar on the interior subcell faces of
+ *     each line of nodes (Sec. 4.1.3);
+ *   - the local bounds from the bar states (eq. bar-states) and the nodal
+ *     limiting coefficients: Zalesak for scalar laws and for the Euler
+ *     density, then the entropy line search of eq. convex-provisional;
+ *   - the flux-corrected update (eq. convex-fct) combined into the SSP-RK3
+ *     stage.
+ *
+ * Conventions shared by every call:
+ *   - Arithmetic is IEEE binary64 throughout.
+ *   - A state is a device array of nc * Nn doubles in structure-of-arrays
+ *     layout u[c][e][b][a]: component c outermost, element e = ey*nx + ex,
+ *     node index b in y, node index a in x fastest.  nc = 1 (advection,
+ *     Burgers) or d+2 (Euler: rho, rho v, rho E).  Nn = nx*ny*(p+1)^d.
+ *   - Device pointers are caller-owned; the library never frees them.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation
+ *     (borrowed, not owned); only idp_dg_max_dt, idp_dg_last_dt and
+ *     idp_dg_diagnostics synchronise that stream.
+ *   - Return codes: 0 success; IDP_DG_EINVAL (-1) bad argument, state left
+ *     untouched; IDP_DG_ENOMEM (-2) allocation failure; IDP_DG_EHIP (-3) a
+ *     HIP runtime error.  No call aborts or throws; idp_dg_last_error gives
+ *     a message for the last failure on a handle.
+ *   - A handle is used from one host thread at a time.
+ */
+#ifndef IDP_DG_H
+#define IDP_DG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IDP_DG_EINVAL (-1)
+#define IDP_DG_ENOMEM (-2)
+#define IDP_DG_EHIP (-3)
+
+/* equations (Sec. 2, Sec. 4.3 for Euler, Sec. 5 for the scalar tests) */
+enum {
+  IDP_DG_ADVECTION = 0, /* u_t + div(v u) = 0, constant v = velocity */
+  IDP_DG_BURGERS = 1,   /* u_t + div(u^2/2 v) = 0, constant direction v */
+  IDP_DG_EULER = 2      /* compressible Euler, ideal gas with gamma */
+};
+
+/* limiter modes */
+enum {
+  IDP_DG_SUBCELL = 0,     /* subcell convex limiting (Sec. 4.1.3, 4.2.2) */
+  IDP_DG_TARGET_ONLY = 1, /* alpha = 1: the unlimited high-order update */
+  IDP_DG_LOW_ONLY = 2     /* alpha = 0: the low-order IDP update */
+};
+
+/* Problem description.  Periodic box [0,lx) x [0,ly) of nx x ny elements
+ * (ny = 1 and ly ignored when dim = 1); p in [1, 8]; velocity is the
+ * advection velocity or the Burgers direction vector; gamma in (1, 5/3]
+ * for Euler (the range where the wave-speed bound used is proven). */
+typedef struct {
+  int dim;
+  int nx, ny;
+  double lx, ly;
+  int p;
+  int eq;
+  double velocity[2];
+  double gamma;
+  int limiter;
+} idp_dg_desc;
+
+typedef struct idp_dg idp_dg;
+
+/* Diagnostics accumulated since the last idp_dg_diagnostics call. */
+typedef struct {
+  long long limited_nodes;  /* nodes whose final coefficient was < 1 */
+  long long entropy_nodes;  /* Euler nodes where the entropy search bound */
+  int bad_input;            /* a stage input had rho <= 0 or p <= 0 */
+  int low_order_violation;  /* u^L left its bounds: dt above the CFL bound */
+} idp_dg_diag;
+
+/* Create a handle for one problem.  Builds the Gauss-Lobatto tables, picks
+ * the launch configuration and allocates two state-sized device buffers
+ * for idp_dg_step.  hip_stream is a hipStream_t (0 for the null stream).
+ * *out receives the handle, or NULL on failure. */
+int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out);
+
+/* Release the handle and its buffers.  NULL-safe. */
+void idp_dg_destroy(idp_dg* h);
+
+/* Number of nodes Nn and of components nc of the handle's problem. */
+long idp_dg_num_nodes(const idp_dg* h);
+int idp_dg_num_comp(const idp_dg* h);
+
+/* One SSP-RK3 stage in Shu-Osher form (Sec. 5: third-order SSP RK):
+ *   u_out = a_s * u_n + b_s * FE(u_s, dt),
+ *   (a_s, b_s) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 0, 1, 2,
+ * FE the limited forward-Euler sub-step.  u_n is not read for stage 0 and
+ * may then be NULL.  u_out may equal u_n but must not overlap u_s
+ * (neighbouring elements read u_s).  dt >= 0; dt above idp_dg_max_dt
+ * loses the IDP guarantee and is reported by the diagnostics. */
+int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s,
+                 double* u_out, double dt, int stage);
+
+/* idp_dg_stage that also writes the limiter's per-node intermediates to
+ * the device array trace (5 * Nn doubles, caller-owned, not overlapping a
+ * state): trace[0..Nn) the lower bound and [Nn..2Nn) the upper bound of
+ * the limited component (u, or rho for Euler; eq. bar-states), [2Nn..3Nn)
+ * the Euler entropy bound K_min = min p rho^-gamma over the stencil (0 for
+ * scalar laws), [3Nn..4Nn) the Zalesak coefficient and [4Nn..5Nn) the
+ * final nodal coefficient (eq. convex-provisional).  For inspection and
+ * testing of the limiter; the state update is the same as idp_dg_stage. */
+int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s,
+                       double* u_out, double dt, int stage, double* trace);
+
+/* One SSP-RK3 step in place: three stages through the handle's buffers. */
+int idp_dg_step(idp_dg* h, double* u, double dt);
+
+/* One SSP-RK3 step in place with dt = cfl * idp_dg_max_dt(u) computed on
+ * the device from u at the start of the step (eq. cfl-low; the paper runs
+ * cfl = 1/2).  Nothing is copied to the host: the four kernels replay from
+ * a HIP graph cached for (u, cfl).  The dt used is kept on the device and
+ * can be read with idp_dg_last_dt. */
+int idp_dg_step_cfl(idp_dg* h, double* u, double cfl);
+
+/* dt of the last idp_dg_step_cfl (synchronises the stream). */
+int idp_dg_last_dt(idp_dg* h, double* dt);
+
+/* Largest dt allowed by the low-order CFL condition (eq. cfl-low):
+ * min over nodes of m_i / (2 sum_{j != i} dhat_ij), written to *dt (host).
+ * +inf when no node has dissipation.  Synchronises the stream. */
+int idp_dg_max_dt(idp_dg* h, const double* u, double* dt);
+
+/* Copy out and reset the diagnostics (synchronises the stream). */
+int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out);
+
+/* Message of the last failure on h (or of the last failed create when h is
+ * NULL).  Never NULL. */
+const char* idp_dg_last_error(const idp_dg* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,87 @@
+// Shared declarations of the gfx950 stage kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace idp {
+
+enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2 };
+enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2 };
+constexpr int MAXP = 8;
+
+// Per-degree constants, passed by value in the kernel arguments.
+struct Tables {
+  double w[MAXP + 1];             // Gauss-Lobatto weights on [0,1]
+  double Q[MAXP * (MAXP + 1)];    // Q[a][e] = sum_{c<=a} D[c][e], a < p; rows of p+1
+};
+
+// Physics constants of one problem.
+struct Phys {
+  double vel0, vel1;   // advection velocity / Burgers direction
+  double gamma;        // Euler
+  double ex;           // (gamma-1)/(2 gamma)
+  double inv_ex;       // 2 gamma/(gamma-1)
+  int inv_ex_int;      // inv_ex when it is an integer (7 for gamma = 1.4), else 0
+};
+
+// Diagnostics words in device memory.
+struct Diag {
+  unsigned long long limited;   // nodes with final alpha < 1
+  unsigned long long entropy;   // nodes where the entropy search bound alpha
+  unsigned int bad_input;       // rho <= 0 or p <= 0 seen in a stage input
+  unsigned int lo_violation;    // u^L outside its bounds (dt above CFL)
+};
+
+// Geometry of one solve and where its arrays are.
+struct Solve {
+  const double* u_n;    // read when use_un
+  const double* u_s;    // stage input
+  double* u_out;        // stage output
+  const double* dt_dev; // when non-null: dt = dt_scale * dt_dev[0]
+  double dt, dt_scale;
+  long long nn;         // nodes
+  int nx, ny, ne;       // elements
+  int ntiles;           // element tiles of this solve
+  double hx, hy;
+};
+
+struct StageArgs {
+  Solve S;
+  Phys ph;
+  Tables T;
+  double a_s, b_s;
+  int use_un;
+  int limiter;
+  Diag* diag;
+  double* trace;   // optional per-node [umin, umax, kmin, alpha_z, alpha] x Nn
+};
+
+struct MaxDtArgs {
+  const double* u;
+  unsigned long long* out;   // bit pattern of the (non-negative) minimum
+  long long nn;
+  int nx, ny, ne, ntiles;
+  double hx, hy;
+  Phys ph;
+  Tables T;
+};
+
+// Kernel launchers, one translation unit per (equation, dimension).
+// Return hipSuccess or the launch error; variant selects elements-per-block.
+#define IDP_DECLARE_LAUNCHERS(NAME)                                               \
+  hipError_t launch_stage_##NAME(int p, int variant, const StageArgs& a,          \
+                                 hipStream_t s);                                  \
+  hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s);       \
+  int tile_elems_##NAME(int p, int variant);                                      \
+  int num_variants_##NAME(int p);
+
+IDP_DECLARE_LAUNCHERS(adv1)
+IDP_DECLARE_LAUNCHERS(adv2)
+IDP_DECLARE_LAUNCHERS(burg1)
+IDP_DECLARE_LAUNCHERS(burg2)
+IDP_DECLARE_LAUNCHERS(euler1)
+IDP_DECLARE_LAUNCHERS(euler2)
+
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v);
+__global__ void u64_to_dt_kernel(const unsigned long long* bits, double* dt);
+
+}  // namespace idp

@@ -1,0 +1,457 @@
+// Host runtime of the C ABI declared in include/idp_dg.h: argument checks,
+// Gauss-Lobatto tables, launch configuration, device buffers, the cached
+// HIP graph of a device-timestepped SSP-RK3 step, diagnostics and the
+// batched driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/idp_dg.h"
+#include "common.hpp"
+
+using namespace idp;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+// ---------------------------------------------------------------------
+// tables: Gauss-Lobatto points as the roots of P_{p+1} - P_{p-1}, which
+// vanishes at +-1 and at the roots of P_p' (Newton from Chebyshev-Lobatto
+// guesses, derivative (2p+1) P_p); weights 2/(p(p+1) P_p^2) on [-1,1];
+// the derivative matrix from barycentric weights with its diagonal set by
+// the exact row sum (derivative of a constant).
+// ---------------------------------------------------------------------
+void legendre_pair(int n, double x, double* pn, double* pnm1) {
+  double a = 1.0, b = x;  // P_0, P_1
+  if (n == 0) { *pn = 1.0; *pnm1 = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    const double c = ((2 * k - 1) * x * b - (k - 1) * a) / k;
+    a = b;
+    b = c;
+  }
+  *pn = b;
+  *pnm1 = a;
+}
+
+void gl_tables(int p, double* xi01, double* w01, double* D) {
+  const int n = p + 1;
+  std::vector<double> x(n);
+  x[0] = -1.0;
+  x[p] = 1.0;
+  for (int k = 1; k < p; ++k) {
+    double t = -std::cos(M_PI * k / p);
+    for (int it = 0; it < 60; ++it) {
+      double pp1, pp, pm1, dummy;
+      legendre_pair(p + 1, t, &pp1, &pp);
+      legendre_pair(p - 1, t, &pm1, &dummy);
+      const double f = pp1 - pm1;
+      const double df = (2.0 * p + 1.0) * pp;
+      const double dx = f / df;
+      t -= dx;
+      if (std::fabs(dx) <= 1e-16) break;
+    }
+    x[k] = t;
+  }
+  std::vector<double> w(n), bw(n);
+  for (int k = 0; k < n; ++k) {
+    double pk, pkm1;
+    legendre_pair(p, x[k], &pk, &pkm1);
+    w[k] = 1.0 / (p * (p + 1.0) * pk * pk);  // on [0,1]
+    xi01[k] = 0.5 * (x[k] + 1.0);
+  }
+  xi01[0] = 0.0;
+  xi01[p] = 1.0;
+  for (int j = 0; j < n; ++j) {
+    double prod = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != j) prod *= xi01[j] - xi01[m];
+    bw[j] = 1.0 / prod;
+  }
+  for (int i = 0; i < n; ++i) {
+    double rs = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dij = bw[j] / bw[i] / (xi01[i] - xi01[j]);
+      D[i * n + j] = w[i] * dij;
+      rs += dij;
+    }
+    D[i * n + i] = -w[i] * rs;
+  }
+  for (int k = 0; k < n; ++k) w01[k] = w[k];
+}
+
+}  // namespace
+
+struct idp_dg {
+  idp_dg_desc d{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nc = 1;
+  long long nn = 0;
+  int ne = 0;
+  int variant = 0;
+  Tables T{};
+  Phys ph{};
+  double* buf1 = nullptr;   // stage buffers of idp_dg_step
+  double* buf2 = nullptr;
+  Diag* diag = nullptr;
+  unsigned long long* dtbits = nullptr;  // device dt of the last step_cfl
+  // cached graph of one device-timestepped step
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* g_u = nullptr;
+  double g_cfl = 0.0;
+  std::string err = "no error";
+};
+
+namespace {
+
+int fail(idp_dg* h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(idp_dg* h, hipError_t e, const char* where) {
+  return fail(h, IDP_DG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool desc_ok(const idp_dg_desc* d, std::string* why) {
+  if (!d) { *why = "desc is NULL"; return false; }
+  if (d->dim != 1 && d->dim != 2) { *why = "dim must be 1 or 2"; return false; }
+  if (d->nx < 1 || d->ny < 1) { *why = "nx, ny must be >= 1"; return false; }
+  if (d->dim == 1 && d->ny != 1) { *why = "ny must be 1 when dim = 1"; return false; }
+  if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) { *why = "lx, ly must be > 0"; return false; }
+  if (d->p < 1 || d->p > MAXP) { *why = "p must be in [1, 8]"; return false; }
+  if (d->eq < IDP_DG_ADVECTION || d->eq > IDP_DG_EULER) { *why = "unknown equation"; return false; }
+  if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_LOW_ONLY) { *why = "unknown limiter"; return false; }
+  if (d->eq == IDP_DG_EULER && !(d->gamma > 1.0 && d->gamma <= 5.0 / 3.0)) {
+    *why = "gamma must be in (1, 5/3]";
+    return false;
+  }
+  const long long n1 = d->p + 1;
+  const long long nn = (long long)d->nx * d->ny * (d->dim == 2 ? n1 * n1 : n1);
+  if ((long long)d->nx * d->ny > 0x7fffffffLL || nn > (1LL << 40)) { *why = "mesh too large"; return false; }
+  return true;
+}
+
+hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
+  const int p = h->d.p;
+  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+    case 0: return launch_stage_adv1(p, h->variant, a, s);
+    case 1: return launch_stage_adv2(p, h->variant, a, s);
+    case 2: return launch_stage_burg1(p, h->variant, a, s);
+    case 3: return launch_stage_burg2(p, h->variant, a, s);
+    case 4: return launch_stage_euler1(p, h->variant, a, s);
+    case 5: return launch_stage_euler2(p, h->variant, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
+  const int p = h->d.p;
+  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+    case 0: return launch_maxdt_adv1(p, a, s);
+    case 1: return launch_maxdt_adv2(p, a, s);
+    case 2: return launch_maxdt_burg1(p, a, s);
+    case 3: return launch_maxdt_burg2(p, a, s);
+    case 4: return launch_maxdt_euler1(p, a, s);
+    case 5: return launch_maxdt_euler2(p, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int tile_elems(const idp_dg* h) {
+  const int p = h->d.p;
+  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+    case 0: return tile_elems_adv1(p, h->variant);
+    case 1: return tile_elems_adv2(p, h->variant);
+    case 2: return tile_elems_burg1(p, h->variant);
+    case 3: return tile_elems_burg2(p, h->variant);
+    case 4: return tile_elems_euler1(p, h->variant);
+    case 5: return tile_elems_euler2(p, h->variant);
+  }
+  return 1;
+}
+
+StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s, double* u_out,
+                          double dt, const double* dt_dev, double dt_scale, int stage) {
+  static const double As[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double Bs[3] = {1.0, 0.25, 2.0 / 3.0};
+  StageArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.S.u_n = u_n;
+  a.S.u_s = u_s;
+  a.S.u_out = u_out;
+  a.S.dt_dev = dt_dev;
+  a.S.dt = dt;
+  a.S.dt_scale = dt_scale;
+  a.S.nn = h->nn;
+  a.S.nx = h->d.nx;
+  a.S.ny = h->d.ny;
+  a.S.ne = h->ne;
+  a.S.ntiles = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  a.S.hx = h->d.lx / h->d.nx;
+  a.S.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
+  a.ph = h->ph;
+  a.T = h->T;
+  a.a_s = As[stage];
+  a.b_s = Bs[stage];
+  a.use_un = stage > 0;
+  a.limiter = h->d.limiter;
+  a.diag = h->diag;
+  return a;
+}
+
+MaxDtArgs make_dt_args(const idp_dg* h, const double* u, unsigned long long* out) {
+  MaxDtArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.u = u;
+  a.out = out;
+  a.nn = h->nn;
+  a.nx = h->d.nx;
+  a.ny = h->d.ny;
+  a.ne = h->ne;
+  a.ntiles = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  a.hx = h->d.lx / h->d.nx;
+  a.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
+  a.ph = h->ph;
+  a.T = h->T;
+  return a;
+}
+
+bool overlaps(const double* a, const double* b, long long n) {
+  return a < b + n && b < a + n;
+}
+
+void drop_graph(idp_dg* h) {
+  if (h->exec) hipGraphExecDestroy(h->exec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  h->exec = nullptr;
+  h->graph = nullptr;
+  h->g_u = nullptr;
+}
+
+// enqueue one device-timestepped step on stream s
+hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, s, h->dtbits, 0x7ff0000000000000ULL);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_maxdt(h, make_dt_args(h, u, h->dtbits), s);
+  if (e != hipSuccess) return e;
+  const double* dtp = reinterpret_cast<const double*>(h->dtbits);
+  e = launch_stage(h, make_stage_args(h, nullptr, u, h->buf1, 0.0, dtp, cfl, 0), s);
+  if (e != hipSuccess) return e;
+  e = launch_stage(h, make_stage_args(h, u, h->buf1, h->buf2, 0.0, dtp, cfl, 1), s);
+  if (e != hipSuccess) return e;
+  return launch_stage(h, make_stage_args(h, u, h->buf2, u, 0.0, dtp, cfl, 2), s);
+}
+
+}  // namespace
+
+namespace idp {
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+__global__ void u64_to_dt_kernel(const unsigned long long* bits, double* dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dt[0] = __longlong_as_double((long long)bits[0]);
+}
+}  // namespace idp
+
+extern "C" {
+
+int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
+  if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!desc_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  idp_dg* h = new (std::nothrow) idp_dg;
+  if (!h) return fail(nullptr, IDP_DG_ENOMEM, "host allocation failed");
+  h->d = *desc;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->nc = desc->eq == IDP_DG_EULER ? desc->dim + 2 : 1;
+  const long long n1 = desc->p + 1;
+  h->ne = desc->nx * desc->ny;
+  h->nn = (long long)h->ne * (desc->dim == 2 ? n1 * n1 : n1);
+  double xi[MAXP + 1], D[(MAXP + 1) * (MAXP + 1)];
+  gl_tables(desc->p, xi, h->T.w, D);
+  for (int a = 0; a < desc->p; ++a) {
+    for (int e = 0; e <= desc->p; ++e) {
+      double acc = 0.0;
+      for (int c = 0; c <= a; ++c) acc += D[c * (desc->p + 1) + e];
+      h->T.Q[a * (desc->p + 1) + e] = acc;
+    }
+  }
+  h->ph.vel0 = desc->velocity[0];
+  h->ph.vel1 = desc->dim == 2 ? desc->velocity[1] : 0.0;
+  h->ph.gamma = desc->eq == IDP_DG_EULER ? desc->gamma : 1.4;
+  h->ph.ex = (h->ph.gamma - 1.0) / (2.0 * h->ph.gamma);
+  h->ph.inv_ex = 1.0 / h->ph.ex;
+  const double r = std::nearbyint(h->ph.inv_ex);
+  h->ph.inv_ex_int = (std::fabs(h->ph.inv_ex - r) < 1e-12 && r > 0 && r < 64) ? (int)r : 0;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
+  const size_t bytes = sizeof(double) * h->nc * h->nn;
+  e = hipMalloc(&h->buf1, bytes);
+  if (e == hipSuccess) e = hipMalloc(&h->buf2, bytes);
+  if (e == hipSuccess) e = hipMalloc(&h->diag, sizeof(Diag) + 64);
+  if (e == hipSuccess) e = hipMalloc(&h->dtbits, 64);
+  if (e == hipSuccess) e = hipMemset(h->diag, 0, sizeof(Diag));
+  if (e != hipSuccess) {
+    const int code = e == hipErrorOutOfMemory ? IDP_DG_ENOMEM : IDP_DG_EHIP;
+    fail(nullptr, code, std::string("device allocation: ") + hipGetErrorString(e));
+    hipFree(h->buf1); hipFree(h->buf2); hipFree(h->diag); hipFree(h->dtbits);
+    delete h;
+    return code;
+  }
+  *out = h;
+  return 0;
+}
+
+void idp_dg_destroy(idp_dg* h) {
+  if (!h) return;
+  drop_graph(h);
+  if (h->cap) hipStreamDestroy(h->cap);
+  hipFree(h->buf1);
+  hipFree(h->buf2);
+  hipFree(h->diag);
+  hipFree(h->dtbits);
+  delete h;
+}
+
+long idp_dg_num_nodes(const idp_dg* h) { return h ? (long)h->nn : -1; }
+int idp_dg_num_comp(const idp_dg* h) { return h ? h->nc : -1; }
+
+int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s, double* u_out, double dt,
+                 int stage) {
+  if (!h) return IDP_DG_EINVAL;
+  if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
+  if (!u_s || !u_out || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(h, IDP_DG_EINVAL, "dt must be finite and >= 0");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u_out, u_s, n)) return fail(h, IDP_DG_EINVAL, "u_out overlaps u_s");
+  if (stage > 0 && u_n != u_out && overlaps(u_out, u_n, n))
+    return fail(h, IDP_DG_EINVAL, "u_out partially overlaps u_n");
+  hipError_t e = launch_stage(h, make_stage_args(h, u_n, u_s, u_out, dt, nullptr, 1.0, stage), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+  return 0;
+}
+
+int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
+                       double dt, int stage, double* trace) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!trace) return fail(h, IDP_DG_EINVAL, "NULL trace pointer");
+  if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
+  if (!u_s || !u_out || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(h, IDP_DG_EINVAL, "dt must be finite and >= 0");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u_out, u_s, n)) return fail(h, IDP_DG_EINVAL, "u_out overlaps u_s");
+  if (overlaps(trace, u_out, n) || overlaps(trace, u_s, n) || (u_n && overlaps(trace, u_n, n)))
+    return fail(h, IDP_DG_EINVAL, "trace overlaps a state");
+  StageArgs a = make_stage_args(h, u_n, u_s, u_out, dt, nullptr, 1.0, stage);
+  a.trace = trace;
+  hipError_t e = launch_stage(h, a, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+  return 0;
+}
+
+int idp_dg_step(idp_dg* h, double* u, double dt) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u, h->buf1, n) || overlaps(u, h->buf2, n))
+    return fail(h, IDP_DG_EINVAL, "u overlaps the handle's buffers");
+  int rc = idp_dg_stage(h, nullptr, u, h->buf1, dt, 0);
+  if (!rc) rc = idp_dg_stage(h, u, h->buf1, h->buf2, dt, 1);
+  if (!rc) rc = idp_dg_stage(h, u, h->buf2, u, dt, 2);
+  return rc;
+}
+
+int idp_dg_step_cfl(idp_dg* h, double* u, double cfl) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, IDP_DG_EINVAL, "cfl must be finite and > 0");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u, h->buf1, n) || overlaps(u, h->buf2, n))
+    return fail(h, IDP_DG_EINVAL, "u overlaps the handle's buffers");
+  hipError_t e;
+  if (!h->exec || h->g_u != u || h->g_cfl != cfl) {
+    drop_graph(h);
+    if (!h->cap) {
+      e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(h, e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+    hipError_t le = enqueue_step_cfl(h, u, cfl, h->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap, &g);
+    if (le != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(h, le, "step capture"); }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    h->graph = g;
+    e = hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_graph(h); return hip_fail(h, e, "hipGraphInstantiate"); }
+    h->g_u = u;
+    h->g_cfl = cfl;
+  }
+  e = hipGraphLaunch(h->exec, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+  return 0;
+}
+
+int idp_dg_last_dt(idp_dg* h, double* dt) {
+  if (!h || !dt) return IDP_DG_EINVAL;
+  unsigned long long bits = 0;
+  hipError_t e = hipMemcpyAsync(&bits, h->dtbits, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "last dt copy");
+  double v;
+  std::memcpy(&v, &bits, sizeof(v));
+  if (!(v < INFINITY)) v = INFINITY;
+  *dt = h->g_cfl * v;  // the same product the stage kernels form
+  if (!(*dt < INFINITY)) *dt = 0.0;  // no dissipation anywhere: the step kept the state
+  return 0;
+}
+
+int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!u || !dt) return fail(h, IDP_DG_EINVAL, "NULL pointer");
+  unsigned long long* bits = h->dtbits + 1;   // keep the step's dt slot intact
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, h->stream, bits, 0x7ff0000000000000ULL);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_maxdt(h, make_dt_args(h, u, bits), h->stream);
+  unsigned long long host = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&host, bits, sizeof(host), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "max_dt");
+  double v;
+  std::memcpy(&v, &host, sizeof(v));
+  *dt = v;
+  return 0;
+}
+
+int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out) {
+  if (!h || !out) return IDP_DG_EINVAL;
+  Diag d;
+  hipError_t e = hipMemcpyAsync(&d, h->diag, sizeof(d), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->diag, 0, sizeof(Diag), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics");
+  out->limited_nodes = (long long)d.limited;
+  out->entropy_nodes = (long long)d.entropy;
+  out->bad_input = d.bad_input ? 1 : 0;
+  out->low_order_violation = d.lo_violation ? 1 : 0;
+  return 0;
+}
+
+const char* idp_dg_last_error(const idp_dg* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

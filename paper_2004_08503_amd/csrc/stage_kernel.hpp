@@ -1,0 +1,731 @@
+// Fused limited SSP-RK stage for gfx950: one workgroup owns a tile of EPB
+// consecutive elements, one thread per node, and runs every step of the
+// stage out of LDS.  Global memory is touched once per node for the stage
+// input (plus the face traces of the 2d neighbouring elements), once for
+// u^n on the second and third stages, and once for the output.
+//
+// Phases (LDS barriers between them):
+//   1. load the tile's states and the neighbours' face traces;
+//   2. pointwise physics: fluxes F^x, F^y and, for Euler, 1/rho, p, c,
+//      p^{-(gamma-1)/(2 gamma)} and K = p rho^{-gamma};
+//   3. one work item per subcell face of every line (element faces
+//      included): wave-speed bound, low-order flux f^L (eq. lax-friedrichs
+//      on the subgrid), bar state of the limited component (eq.
+//      bar-states), the entropy bound over the pair, and on interior
+//      subcell faces the high-order subcell flux f^H and the antidiffusive
+//      flux rbar = s (f^L - f^H);
+//   4. per node: u^L, local bounds, Zalesak coefficient and, for Euler,
+//      the entropy line search of eq. convex-provisional;
+//   5. per node: subcell-face coefficients min(alpha_i, alpha_j), the
+//      flux-corrected update (eq. convex-fct) and the RK combination.
+//
+// The high-order subcell flux uses the cumulative derivative matrix
+// Q[a][e] = sum_{c<=a} D[c][e]: on an interior subcell face a+1/2 of a
+// line, f^H_{a+1/2} = F_0 + sum_e Q[a][e] F_e is the flux whose
+// differences reproduce the strong-form residual (eq. dg-strong), so the
+// prefix sums of r^H - r^L of Sec. 4.1.3 become one short contraction per
+// face and rbar = s (f^L - f^H) is the difference of the two fluxes.
+#pragma once
+#include "common.hpp"
+
+namespace idp {
+
+template <int EQ, int DIM, int P, int EPB>
+struct Cfg {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = DIM == 2 ? N1 * N1 : N1;   // own nodes per element
+  static constexpr int TJ = DIM == 2 ? N1 : 1;          // nodes per face trace
+  static constexpr int NT = 2 * DIM * TJ;               // trace nodes per element
+  static constexpr int NS = NP + NT;                    // LDS slots per element
+  static constexpr int NC = EQ == EQ_EULER ? DIM + 2 : 1;
+  static constexpr int NAUX = EQ == EQ_EULER ? 5 : 0;   // 1/rho, p, c, p^-ex, K
+  static constexpr int NFL = P + 2;                     // subcell faces per line
+  static constexpr int NL = DIM == 2 ? N1 : 1;          // lines per direction
+  static constexpr int NF = NFL * NL;                   // faces per direction
+  static constexpr int BS = ((EPB * NP + 63) / 64) * 64;
+  static constexpr int NITEM = (EPB * DIM * NF + BS - 1) / BS;
+  // region A: phase 1-2 results, read in phase 3
+  static constexpr int A_U = 0;
+  static constexpr int A_F = A_U + NC * EPB * NS;
+  static constexpr int A_X = A_F + DIM * NC * EPB * NS;
+  static constexpr int A_END = A_X + NAUX * EPB * NS;
+  // region B (aliases A): phase 3 results, read in phases 4-5
+  static constexpr int B_FL = 0;
+  static constexpr int B_RB = B_FL + DIM * NC * EPB * NF;
+  static constexpr int B_UB = B_RB + DIM * NC * EPB * NF;
+  static constexpr int B_KF = B_UB + DIM * EPB * NF;
+  static constexpr int B_END = B_KF + (EQ == EQ_EULER ? DIM * EPB * NF : 0);
+  static constexpr int AB = A_END > B_END ? A_END : B_END;
+  static constexpr int S_AL = AB;                       // nodal alpha
+  static constexpr int S_W = S_AL + EPB * NP;           // weights
+  static constexpr int S_Q = S_W + N1;                  // cumulative D
+  static constexpr int LDS = S_Q + P * N1;
+  static_assert(LDS * 8 <= 160 * 1024, "tile does not fit in LDS");
+};
+
+// Workgroups are dealt round-robin to the eight XCDs; give every XCD a
+// contiguous range of tiles so that the face traces a tile reads from the
+// element rows above and below were fetched into the same XCD's L2.
+__device__ inline int xcd_tile(int b, int nb) {
+  const int x = b & 7, i = b >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+// Global node index of trace t of element e: face 0/1 = the x-neighbours'
+// facing node columns, 2/3 = the y-neighbours' facing rows (periodic).
+template <int DIM, int P>
+__device__ inline long long trace_node(int e, int t, int nx, int ny) {
+  constexpr int N1 = P + 1;
+  const int ex = e % nx, ey = e / nx;
+  if constexpr (DIM == 1) {
+    const int exn = t == 0 ? (ex == 0 ? nx - 1 : ex - 1) : (ex == nx - 1 ? 0 : ex + 1);
+    return (long long)exn * N1 + (t == 0 ? P : 0);
+  } else {
+    constexpr int NP = N1 * N1;
+    const int face = t / N1, j = t - face * N1;
+    int exn = ex, eyn = ey, loc;
+    if (face == 0) { exn = ex == 0 ? nx - 1 : ex - 1; loc = j * N1 + P; }
+    else if (face == 1) { exn = ex == nx - 1 ? 0 : ex + 1; loc = j * N1; }
+    else if (face == 2) { eyn = ey == 0 ? ny - 1 : ey - 1; loc = P * N1 + j; }
+    else { eyn = ey == ny - 1 ? 0 : ey + 1; loc = j; }
+    return ((long long)eyn * nx + exn) * NP + loc;
+  }
+}
+
+__device__ inline double ipow(double x, int n) {
+  double r = 1.0;
+  while (n) {
+    if (n & 1) r *= x;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
+// Euler auxiliaries of one state: 1/rho, p, c, p^-ex, K = p rho^-gamma.
+template <int DIM>
+__device__ inline void euler_aux(const double* U, const Phys& ph, double* X, bool& bad) {
+  const double rinv = 1.0 / U[0];
+  double mm = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) mm += U[1 + k] * U[1 + k];
+  const double p = (ph.gamma - 1.0) * (U[DIM + 1] - 0.5 * mm * rinv);
+  bad = !(U[0] > 0.0) || !(p > 0.0);
+  X[0] = rinv;
+  X[1] = p;
+  X[2] = sqrt(ph.gamma * p * rinv);
+  X[3] = pow(p, -ph.ex);
+  X[4] = p * pow(U[0], -ph.gamma);
+}
+
+// flux in direction k of one state (X: Euler auxiliaries)
+template <int EQ, int DIM>
+__device__ inline void flux_k(int k, const double* U, const double* X, const Phys& ph, double* F) {
+  if constexpr (EQ == EQ_ADV) {
+    F[0] = (k == 0 ? ph.vel0 : ph.vel1) * U[0];
+  } else if constexpr (EQ == EQ_BURG) {
+    F[0] = 0.5 * U[0] * U[0] * (k == 0 ? ph.vel0 : ph.vel1);
+  } else {
+    const double vk = U[1 + k] * X[0];
+    const double p = X[1];
+    F[0] = U[1 + k];
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) F[1 + l] = U[1 + l] * vk + (l == k ? p : 0.0);
+    F[DIM + 1] = vk * (U[DIM + 1] + p);
+  }
+}
+
+// Upper bound of the maximum wave speed of the Riemann problem (UL | UR)
+// along +e_k.  Euler: the two-rarefaction pressure bound (Guermond and
+// Popov, J. Comput. Phys. 2016), valid for 1 < gamma <= 5/3.
+template <int EQ, int DIM>
+__device__ inline double lambda_k(int k, const double* UL, const double* XL, const double* UR,
+                                  const double* XR, const Phys& ph) {
+  if constexpr (EQ == EQ_ADV) {
+    return fabs(k == 0 ? ph.vel0 : ph.vel1);
+  } else if constexpr (EQ == EQ_BURG) {
+    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(k == 0 ? ph.vel0 : ph.vel1);
+  } else {
+    const double g = ph.gamma;
+    const double vl = UL[1 + k] * XL[0], vr = UR[1 + k] * XR[0];
+    const double pl = XL[1], pr = XR[1], cl = XL[2], cr = XR[2];
+    double num = cl + cr - 0.5 * (g - 1.0) * (vr - vl);
+    num = num < 0.0 ? 0.0 : num;
+    const double den = cl * XL[3] + cr * XR[3];
+    const double base = num / den;
+    const double pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
+    const double fac = (g + 1.0) / (2.0 * g);
+    const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) / pl);
+    const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) / pr);
+    return fmax(fmax(-lam_l, 0.0), fmax(lam_r, 0.0));
+  }
+}
+
+// Phi(V) = rho e - K_min rho^gamma / (gamma - 1) along V = uL + t P, with
+// its t-derivative.  Phi >= 0 with rho > 0 is the specific-entropy minimum
+// principle of Sec. 4.3; Phi is concave.
+struct PhiVal {
+  double rho, phi, dphi;
+};
+
+template <int DIM>
+__device__ inline PhiVal phi_at(double t, const double* uL, const double* P, double kmin,
+                                const Phys& ph) {
+  PhiVal r;
+  r.rho = fma(t, P[0], uL[0]);
+  if (!(r.rho > 0.0)) {
+    r.phi = -INFINITY;
+    r.dphi = 0.0;
+    return r;
+  }
+  const double g = ph.gamma;
+  const double rinv = 1.0 / r.rho;
+  double mm = 0.0, mp = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const double m = fma(t, P[1 + k], uL[1 + k]);
+    mm += m * m;
+    mp += m * P[1 + k];
+  }
+  const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
+  const double rg = pow(r.rho, g);
+  const double kg = kmin / (g - 1.0);
+  r.phi = E - 0.5 * mm * rinv - kg * rg;
+  r.dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
+  return r;
+}
+
+// sup { t in [0,T] : uL + t P admissible }.  Newton from the infeasible
+// side: the tangent of a concave function overshoots its root from above,
+// so the iterates decrease monotonically onto the root (bisection steps
+// while the density is not positive).  Near the root Phi is only known to
+// rounding, so once the steps stall the search steps back geometrically
+// from the last infeasible point to the nearest feasible one.  The result
+// is feasible and within a few rounding widths of the supremum.
+template <int DIM>
+__device__ double entropy_search(const double* uL, const double* P, double T, double kmin,
+                                 const Phys& ph) {
+  PhiVal er = phi_at<DIM>(T, uL, P, kmin, ph);
+  if (er.rho > 0.0 && er.phi >= 0.0) return T;
+  const PhiVal e0 = phi_at<DIM>(0.0, uL, P, kmin, ph);
+  if (!(e0.rho > 0.0 && e0.phi >= 0.0)) return 0.0;
+  double tl = 0.0, tr = T;
+  bool done = false;
+  for (int it = 0; it < 64; ++it) {
+    if (tr - tl <= 1e-15) {
+      done = true;
+      break;
+    }
+    if (er.rho > 0.0 && er.dphi < 0.0 && er.phi > -INFINITY) {
+      const double tn = tr - er.phi / er.dphi;
+      if (!(tn < tr)) break;  // step below rounding: tr sits on the root
+      if (!(tn > tl)) {       // the root is within rounding of tl
+        done = true;
+        break;
+      }
+      const PhiVal en = phi_at<DIM>(tn, uL, P, kmin, ph);
+      if (en.rho > 0.0 && en.phi >= 0.0) {
+        tl = tn;  // a tangent step lands feasible only within rounding of the root
+        done = true;
+        break;
+      }
+      const double step = tr - tn;
+      tr = tn;
+      er = en;
+      if (step <= 1e-14) break;
+    } else {  // no usable tangent (density not positive at tr): bisect
+      const double tn = 0.5 * (tl + tr);
+      const PhiVal en = phi_at<DIM>(tn, uL, P, kmin, ph);
+      if (en.rho > 0.0 && en.phi >= 0.0) {
+        tl = tn;
+      } else {
+        tr = tn;
+        er = en;
+      }
+    }
+  }
+  if (!done) {
+    double d = 4.5e-16 * tr;
+    for (int j = 0; j < 64; ++j) {
+      const double tb = tr - d;
+      if (!(tb > tl)) break;
+      const PhiVal eb = phi_at<DIM>(tb, uL, P, kmin, ph);
+      if (eb.rho > 0.0 && eb.phi >= 0.0) {
+        tl = tb;
+        break;
+      }
+      d *= 2.0;
+    }
+  }
+  return tl;
+}
+
+// local slot of the node at position pos of line l in direction k
+template <int DIM, int P>
+__device__ inline int own_slot(int k, int l, int pos) {
+  if constexpr (DIM == 1) return pos;
+  return k == 0 ? l * (P + 1) + pos : pos * (P + 1) + l;
+}
+
+// ----------------------------------------------------------------------
+// phases 1-2 shared by the stage and the time-step kernels
+// ----------------------------------------------------------------------
+template <int EQ, int DIM, int P, int EPB, bool FLUX>
+__device__ inline void load_tile(double* lds, const double* __restrict__ u, long long nn, int e0,
+                                 int ne, int nx, int ny, const Phys& ph, double* Uown,
+                                 unsigned int* bad_flag) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NT = C::NT;
+  const int tid = threadIdx.x;
+  const int nel = min(EPB, ne - e0);
+  bool bad = false;
+  // own nodes: one per thread, contiguous in global memory
+  if (tid < nel * NP) {
+    const int le = tid / NP, s = tid - le * NP;
+    const long long g = (long long)e0 * NP + tid;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Uown[c] = u[c * nn + g];
+      lds[C::A_U + c * EPB * NS + le * NS + s] = Uown[c];
+    }
+  }
+  // face traces of the neighbouring elements
+  for (int t = tid; t < nel * NT; t += C::BS) {
+    const int le = t / NT, j = t - le * NT;
+    const long long g = trace_node<DIM, P>(e0 + le, j, nx, ny);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = u[c * nn + g];
+  }
+  __syncthreads();
+  // pointwise physics on every slot
+  for (int t = tid; t < nel * NS; t += C::BS) {
+    const int le = t / NS, s = t - le * NS;
+    double U[NC], X[C::NAUX > 0 ? C::NAUX : 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c] = lds[C::A_U + c * EPB * NS + t];
+    if constexpr (EQ == EQ_EULER) {
+      bool b;
+      euler_aux<DIM>(U, ph, X, b);
+      bad |= b;
+#pragma unroll
+      for (int q = 0; q < C::NAUX; ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
+    }
+    if constexpr (FLUX) {
+      if (s < NP) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double F[NC];
+          flux_k<EQ, DIM>(k, U, X, ph, F);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NS + t] = F[c];
+        }
+      } else {
+        const int k = (s - NP) / (2 * C::TJ);   // normal direction of the trace
+        double F[NC];
+        flux_k<EQ, DIM>(k, U, X, ph, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NS + t] = F[c];
+      }
+    }
+  }
+  if (bad && bad_flag) atomicOr(bad_flag, 1u);
+}
+
+// copy the per-degree tables into LDS
+template <int P>
+__device__ inline void load_tables(double* sw, double* sq, const Tables& T, int nthreads) {
+  constexpr int N1 = P + 1;
+  for (int t = threadIdx.x; t < N1; t += nthreads) sw[t] = T.w[t];
+  for (int t = threadIdx.x; t < P * N1; t += nthreads) sq[t] = T.Q[t];
+}
+
+// ----------------------------------------------------------------------
+// the fused stage kernel
+// ----------------------------------------------------------------------
+template <int EQ, int DIM, int P, int EPB>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(StageArgs A) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
+  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  __shared__ double lds[C::LDS];
+  const int tid = threadIdx.x;
+  const Solve& S = A.S;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int e0 = tile * EPB;
+  if (e0 >= S.ne) return;  // whole workgroup
+  const int nel = min(EPB, S.ne - e0);
+  const long long nn = S.nn;
+
+  double dt = S.dt_dev ? S.dt_scale * S.dt_dev[0] : S.dt;
+  if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
+
+  load_tables<P>(lds + C::S_W, lds + C::S_Q, A.T, C::BS);
+  double U[NC], Un[NC];
+  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
+                                   A.diag ? &A.diag->bad_input : nullptr);
+  const bool own = tid < nel * NP;
+  if (A.use_un && own) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Un[c] = S.u_n[c * nn + (long long)e0 * NP + tid];
+  }
+  __syncthreads();
+
+  // ---- phase 3: subcell faces ----
+  double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM], rKF[C::NITEM];
+#pragma unroll
+  for (int it = 0; it < C::NITEM; ++it) {
+    const int w = tid + it * C::BS;
+    rUB[it] = 0.0;
+    rKF[it] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
+    if (w < nel * DIM * NF) {
+      const int le = w / (DIM * NF);
+      const int r = w - le * (DIM * NF);
+      const int k = DIM == 2 ? r / NF : 0;
+      const int fi = r - k * NF;
+      const int l = fi / NFL;
+      const int f = fi - l * NFL;
+      const int base = le * NS;
+      const int sl = base + (f == 0 ? NP + (2 * k) * C::TJ + l : own_slot<DIM, P>(k, l, f - 1));
+      const int sr = base + (f == P + 1 ? NP + (2 * k + 1) * C::TJ + l : own_slot<DIM, P>(k, l, f));
+      double UL[NC], UR[NC], FL[NC], FR[NC], XL[NX], XR[NX];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        UL[c] = lds[C::A_U + c * EPB * NS + sl];
+        UR[c] = lds[C::A_U + c * EPB * NS + sr];
+        FL[c] = lds[C::A_F + (k * NC + c) * EPB * NS + sl];
+        FR[c] = lds[C::A_F + (k * NC + c) * EPB * NS + sr];
+      }
+#pragma unroll
+      for (int q = 0; q < C::NAUX; ++q) {
+        XL[q] = lds[C::A_X + q * EPB * NS + sl];
+        XR[q] = lds[C::A_X + q * EPB * NS + sr];
+      }
+      const double lam = lambda_k<EQ, DIM>(k, UL, XL, UR, XR, A.ph);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) rFL[it][c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
+      const double avg = 0.5 * (UL[0] + UR[0]);
+      rUB[it] = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
+      if constexpr (EQ == EQ_EULER) rKF[it] = fmin(XL[4], XR[4]);
+      if (f >= 1 && f <= P) {
+        const double sc = DIM == 2 ? lds[C::S_W + l] * (k == 0 ? S.hy : S.hx) : 1.0;
+        const double* q = lds + C::S_Q + (f - 1) * N1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double* Fl = lds + C::A_F + (k * NC + c) * EPB * NS + base;
+          double fh = Fl[own_slot<DIM, P>(k, l, 0)];
+#pragma unroll
+          for (int e = 0; e <= P; ++e) fh += q[e] * Fl[own_slot<DIM, P>(k, l, e)];
+          rRB[it][c] = sc * (rFL[it][c] - fh);
+        }
+      }
+    }
+  }
+  __syncthreads();  // region A is dead from here on
+#pragma unroll
+  for (int it = 0; it < C::NITEM; ++it) {
+    const int w = tid + it * C::BS;
+    if (w < nel * DIM * NF) {
+      const int le = w / (DIM * NF);
+      const int r = w - le * (DIM * NF);
+      const int k = DIM == 2 ? r / NF : 0;
+      const int fi = r - k * NF;
+      const int o = le * NF + fi;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        lds[C::B_FL + (k * NC + c) * EPB * NF + o] = rFL[it][c];
+        lds[C::B_RB + (k * NC + c) * EPB * NF + o] = rRB[it][c];
+      }
+      lds[C::B_UB + k * EPB * NF + o] = rUB[it];
+      if constexpr (EQ == EQ_EULER) lds[C::B_KF + k * EPB * NF + o] = rKF[it];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 4: low-order state, bounds, nodal coefficients ----
+  const int le = tid / NP, s = tid - le * NP;
+  const int a = DIM == 2 ? s % N1 : s;
+  const int b = DIM == 2 ? s / N1 : 0;
+  double uL[NC], alpha = 1.0, m = 1.0;
+  int fl[DIM], fr[DIM];
+  fl[0] = le * NF + b * NFL + a;
+  fr[0] = fl[0] + 1;
+  if constexpr (DIM == 2) {
+    fl[1] = le * NF + a * NFL + b;
+    fr[1] = fl[1] + 1;
+  }
+  bool limited = false, ent = false, lov = false;
+  if (own) {
+    const double wa = lds[C::S_W + a];
+    const double wb = DIM == 2 ? lds[C::S_W + b] : 1.0;
+    m = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
+    const double cx = dt / (wa * S.hx);
+    const double cy = DIM == 2 ? dt / (wb * S.hy) : 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double d = (lds[C::B_FL + c * EPB * NF + fl[0]] - lds[C::B_FL + c * EPB * NF + fr[0]]) * cx;
+      if constexpr (DIM == 2)
+        d += (lds[C::B_FL + (NC + c) * EPB * NF + fl[1]] - lds[C::B_FL + (NC + c) * EPB * NF + fr[1]]) * cy;
+      uL[c] = U[c] + d;
+    }
+    double umin = U[0], umax = U[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double b1 = lds[C::B_UB + k * EPB * NF + fl[k]];
+      const double b2 = lds[C::B_UB + k * EPB * NF + fr[k]];
+      umin = fmin(umin, fmin(b1, b2));
+      umax = fmax(umax, fmax(b1, b2));
+    }
+    const double tol = 1e-12 * fmax(fabs(umin), fabs(umax));
+    lov = uL[0] > umax + tol || uL[0] < umin - tol;
+    double kmin_dbg = 0.0, az_dbg = 1.0;
+    if (A.limiter == LIM_TARGET) {
+      alpha = 1.0;
+    } else if (A.limiter == LIM_LOW) {
+      alpha = 0.0;
+    } else if (dt > 0.0) {
+      double Pp = 0.0, Pm = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const double cp = lds[C::B_RB + (k * NC) * EPB * NF + fr[k]];
+        const double cm = -lds[C::B_RB + (k * NC) * EPB * NF + fl[k]];
+        Pp += fmax(cp, 0.0) + fmax(cm, 0.0);
+        Pm += fmin(cp, 0.0) + fmin(cm, 0.0);
+      }
+      const double mdt = m / dt;
+      const double Qp = fmax(0.0, mdt * (umax - uL[0]));
+      const double Qm = fmin(0.0, mdt * (umin - uL[0]));
+      const double Rp = Pp == 0.0 ? 1.0 : fmin(1.0, Qp / Pp);
+      const double Rm = Pm == 0.0 ? 1.0 : fmin(1.0, Qm / Pm);
+      alpha = fmin(Rp, Rm);
+      az_dbg = alpha;
+      if constexpr (EQ == EQ_EULER) {
+        double kmin = INFINITY;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          kmin = fmin(kmin, fmin(lds[C::B_KF + k * EPB * NF + fl[k]], lds[C::B_KF + k * EPB * NF + fr[k]]));
+        const double az = alpha;
+        kmin_dbg = kmin;
+        const double g2 = 2.0 * DIM * dt / m;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) {
+            const int fidx = sd ? fr[k] : fl[k];
+            const double sg = sd ? 1.0 : -1.0;
+            double Pv[NC];
+            bool nz = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const double cf = sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
+              nz |= cf != 0.0;
+              Pv[c] = g2 * cf;
+            }
+            if (nz) alpha = fmin(alpha, entropy_search<DIM>(uL, Pv, az, kmin, A.ph));
+          }
+        }
+        ent = alpha < az;
+      }
+    }
+    limited = alpha < 1.0;
+    lds[C::S_AL + tid] = alpha;
+    if (A.trace) {
+      const long long g = (long long)e0 * NP + tid;
+      A.trace[g] = umin;
+      A.trace[nn + g] = umax;
+      A.trace[2 * nn + g] = kmin_dbg;
+      A.trace[3 * nn + g] = az_dbg;
+      A.trace[4 * nn + g] = alpha;
+    }
+  }
+  if (A.diag) {
+    const unsigned long long bl = __ballot(limited), be = __ballot(ent), bv = __ballot(lov);
+    if ((tid & 63) == 0) {
+      if (bl) atomicAdd(&A.diag->limited, (unsigned long long)__popcll(bl));
+      if (be) atomicAdd(&A.diag->entropy, (unsigned long long)__popcll(be));
+      if (bv) atomicOr(&A.diag->lo_violation, 1u);
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 5: subcell-face coefficients, corrected update, RK stage ----
+  if (own) {
+    double corr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) corr[c] = 0.0;
+    const int pos[2] = {a, b};
+    const int stride[2] = {1, N1};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      if (pos[k] < P) {
+        const double ap = fmin(alpha, lds[C::S_AL + tid + stride[k]]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) corr[c] += ap * lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]];
+      }
+      if (pos[k] > 0) {
+        const double am = fmin(alpha, lds[C::S_AL + tid - stride[k]]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) corr[c] -= am * lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
+      }
+    }
+    const double dtm = dt / m;
+    const long long g = (long long)e0 * NP + tid;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double fe = uL[c] + dtm * corr[c];
+      S.u_out[c * nn + g] = A.use_un ? A.a_s * Un[c] + A.b_s * fe : fe;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------
+// low-order CFL bound (eq. cfl-low): min over nodes of m_i/(2 sum dhat_ij)
+// ----------------------------------------------------------------------
+template <int EQ, int DIM, int P, int EPB>
+struct DtCfg {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  static constexpr int L = C::A_END;                        // [DIM][EPB*NF] wave speeds
+  static constexpr int W = L + DIM * EPB * C::NF;
+  static constexpr int R = W + C::N1;
+  static constexpr int LDS = R + C::BS / 64;
+};
+
+template <int EQ, int DIM, int P, int EPB>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDtArgs A) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  using D = DtCfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
+  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  __shared__ double lds[D::LDS];
+  const int tid = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int e0 = tile * EPB;
+  if (e0 >= A.ne) return;
+  const int nel = min(EPB, A.ne - e0);
+  for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = A.T.w[t];
+  double U[NC];
+  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, U, nullptr);
+  __syncthreads();
+  for (int w = tid; w < nel * DIM * NF; w += C::BS) {
+    const int le = w / (DIM * NF);
+    const int r = w - le * (DIM * NF);
+    const int k = DIM == 2 ? r / NF : 0;
+    const int fi = r - k * NF;
+    const int l = fi / NFL;
+    const int f = fi - l * NFL;
+    const int base = le * NS;
+    const int sl = base + (f == 0 ? NP + (2 * k) * C::TJ + l : own_slot<DIM, P>(k, l, f - 1));
+    const int sr = base + (f == P + 1 ? NP + (2 * k + 1) * C::TJ + l : own_slot<DIM, P>(k, l, f));
+    double UL[NC], UR[NC], XL[NX], XR[NX];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      UL[c] = lds[C::A_U + c * EPB * NS + sl];
+      UR[c] = lds[C::A_U + c * EPB * NS + sr];
+    }
+#pragma unroll
+    for (int q = 0; q < C::NAUX; ++q) {
+      XL[q] = lds[C::A_X + q * EPB * NS + sl];
+      XR[q] = lds[C::A_X + q * EPB * NS + sr];
+    }
+    lds[D::L + k * EPB * NF + le * NF + fi] = lambda_k<EQ, DIM>(k, UL, XL, UR, XR, A.ph);
+  }
+  __syncthreads();
+  double dti = INFINITY;
+  if (tid < nel * NP) {
+    const int le = tid / NP, s = tid - le * NP;
+    const int a = DIM == 2 ? s % N1 : s;
+    const int b = DIM == 2 ? s / N1 : 0;
+    const double wa = lds[D::W + a];
+    const double wb = DIM == 2 ? lds[D::W + b] : 1.0;
+    const int fx = le * NF + b * NFL + a;
+    double den = (lds[D::L + fx] + lds[D::L + fx + 1]) * (DIM == 2 ? wb * A.hy : 1.0);
+    if constexpr (DIM == 2) {
+      const int fy = le * NF + a * NFL + b;
+      den += (lds[D::L + EPB * NF + fy] + lds[D::L + EPB * NF + fy + 1]) * (wa * A.hx);
+    }
+    const double m = DIM == 2 ? wa * wb * A.hx * A.hy : wa * A.hx;
+    dti = den > 0.0 ? m / den : INFINITY;
+  }
+  for (int off = 32; off > 0; off >>= 1) dti = fmin(dti, __shfl_xor(dti, off));
+  if ((tid & 63) == 0) lds[D::R + (tid >> 6)] = dti;
+  __syncthreads();
+  if (tid == 0) {
+    double v = lds[D::R];
+    for (int i = 1; i < C::BS / 64; ++i) v = fmin(v, lds[D::R + i]);
+    atomicMin(A.out, (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+// ----------------------------------------------------------------------
+// elements per workgroup: variant 0 fills 64-lane multiples best
+// ----------------------------------------------------------------------
+constexpr int epb_for(int dim, int p, int variant) {
+  if (dim == 1) return (variant == 0 ? 64 : 128) / (p + 1);
+  constexpr int v0[9] = {0, 16, 7, 4, 5, 7, 5, 2, 3};
+  constexpr int v1[9] = {0, 32, 14, 8, 10, 3, 2, 4, 6};
+  return variant == 0 ? v0[p] : v1[p];
+}
+
+#define IDP_NUM_VARIANTS 1
+
+template <int EQ, int DIM, int P, int EPB>
+hipError_t launch_stage_t(const StageArgs& a, hipStream_t s) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  const int nb = (a.S.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((stage_kernel<EQ, DIM, P, EPB>), dim3(nb), dim3(C::BS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int EQ, int DIM, int P, int EPB>
+hipError_t launch_maxdt_t(const MaxDtArgs& a, hipStream_t s) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  const int nb = (a.ne + EPB - 1) / EPB;
+  hipLaunchKernelGGL((maxdt_kernel<EQ, DIM, P, EPB>), dim3(nb), dim3(C::BS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int EQ, int DIM, int P>
+hipError_t launch_stage_v(int variant, const StageArgs& a, hipStream_t s) {
+#if IDP_NUM_VARIANTS > 1
+  if (variant == 1) return launch_stage_t<EQ, DIM, P, epb_for(DIM, P, 1)>(a, s);
+#endif
+  (void)variant;
+  return launch_stage_t<EQ, DIM, P, epb_for(DIM, P, 0)>(a, s);
+}
+
+#define IDP_DEFINE_LAUNCHERS(NAME, EQ, DIM)                                              \
+  hipError_t launch_stage_##NAME(int p, int variant, const StageArgs& a, hipStream_t s) { \
+    switch (p) {                                                                         \
+      case 1: return launch_stage_v<EQ, DIM, 1>(variant, a, s);                          \
+      case 2: return launch_stage_v<EQ, DIM, 2>(variant, a, s);                          \
+      case 3: return launch_stage_v<EQ, DIM, 3>(variant, a, s);                          \
+      case 4: return launch_stage_v<EQ, DIM, 4>(variant, a, s);                          \
+      case 5: return launch_stage_v<EQ, DIM, 5>(variant, a, s);                          \
+      case 6: return launch_stage_v<EQ, DIM, 6>(variant, a, s);                          \
+      case 7: return launch_stage_v<EQ, DIM, 7>(variant, a, s);                          \
+      case 8: return launch_stage_v<EQ, DIM, 8>(variant, a, s);                          \
+    }                                                                                    \
+    return hipErrorInvalidValue;                                                         \
+  }                                                                                      \
+  hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s) {             \
+    switch (p) {                                                                         \
+      case 1: return launch_maxdt_t<EQ, DIM, 1, epb_for(DIM, 1, 0)>(a, s);               \
+      case 2: return launch_maxdt_t<EQ, DIM, 2, epb_for(DIM, 2, 0)>(a, s);               \
+      case 3: return launch_maxdt_t<EQ, DIM, 3, epb_for(DIM, 3, 0)>(a, s);               \
+      case 4: return launch_maxdt_t<EQ, DIM, 4, epb_for(DIM, 4, 0)>(a, s);               \
+      case 5: return launch_maxdt_t<EQ, DIM, 5, epb_for(DIM, 5, 0)>(a, s);               \
+      case 6: return launch_maxdt_t<EQ, DIM, 6, epb_for(DIM, 6, 0)>(a, s);               \
+      case 7: return launch_maxdt_t<EQ, DIM, 7, epb_for(DIM, 7, 0)>(a, s);               \
+      case 8: return launch_maxdt_t<EQ, DIM, 8, epb_for(DIM, 8, 0)>(a, s);               \
+    }                                                                                    \
+    return hipErrorInvalidValue;                                                         \
+  }                                                                                      \
+  int tile_elems_##NAME(int p, int variant) { return epb_for(DIM, p, variant); }         \
+  int num_variants_##NAME(int p) {                                                       \
+    (void)p;                                                                             \
+    return IDP_NUM_VARIANTS;                                                             \
+  }
+
+}  // namespace idp

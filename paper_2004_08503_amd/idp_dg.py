@@ -1,0 +1,183 @@
+"""ctypes binding of libidp_dg.so (include/idp_dg.h).
+
+Argument marshalling only: every step of the stage runs in the library's
+HIP kernels.  States are torch float64 CUDA tensors of shape (nc, Nn)
+(contiguous, layout u[c][e][b][a]); work is enqueued on the torch stream
+that was current when the Solver was created.  The library must have been
+built (``python -m paper_2004_08503_amd.build``); importing this module
+raises if it is missing.
+"""
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libidp_dg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "idp_dg.h")
+
+ADVECTION, BURGERS, EULER = 0, 1, 2
+SUBCELL, TARGET_ONLY, LOW_ONLY = 0, 1, 2
+EINVAL, ENOMEM, EHIP = -1, -2, -3
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("p", ctypes.c_int), ("eq", ctypes.c_int),
+                ("velocity", ctypes.c_double * 2), ("gamma", ctypes.c_double),
+                ("limiter", ctypes.c_int)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("limited_nodes", ctypes.c_longlong), ("entropy_nodes", ctypes.c_longlong),
+                ("bad_input", ctypes.c_int), ("low_order_violation", ctypes.c_int)]
+
+
+_VP = ctypes.c_void_p
+_DPP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def _declare(lib):
+    H = ctypes.c_void_p
+    sig = {
+        "idp_dg_create": (ctypes.c_int, [ctypes.POINTER(Desc), _VP, ctypes.POINTER(H)]),
+        "idp_dg_destroy": (None, [H]),
+        "idp_dg_num_nodes": (ctypes.c_long, [H]),
+        "idp_dg_num_comp": (ctypes.c_int, [H]),
+        "idp_dg_stage": (ctypes.c_int, [H, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
+        "idp_dg_stage_trace": (ctypes.c_int, [H, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP]),
+        "idp_dg_step": (ctypes.c_int, [H, _VP, ctypes.c_double]),
+        "idp_dg_step_cfl": (ctypes.c_int, [H, _VP, ctypes.c_double]),
+        "idp_dg_last_dt": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
+        "idp_dg_max_dt": (ctypes.c_int, [H, _VP, ctypes.POINTER(ctypes.c_double)]),
+        "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
+        "idp_dg_last_error": (ctypes.c_char_p, [H]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libidp_dg.so is not built (run python -m paper_2004_08503_amd.build)")
+lib = _declare(ctypes.CDLL(LIB_PATH))
+
+
+def header_symbols():
+    """Function names declared in include/idp_dg.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(idp_dg_\w+)\s*\(", text)))
+
+
+class IdpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("idp_dg error %d: %s" % (code, msg))
+        self.code = code
+
+
+def make_desc(prob):
+    d = Desc()
+    d.dim, d.nx, d.ny = int(prob.dim), int(prob.nx), int(prob.ny)
+    d.lx, d.ly = float(prob.lx), float(prob.ly)
+    d.p, d.eq = int(prob.p), int(prob.eq)
+    v = list(prob.vel) + [0.0] * (2 - len(prob.vel))
+    d.velocity[0], d.velocity[1] = float(v[0]), float(v[1])
+    d.gamma = float(prob.gamma)
+    d.limiter = int(prob.limiter)
+    return d
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One problem on the current device and torch stream."""
+
+    def __init__(self, prob, stream=None):
+        torch = _torch()
+        self.prob = prob
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        desc = make_desc(prob)
+        rc = lib.idp_dg_create(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream),
+                               ctypes.byref(self._h))
+        if rc:
+            raise IdpError(rc, lib.idp_dg_last_error(None).decode())
+        self.nc = lib.idp_dg_num_comp(self._h)
+        self.nn = lib.idp_dg_num_nodes(self._h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib.idp_dg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise IdpError(rc, lib.idp_dg_last_error(self._h).decode())
+
+    def _ptr(self, t, name):
+        torch = _torch()
+        if t is None:
+            return None
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() == self.nc * self.nn):
+            raise ValueError("%s must be a contiguous float64 CUDA tensor of %d values"
+                             % (name, self.nc * self.nn))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self):
+        torch = _torch()
+        return torch.empty((self.nc, self.nn), dtype=torch.float64, device="cuda")
+
+    def stage(self, u_n, u_s, u_out, dt, stage):
+        self._check(lib.idp_dg_stage(self._h, self._ptr(u_n, "u_n"), self._ptr(u_s, "u_s"),
+                                     self._ptr(u_out, "u_out"), float(dt), int(stage)))
+
+    def stage_trace(self, u_n, u_s, u_out, dt, stage):
+        """idp_dg_stage plus the limiter intermediates: returns a (5, Nn)
+        tensor [umin, umax, kmin, alpha_z, alpha]."""
+        torch = _torch()
+        tr = torch.empty((5, self.nn), dtype=torch.float64, device="cuda")
+        self._check(lib.idp_dg_stage_trace(self._h, self._ptr(u_n, "u_n"), self._ptr(u_s, "u_s"),
+                                           self._ptr(u_out, "u_out"), float(dt), int(stage),
+                                           ctypes.c_void_p(tr.data_ptr())))
+        return tr
+
+    def step(self, u, dt):
+        self._check(lib.idp_dg_step(self._h, self._ptr(u, "u"), float(dt)))
+
+    def step_cfl(self, u, cfl):
+        self._check(lib.idp_dg_step_cfl(self._h, self._ptr(u, "u"), float(cfl)))
+
+    def last_dt(self):
+        v = ctypes.c_double()
+        self._check(lib.idp_dg_last_dt(self._h, ctypes.byref(v)))
+        return v.value
+
+    def max_dt(self, u):
+        v = ctypes.c_double()
+        self._check(lib.idp_dg_max_dt(self._h, self._ptr(u, "u"), ctypes.byref(v)))
+        return v.value
+
+    def diagnostics(self):
+        d = Diag()
+        self._check(lib.idp_dg_diagnostics(self._h, ctypes.byref(d)))
+        return {"limited_nodes": d.limited_nodes, "entropy_nodes": d.entropy_nodes,
+                "bad_input": bool(d.bad_input), "low_order_violation": bool(d.low_order_violation)}

@@ -1,0 +1,52 @@
+"""The C-ABI library loads, exports every function include/idp_dg.h
+declares, and rejects bad arguments before touching a GPU (CPU only)."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_2004_08503_amd import idp_dg
+from paper_2004_08503_amd.workloads import Problem, EULER, BURGERS
+
+
+def test_exports_every_declared_symbol():
+    names = idp_dg.header_symbols()
+    assert "idp_dg_create" in names and "idp_dg_stage" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", idp_dg.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(idp_dg.lib, n)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(p=0), dict(p=9), dict(dim=3), dict(nx=0), dict(eq=5), dict(gamma=1.0),
+    dict(gamma=1.8), dict(limiter=4), dict(dim=1, ny=3), dict(lx=0.0), dict(lx=float("nan")),
+])
+def test_create_rejects_bad_desc(bad):
+    prob = Problem(dim=2, nx=4, ny=4, p=3, eq=EULER).replace(**bad)
+    h = ctypes.c_void_p()
+    d = idp_dg.make_desc(prob)
+    rc = idp_dg.lib.idp_dg_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert rc == idp_dg.EINVAL
+    assert not h.value
+    assert len(idp_dg.lib.idp_dg_last_error(None)) > 0
+
+
+def test_null_safety():
+    lib = idp_dg.lib
+    lib.idp_dg_destroy(None)
+    assert lib.idp_dg_num_nodes(None) == -1
+    assert lib.idp_dg_num_comp(None) == -1
+    assert lib.idp_dg_stage(None, None, None, None, 0.1, 0) == idp_dg.EINVAL
+    assert lib.idp_dg_step(None, None, 0.1) == idp_dg.EINVAL
+    assert lib.idp_dg_step_cfl(None, None, 0.5) == idp_dg.EINVAL
+    assert lib.idp_dg_max_dt(None, None, None) == idp_dg.EINVAL
+    assert lib.idp_dg_diagnostics(None, None) == idp_dg.EINVAL
+    assert lib.idp_dg_last_error(None) is not None
+    h = ctypes.c_void_p()
+    assert lib.idp_dg_create(None, None, ctypes.byref(h)) == idp_dg.EINVAL
+    d = idp_dg.make_desc(Problem(dim=2, nx=4, ny=4, p=3, eq=BURGERS))
+    assert lib.idp_dg_create(ctypes.byref(d), None, None) == idp_dg.EINVAL
