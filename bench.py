@@ -1,0 +1,174 @@
+"""Benchmark of the limited SSP-RK3 stage: 2-D Euler, 256 x 256 elements,
+p = 4 (1 638 400 Gauss-Lobatto nodes, 4 conserved components, FP64).
+
+One step = the whole hot path: the low-order CFL bound reduced on the
+device (dt = 1/2 of it, as in the paper's runs), then the three limited
+stages.  K steps are timed between device synchronisations; every kernel is
+bracketed by HIP events on the stream it runs on, which gives the stage
+kernel's average duration for the roofline and the p50/p99 stage latency.
+
+value = DOF (node) updates per second over the timed region:
+3 * Nn * K / elapsed.  The rocprofv3 counter figures under profiles/ supply
+the measured HBM traffic when they match the current kernel source.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 DOF-updates/s per limited RK stage (p=4 Euler); batched vs plain; p99"
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_euler2d_p4_256x256_pmc.md")
+KERNEL_SOURCES = ["paper_2004_08503_amd/csrc/stage_kernel.hpp",
+                  "paper_2004_08503_amd/csrc/common.hpp",
+                  "paper_2004_08503_amd/csrc/kernels_euler2.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_stage_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(wl, dt):
+    """The oracle (single-threaded C, as it stands) on one SSP-RK3 step of
+    the same workload."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.step(wl.prob, wl.u0, dt)
+    el = time.perf_counter() - t0
+    return {"value": 3 * wl.prob.num_nodes / el, "unit": "DOF-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one SSP-RK3 step (3 limited stages) of the same 256x256 p=4 Euler "
+                      "state on the host, %.1f s" % el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="elements per direction")
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the path is single-GPU; "
+              "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_08503_amd import idp_dg, workloads as W
+
+    wl = W.euler_2d(n=args.n, p=args.p)
+    prob = wl.prob
+    nn = prob.num_nodes
+    sv = idp_dg.Solver(prob)
+    u = torch.from_numpy(wl.u0.copy()).to("cuda")
+    b1, b2 = sv.empty(), sv.empty()
+    dtd = torch.empty(1, dtype=torch.float64, device="cuda")
+    cfl = wl.cfl
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        sv.max_dt_async(u, dtd)
+        if ev is not None:
+            ev[1].record(stream)
+        sv.stage_dt(None, u, b1, dtd, cfl, 0)
+        if ev is not None:
+            ev[2].record(stream)
+        sv.stage_dt(u, b1, b2, dtd, cfl, 1)
+        if ev is not None:
+            ev[3].record(stream)
+        sv.stage_dt(u, b2, u, dtd, cfl, 2)
+        if ev is not None:
+            ev[4].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.diagnostics()  # reset counters
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    diag = sv.diagnostics()
+    dt_last = sv.max_dt(u) * cfl
+
+    ms = np.array([[evs[k][j].elapsed_time(evs[k][j + 1]) for j in range(4)]
+                   for k in range(args.steps)])          # [step][maxdt, s0, s1, s2]
+    stage_ms = ms[:, 1:].reshape(-1)
+    # algorithmic bytes: stage 0 reads U and writes the output (64 B/node),
+    # stages 1 and 2 also read u^n (96 B/node)
+    bytes_stage = np.array([64.0, 96.0, 96.0]) * nn
+    achieved = bytes_stage.sum() / (ms[:, 1:].mean(axis=0).sum() * 1e-3) / 1e9   # GB/s
+    traffic = measured_traffic()
+    value = 3 * nn * args.steps / elapsed
+
+    assert np.isfinite(u.cpu().numpy()).all()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "euler_2d_%dx%d_p%d" % (args.n, args.n, args.p),
+                   "elements": prob.nx * prob.ny, "p": prob.p, "nodes": nn, "components": prob.nc,
+                   "cfl": cfl, "limiter": "subcell convex (density Zalesak + entropy)",
+                   "path": "plain (one solve per launch)", "parallelism": "single GPU"},
+        "stage_ms_p50": float(np.percentile(stage_ms, 50)),
+        "stage_ms_p99": float(np.percentile(stage_ms, 99)),
+        "maxdt_ms_mean": float(ms[:, 0].mean()),
+        "stage_ms_mean": [float(x) for x in ms[:, 1:].mean(axis=0)],
+        "stage_dof_updates_per_s": float(nn / (stage_ms.mean() * 1e-3)),
+        "limited_node_fraction": diag["limited_nodes"] / (3.0 * nn * args.steps),
+        "entropy_node_fraction": diag["entropy_nodes"] / (3.0 * nn * args.steps),
+        "dt_last": dt_last,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "stage_kernel<EULER,2,4,5>",
+                     "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, dt_last)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

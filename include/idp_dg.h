@@ -138,6 +138,18 @@ int idp_dg_last_dt(idp_dg* h, double* dt);
  * +inf when no node has dissipation.  Synchronises the stream. */
 int idp_dg_max_dt(idp_dg* h, const double* u, double* dt);
 
+/* The low-order CFL bound of idp_dg_max_dt written to device memory
+ * (dt_dev: one caller-owned double, 8-byte aligned) without synchronising:
+ * for callers that keep the whole step on the device or capture it in a
+ * graph. */
+int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev);
+
+/* idp_dg_stage with dt = cfl * dt_dev[0] read on the device (dt_dev as
+ * written by idp_dg_max_dt_async; cfl > 0).  A bound of +inf (no
+ * dissipation anywhere) is taken as dt = 0. */
+int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
+                    double* u_out, const double* dt_dev, double cfl, int stage);
+
 /* Copy out and reset the diagnostics (synchronises the stream). */
 int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out);
 

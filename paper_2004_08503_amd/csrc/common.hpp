@@ -21,14 +21,18 @@ struct Phys {
   double ex;           // (gamma-1)/(2 gamma)
   double inv_ex;       // 2 gamma/(gamma-1)
   int inv_ex_int;      // inv_ex when it is an integer (7 for gamma = 1.4), else 0
+  int gn;              // n when gamma = 1 + 2/n with n = 3 or 5 (gamma = 5/3, 7/5), else 0
 };
 
-// Diagnostics words in device memory.
+// Diagnostics words in device memory.  Counters are spread over slots
+// (indexed by workgroup) so that concurrent workgroups rarely meet on one
+// address; the host sums them.
+constexpr int DIAG_SLOTS = 1024;
 struct Diag {
-  unsigned long long limited;   // nodes with final alpha < 1
-  unsigned long long entropy;   // nodes where the entropy search bound alpha
-  unsigned int bad_input;       // rho <= 0 or p <= 0 seen in a stage input
-  unsigned int lo_violation;    // u^L outside its bounds (dt above CFL)
+  unsigned long long limited[DIAG_SLOTS];   // nodes with final alpha < 1
+  unsigned long long entropy[DIAG_SLOTS];   // nodes where the entropy search bound alpha
+  unsigned int bad_input;                   // rho <= 0 or p <= 0 seen in a stage input
+  unsigned int lo_violation;                // u^L outside its bounds (dt above CFL)
 };
 
 // Geometry of one solve and where its arrays are.
@@ -57,7 +61,7 @@ struct StageArgs {
 
 struct MaxDtArgs {
   const double* u;
-  unsigned long long* out;   // bit pattern of the (non-negative) minimum
+  double* partial;           // one minimum per workgroup
   long long nn;
   int nx, ny, ne, ntiles;
   double hx, hy;
@@ -81,7 +85,7 @@ IDP_DECLARE_LAUNCHERS(burg2)
 IDP_DECLARE_LAUNCHERS(euler1)
 IDP_DECLARE_LAUNCHERS(euler2)
 
-__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v);
-__global__ void u64_to_dt_kernel(const unsigned long long* bits, double* dt);
+// min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
+__global__ void min_reduce_kernel(const double* partial, int n, double* out);
 
 }  // namespace idp

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -101,7 +102,8 @@ struct idp_dg {
   double* buf1 = nullptr;   // stage buffers of idp_dg_step
   double* buf2 = nullptr;
   Diag* diag = nullptr;
-  unsigned long long* dtbits = nullptr;  // device dt of the last step_cfl
+  double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
+  double* partial = nullptr;   // per-workgroup minima of the time-step kernel
   // cached graph of one device-timestepped step
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -209,11 +211,11 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   return a;
 }
 
-MaxDtArgs make_dt_args(const idp_dg* h, const double* u, unsigned long long* out) {
+MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   MaxDtArgs a;
   std::memset(&a, 0, sizeof(a));
   a.u = u;
-  a.out = out;
+  a.partial = h->partial;
   a.nn = h->nn;
   a.nx = h->d.nx;
   a.ny = h->d.ny;
@@ -238,14 +240,20 @@ void drop_graph(idp_dg* h) {
   h->g_u = nullptr;
 }
 
+// the low-order CFL bound of u into out[0] (device), two launches
+hipError_t enqueue_max_dt(const idp_dg* h, const double* u, double* out, hipStream_t s) {
+  hipError_t e = launch_maxdt(h, make_dt_args(h, u), s);
+  if (e != hipSuccess) return e;
+  const int nb = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(1024), 0, s, h->partial, nb, out);
+  return hipGetLastError();
+}
+
 // enqueue one device-timestepped step on stream s
 hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, s, h->dtbits, 0x7ff0000000000000ULL);
-  hipError_t e = hipGetLastError();
+  hipError_t e = enqueue_max_dt(h, u, h->dtdev, s);
   if (e != hipSuccess) return e;
-  e = launch_maxdt(h, make_dt_args(h, u, h->dtbits), s);
-  if (e != hipSuccess) return e;
-  const double* dtp = reinterpret_cast<const double*>(h->dtbits);
+  const double* dtp = h->dtdev;
   e = launch_stage(h, make_stage_args(h, nullptr, u, h->buf1, 0.0, dtp, cfl, 0), s);
   if (e != hipSuccess) return e;
   e = launch_stage(h, make_stage_args(h, u, h->buf1, h->buf2, 0.0, dtp, cfl, 1), s);
@@ -256,11 +264,17 @@ hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
 }  // namespace
 
 namespace idp {
-__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
-}
-__global__ void u64_to_dt_kernel(const unsigned long long* bits, double* dt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) dt[0] = __longlong_as_double((long long)bits[0]);
+__global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial, int n, double* out) {
+  __shared__ double red[16];
+  double v = INFINITY;
+  for (int i = threadIdx.x; i < n; i += 1024) v = fmin(v, partial[i]);
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 16; ++i) v = fmin(v, red[i]);
+    out[0] = v;
+  }
 }
 }  // namespace idp
 
@@ -295,18 +309,22 @@ int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
   h->ph.inv_ex = 1.0 / h->ph.ex;
   const double r = std::nearbyint(h->ph.inv_ex);
   h->ph.inv_ex_int = (std::fabs(h->ph.inv_ex - r) < 1e-12 && r > 0 && r < 64) ? (int)r : 0;
+  const double gn = std::nearbyint(2.0 / (h->ph.gamma - 1.0));
+  h->ph.gn = ((gn == 3.0 || gn == 5.0) &&
+              std::fabs(h->ph.gamma - (1.0 + 2.0 / gn)) <= 4e-16 * h->ph.gamma) ? (int)gn : 0;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
   const size_t bytes = sizeof(double) * h->nc * h->nn;
   e = hipMalloc(&h->buf1, bytes);
   if (e == hipSuccess) e = hipMalloc(&h->buf2, bytes);
   if (e == hipSuccess) e = hipMalloc(&h->diag, sizeof(Diag) + 64);
-  if (e == hipSuccess) e = hipMalloc(&h->dtbits, 64);
+  if (e == hipSuccess) e = hipMalloc(&h->dtdev, 64);
+  if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * (h->ne + 64));
   if (e == hipSuccess) e = hipMemset(h->diag, 0, sizeof(Diag));
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? IDP_DG_ENOMEM : IDP_DG_EHIP;
     fail(nullptr, code, std::string("device allocation: ") + hipGetErrorString(e));
-    hipFree(h->buf1); hipFree(h->buf2); hipFree(h->diag); hipFree(h->dtbits);
+    hipFree(h->buf1); hipFree(h->buf2); hipFree(h->diag); hipFree(h->dtdev); hipFree(h->partial);
     delete h;
     return code;
   }
@@ -321,7 +339,8 @@ void idp_dg_destroy(idp_dg* h) {
   hipFree(h->buf1);
   hipFree(h->buf2);
   hipFree(h->diag);
-  hipFree(h->dtbits);
+  hipFree(h->dtdev);
+  hipFree(h->partial);
   delete h;
 }
 
@@ -407,12 +426,10 @@ int idp_dg_step_cfl(idp_dg* h, double* u, double cfl) {
 
 int idp_dg_last_dt(idp_dg* h, double* dt) {
   if (!h || !dt) return IDP_DG_EINVAL;
-  unsigned long long bits = 0;
-  hipError_t e = hipMemcpyAsync(&bits, h->dtbits, sizeof(bits), hipMemcpyDeviceToHost, h->stream);
+  double v = 0.0;
+  hipError_t e = hipMemcpyAsync(&v, h->dtdev, sizeof(v), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "last dt copy");
-  double v;
-  std::memcpy(&v, &bits, sizeof(v));
   if (!(v < INFINITY)) v = INFINITY;
   *dt = h->g_cfl * v;  // the same product the stage kernels form
   if (!(*dt < INFINITY)) *dt = 0.0;  // no dissipation anywhere: the step kept the state
@@ -422,31 +439,57 @@ int idp_dg_last_dt(idp_dg* h, double* dt) {
 int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
   if (!h) return IDP_DG_EINVAL;
   if (!u || !dt) return fail(h, IDP_DG_EINVAL, "NULL pointer");
-  unsigned long long* bits = h->dtbits + 1;   // keep the step's dt slot intact
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, h->stream, bits, 0x7ff0000000000000ULL);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = launch_maxdt(h, make_dt_args(h, u, bits), h->stream);
-  unsigned long long host = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&host, bits, sizeof(host), hipMemcpyDeviceToHost, h->stream);
+  double* slot = h->dtdev + 1;   // keep the step's dt slot intact
+  hipError_t e = enqueue_max_dt(h, u, slot, h->stream);
+  double v = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&v, slot, sizeof(v), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "max_dt");
-  double v;
-  std::memcpy(&v, &host, sizeof(v));
   *dt = v;
+  return 0;
+}
+
+int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!u || !dt_dev) return fail(h, IDP_DG_EINVAL, "NULL pointer");
+  if (reinterpret_cast<uintptr_t>(dt_dev) % 8) return fail(h, IDP_DG_EINVAL, "dt_dev not 8-byte aligned");
+  hipError_t e = enqueue_max_dt(h, u, dt_dev, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "max_dt_async");
+  return 0;
+}
+
+int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
+                    const double* dt_dev, double cfl, int stage) {
+  if (!h) return IDP_DG_EINVAL;
+  if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
+  if (!u_s || !u_out || !dt_dev || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL pointer");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, IDP_DG_EINVAL, "cfl must be finite and > 0");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u_out, u_s, n)) return fail(h, IDP_DG_EINVAL, "u_out overlaps u_s");
+  if (stage > 0 && u_n != u_out && overlaps(u_out, u_n, n))
+    return fail(h, IDP_DG_EINVAL, "u_out partially overlaps u_n");
+  hipError_t e = launch_stage(h, make_stage_args(h, u_n, u_s, u_out, 0.0, dt_dev, cfl, stage), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stage launch");
   return 0;
 }
 
 int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out) {
   if (!h || !out) return IDP_DG_EINVAL;
-  Diag d;
-  hipError_t e = hipMemcpyAsync(&d, h->diag, sizeof(d), hipMemcpyDeviceToHost, h->stream);
+  std::vector<unsigned char> buf(sizeof(Diag));
+  Diag* d = reinterpret_cast<Diag*>(buf.data());
+  hipError_t e = hipMemcpyAsync(d, h->diag, sizeof(Diag), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->diag, 0, sizeof(Diag), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "diagnostics");
-  out->limited_nodes = (long long)d.limited;
-  out->entropy_nodes = (long long)d.entropy;
-  out->bad_input = d.bad_input ? 1 : 0;
-  out->low_order_violation = d.lo_violation ? 1 : 0;
+  long long nl = 0, ne = 0;
+  for (int i = 0; i < DIAG_SLOTS; ++i) {
+    nl += (long long)d->limited[i];
+    ne += (long long)d->entropy[i];
+  }
+  out->limited_nodes = nl;
+  out->entropy_nodes = ne;
+  out->bad_input = d->bad_input ? 1 : 0;
+  out->low_order_violation = d->lo_violation ? 1 : 0;
   return 0;
 }
 

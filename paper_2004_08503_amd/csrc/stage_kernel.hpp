@@ -55,11 +55,18 @@ struct Cfg {
   static constexpr int B_UB = B_RB + DIM * NC * EPB * NF;
   static constexpr int B_KF = B_UB + DIM * EPB * NF;
   static constexpr int B_END = B_KF + (EQ == EQ_EULER ? DIM * EPB * NF : 0);
-  static constexpr int AB = A_END > B_END ? A_END : B_END;
+  // region C (after B, aliases the dead tail of A): Euler search data
+  static constexpr int C_UL = B_END;                                   // [NC][EPB*NP]
+  static constexpr int C_KM = C_UL + (EQ == EQ_EULER ? NC * EPB * NP : 0);
+  static constexpr int C_AZ = C_KM + (EQ == EQ_EULER ? EPB * NP : 0);
+  static constexpr int C_LIST = C_AZ + (EQ == EQ_EULER ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
+  static constexpr int C_END = C_LIST + (EQ == EQ_EULER ? DIM * EPB * NP : 0);
+  static constexpr int AB = A_END > C_END ? A_END : C_END;
   static constexpr int S_AL = AB;                       // nodal alpha
   static constexpr int S_W = S_AL + EPB * NP;           // weights
   static constexpr int S_Q = S_W + N1;                  // cumulative D
-  static constexpr int LDS = S_Q + P * N1;
+  static constexpr int S_LN = S_Q + P * N1;             // search list length (int)
+  static constexpr int LDS = S_LN + 1;
   static_assert(LDS * 8 <= 160 * 1024, "tile does not fit in LDS");
 };
 
@@ -103,8 +110,52 @@ __device__ inline double ipow(double x, int n) {
   return r;
 }
 
-// Euler auxiliaries of one state: 1/rho, p, c, p^-ex, K = p rho^-gamma.
-template <int DIM>
+template <int N>
+__device__ inline double ipow_c(double x) {
+  if constexpr (N == 1) return x;
+  else if constexpr (N % 2 == 0) { const double h = ipow_c<N / 2>(x); return h * h; }
+  else return x * ipow_c<N - 1>(x);
+}
+
+// x^(-1/N) in binary64 for x > 0: a single-precision seed from the hardware
+// log2/exp2, then three Newton steps y <- y (1 + (1 - x y^N)/N), which
+// converge quadratically from the seed's ~1e-7 to a few ulp.  Arguments
+// outside the normal single-precision range use pow.
+template <int N>
+__device__ inline double inv_root(double x) {
+  const float xf = (float)x;
+  if (!(xf > 1e-36f && xf < 1e36f)) return pow(x, -1.0 / N);
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / N));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double e = fma(-x, ipow_c<N>(y), 1.0);
+    y = fma(y * e, 1.0 / N, y);
+  }
+  return y;
+}
+
+// p^-(gamma-1)/(2 gamma), rho^gamma and rho^-gamma.  For gamma = 1 + 2/n
+// (n = 5: 7/5, n = 3: 5/3) these are p^(-1/(n+2)), rho^2 z^(n-2) and
+// z^(n+2) with z = rho^(-1/n); other gammas use pow.
+__device__ inline double pow_neg_ex(double p, const Phys& ph) {
+  if (ph.gn == 5) return inv_root<7>(p);
+  if (ph.gn == 3) return inv_root<5>(p);
+  return pow(p, -ph.ex);
+}
+__device__ inline double rho_pow_gamma(double r, const Phys& ph) {
+  if (ph.gn == 5) { const double z = inv_root<5>(r); return (r * r) * (z * z * z); }
+  if (ph.gn == 3) { const double z = inv_root<3>(r); return (r * r) * z; }
+  return pow(r, ph.gamma);
+}
+__device__ inline double rho_pow_neg_gamma(double r, const Phys& ph) {
+  if (ph.gn == 5) return ipow_c<7>(inv_root<5>(r));
+  if (ph.gn == 3) return ipow_c<5>(inv_root<3>(r));
+  return pow(r, -ph.gamma);
+}
+
+// Euler auxiliaries of one state: 1/rho, p, c, p^-ex, K = p rho^-gamma
+// (K only when WITHK).
+template <int DIM, bool WITHK = true>
 __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, bool& bad) {
   const double rinv = 1.0 / U[0];
   double mm = 0.0;
@@ -115,8 +166,8 @@ __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, boo
   X[0] = rinv;
   X[1] = p;
   X[2] = sqrt(ph.gamma * p * rinv);
-  X[3] = pow(p, -ph.ex);
-  X[4] = p * pow(U[0], -ph.gamma);
+  X[3] = pow_neg_ex(p, ph);
+  if constexpr (WITHK) X[4] = p * rho_pow_neg_gamma(U[0], ph);
 }
 
 // flux in direction k of one state (X: Euler auxiliaries)
@@ -189,7 +240,7 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
     mp += m * P[1 + k];
   }
   const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
-  const double rg = pow(r.rho, g);
+  const double rg = rho_pow_gamma(r.rho, ph);
   const double kg = kmin / (g - 1.0);
   r.phi = E - 0.5 * mm * rinv - kg * rg;
   r.dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
@@ -203,13 +254,11 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
 // rounding, so once the steps stall the search steps back geometrically
 // from the last infeasible point to the nearest feasible one.  The result
 // is feasible and within a few rounding widths of the supremum.
+// Called for a partial state that is admissible at t = 0 and not at t = T.
 template <int DIM>
-__device__ double entropy_search(const double* uL, const double* P, double T, double kmin,
-                                 const Phys& ph) {
+__device__ double entropy_root(const double* uL, const double* P, double T, double kmin,
+                               const Phys& ph) {
   PhiVal er = phi_at<DIM>(T, uL, P, kmin, ph);
-  if (er.rho > 0.0 && er.phi >= 0.0) return T;
-  const PhiVal e0 = phi_at<DIM>(0.0, uL, P, kmin, ph);
-  if (!(e0.rho > 0.0 && e0.phi >= 0.0)) return 0.0;
   double tl = 0.0, tr = T;
   bool done = false;
   for (int it = 0; it < 64; ++it) {
@@ -261,6 +310,8 @@ __device__ double entropy_search(const double* uL, const double* P, double T, do
   return tl;
 }
 
+__device__ inline const Phys& ph_of(const StageArgs& A) { return A.ph; }
+
 // local slot of the node at position pos of line l in direction k
 template <int DIM, int P>
 __device__ inline int own_slot(int k, int l, int pos) {
@@ -306,10 +357,10 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
     for (int c = 0; c < NC; ++c) U[c] = lds[C::A_U + c * EPB * NS + t];
     if constexpr (EQ == EQ_EULER) {
       bool b;
-      euler_aux<DIM>(U, ph, X, b);
+      euler_aux<DIM, FLUX>(U, ph, X, b);
       bad |= b;
 #pragma unroll
-      for (int q = 0; q < C::NAUX; ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
+      for (int q = 0; q < (FLUX ? C::NAUX : C::NAUX - 1); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
     }
     if constexpr (FLUX) {
       if (s < NP) {
@@ -361,6 +412,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
   if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
 
   load_tables<P>(lds + C::S_W, lds + C::S_Q, A.T, C::BS);
+  if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
   load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
                                    A.diag ? &A.diag->bad_input : nullptr);
@@ -444,7 +496,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
   }
   __syncthreads();
 
-  // ---- phase 4: low-order state, bounds, nodal coefficients ----
+  // ---- phase 4a: low-order state, bounds, Zalesak, entropy checks ----
   const int le = tid / NP, s = tid - le * NP;
   const int a = DIM == 2 ? s % N1 : s;
   const int b = DIM == 2 ? s / N1 : 0;
@@ -456,7 +508,8 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
     fl[1] = le * NF + a * NFL + b;
     fr[1] = fl[1] + 1;
   }
-  bool limited = false, ent = false, lov = false;
+  bool lov = false;
+  double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
   if (own) {
     const double wa = lds[C::S_W + a];
     const double wb = DIM == 2 ? lds[C::S_W + b] : 1.0;
@@ -470,7 +523,8 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         d += (lds[C::B_FL + (NC + c) * EPB * NF + fl[1]] - lds[C::B_FL + (NC + c) * EPB * NF + fr[1]]) * cy;
       uL[c] = U[c] + d;
     }
-    double umin = U[0], umax = U[0];
+    umin = U[0];
+    umax = U[0];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const double b1 = lds[C::B_UB + k * EPB * NF + fl[k]];
@@ -480,7 +534,6 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
     }
     const double tol = 1e-12 * fmax(fabs(umin), fabs(umax));
     lov = uL[0] > umax + tol || uL[0] < umin - tol;
-    double kmin_dbg = 0.0, az_dbg = 1.0;
     if (A.limiter == LIM_TARGET) {
       alpha = 1.0;
     } else if (A.limiter == LIM_LOW) {
@@ -500,15 +553,19 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
       const double Rp = Pp == 0.0 ? 1.0 : fmin(1.0, Qp / Pp);
       const double Rm = Pm == 0.0 ? 1.0 : fmin(1.0, Qm / Pm);
       alpha = fmin(Rp, Rm);
+      alpha = alpha > 0.0 ? alpha : 0.0;  // no negative zero: alpha is ordered as a u64 below
       az_dbg = alpha;
       if constexpr (EQ == EQ_EULER) {
+        // every partial state uL + t 2d dt/m (+-rbar) must stay admissible
+        // for t <= alpha (eq. convex-provisional); faces whose partial
+        // state fails at t = alpha go to the workgroup's search list
         double kmin = INFINITY;
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
           kmin = fmin(kmin, fmin(lds[C::B_KF + k * EPB * NF + fl[k]], lds[C::B_KF + k * EPB * NF + fr[k]]));
-        const double az = alpha;
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dt / m;
+        int act = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
 #pragma unroll
@@ -523,14 +580,70 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
               nz |= cf != 0.0;
               Pv[c] = g2 * cf;
             }
-            if (nz) alpha = fmin(alpha, entropy_search<DIM>(uL, Pv, az, kmin, A.ph));
+            if (nz) {
+              const PhiVal e = phi_at<DIM>(alpha, uL, Pv, kmin, ph_of(A));
+              if (!(e.rho > 0.0 && e.phi >= 0.0)) act |= 1 << (2 * k + sd);
+            }
           }
         }
-        ent = alpha < az;
+        if (act) {
+          const double zero[NC] = {};
+          const PhiVal e0 = phi_at<DIM>(0.0, uL, zero, kmin, ph_of(A));
+          if (!(e0.rho > 0.0 && e0.phi >= 0.0)) {  // u^L itself off the set by rounding
+            alpha = 0.0;
+            act = 0;
+          }
+        }
+        if (act) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
+          lds[C::C_KM + tid] = kmin;
+          lds[C::C_AZ + tid] = alpha;
+          int* list = reinterpret_cast<int*>(lds + C::C_LIST);
+          int* count = reinterpret_cast<int*>(lds + C::S_LN);
+#pragma unroll
+          for (int f = 0; f < 2 * DIM; ++f)
+            if (act & (1 << f)) list[atomicAdd(count, 1)] = tid * 4 + f;
+        }
       }
     }
-    limited = alpha < 1.0;
     lds[C::S_AL + tid] = alpha;
+  }
+  if constexpr (EQ == EQ_EULER) {
+    __syncthreads();
+    // ---- phase 4b: entropy line searches, spread over the workgroup ----
+    const int nact = *reinterpret_cast<const int*>(lds + C::S_LN);
+    const int* list = reinterpret_cast<const int*>(lds + C::C_LIST);
+    for (int w = tid; w < nact; w += C::BS) {
+      const int item = list[w];
+      const int node = item >> 2, f = item & 3, k = f >> 1, sd = f & 1;
+      const int nle = node / NP, ns = node - nle * NP;
+      const int na = DIM == 2 ? ns % N1 : ns;
+      const int nb = DIM == 2 ? ns / N1 : 0;
+      const double wa = lds[C::S_W + na];
+      const double wb = DIM == 2 ? lds[C::S_W + nb] : 1.0;
+      const double mm = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
+      const double g2 = 2.0 * DIM * dt / mm;
+      const int fidx = k == 0 ? nle * NF + nb * NFL + na + sd : nle * NF + na * NFL + nb + sd;
+      double ul[NC], Pv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        ul[c] = lds[C::C_UL + c * EPB * NP + node];
+        Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
+      }
+      const double t = entropy_root<DIM>(ul, Pv, lds[C::C_AZ + node], lds[C::C_KM + node], ph_of(A));
+      atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
+                (unsigned long long)__double_as_longlong(t));
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 5: subcell-face coefficients, corrected update, RK stage ----
+  bool limited = false, ent = false;
+  if (own) {
+    alpha = lds[C::S_AL + tid];
+    limited = alpha < 1.0;
+    ent = EQ == EQ_EULER && A.limiter == LIM_SUBCELL && alpha < az_dbg;
     if (A.trace) {
       const long long g = (long long)e0 * NP + tid;
       A.trace[g] = umin;
@@ -539,19 +652,6 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
       A.trace[3 * nn + g] = az_dbg;
       A.trace[4 * nn + g] = alpha;
     }
-  }
-  if (A.diag) {
-    const unsigned long long bl = __ballot(limited), be = __ballot(ent), bv = __ballot(lov);
-    if ((tid & 63) == 0) {
-      if (bl) atomicAdd(&A.diag->limited, (unsigned long long)__popcll(bl));
-      if (be) atomicAdd(&A.diag->entropy, (unsigned long long)__popcll(be));
-      if (bv) atomicOr(&A.diag->lo_violation, 1u);
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 5: subcell-face coefficients, corrected update, RK stage ----
-  if (own) {
     double corr[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) corr[c] = 0.0;
@@ -576,6 +676,15 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
     for (int c = 0; c < NC; ++c) {
       const double fe = uL[c] + dtm * corr[c];
       S.u_out[c * nn + g] = A.use_un ? A.a_s * Un[c] + A.b_s * fe : fe;
+    }
+  }
+  if (A.diag) {
+    const unsigned long long bl = __ballot(limited), be = __ballot(ent), bv = __ballot(lov);
+    if ((tid & 63) == 0) {
+      const int slot = (blockIdx.x * (C::BS / 64) + (tid >> 6)) & (DIAG_SLOTS - 1);
+      if (bl) atomicAdd(&A.diag->limited[slot], (unsigned long long)__popcll(bl));
+      if (be) atomicAdd(&A.diag->entropy[slot], (unsigned long long)__popcll(be));
+      if (bv) atomicOr(&A.diag->lo_violation, 1u);
     }
   }
 }
@@ -625,7 +734,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDt
       UR[c] = lds[C::A_U + c * EPB * NS + sr];
     }
 #pragma unroll
-    for (int q = 0; q < C::NAUX; ++q) {
+    for (int q = 0; q < (C::NAUX > 0 ? C::NAUX - 1 : 0); ++q) {
       XL[q] = lds[C::A_X + q * EPB * NS + sl];
       XR[q] = lds[C::A_X + q * EPB * NS + sr];
     }
@@ -654,7 +763,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDt
   if (tid == 0) {
     double v = lds[D::R];
     for (int i = 1; i < C::BS / 64; ++i) v = fmin(v, lds[D::R + i]);
-    atomicMin(A.out, (unsigned long long)__double_as_longlong(v));
+    A.partial[blockIdx.x] = v;
   }
 }
 

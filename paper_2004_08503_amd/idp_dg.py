@@ -50,6 +50,8 @@ def _declare(lib):
         "idp_dg_step_cfl": (ctypes.c_int, [H, _VP, ctypes.c_double]),
         "idp_dg_last_dt": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
         "idp_dg_max_dt": (ctypes.c_int, [H, _VP, ctypes.POINTER(ctypes.c_double)]),
+        "idp_dg_max_dt_async": (ctypes.c_int, [H, _VP, _VP]),
+        "idp_dg_stage_dt": (ctypes.c_int, [H, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
     }
@@ -175,6 +177,24 @@ class Solver:
         v = ctypes.c_double()
         self._check(lib.idp_dg_max_dt(self._h, self._ptr(u, "u"), ctypes.byref(v)))
         return v.value
+
+    def max_dt_async(self, u, dt_dev):
+        """Write the CFL bound of u into the one-element float64 CUDA tensor
+        dt_dev without synchronising."""
+        self._check(lib.idp_dg_max_dt_async(self._h, self._ptr(u, "u"), self._scalar(dt_dev)))
+
+    def stage_dt(self, u_n, u_s, u_out, dt_dev, cfl, stage):
+        """idp_dg_stage with dt = cfl * dt_dev[0] read on the device."""
+        self._check(lib.idp_dg_stage_dt(self._h, self._ptr(u_n, "u_n"), self._ptr(u_s, "u_s"),
+                                        self._ptr(u_out, "u_out"), self._scalar(dt_dev),
+                                        float(cfl), int(stage)))
+
+    def _scalar(self, t):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.numel() >= 1):
+            raise ValueError("dt_dev must be a float64 CUDA tensor")
+        return ctypes.c_void_p(t.data_ptr())
 
     def diagnostics(self):
         d = Diag()
