@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="elements per direction")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 512 MiB (4 times), the reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path is single-GPU; "
@@ -82,6 +85,16 @@ def main():
 
     import torch
     from paper_2004_08503_amd import idp_dg, workloads as W
+
+    if args.copy_calibration:
+        n = 64 * 1024 * 1024    # doubles: 512 MiB read + 512 MiB written per copy
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 8 * n, "copy_bytes_written_per_launch": 8 * n}))
+        return
 
     wl = W.euler_2d(n=args.n, p=args.p)
     prob = wl.prob

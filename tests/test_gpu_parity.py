@@ -6,7 +6,9 @@ max |u_gpu - u_ref| / max |u_ref| <= 1e-12 for one stage and <= 1e-9 after
 100 SSP-RK3 steps.  Both sides compute in binary64; they differ by the
 order of rounding (the GPU contracts multiply-adds, forms the high-order
 subcell flux directly instead of by prefix sums, and finds the entropy
-root by Newton/secant instead of bisection, both to a 1e-15 bracket).
+root by Newton from the infeasible side with a step back to the nearest
+admissible point instead of bisection; both land within rounding of the
+supremum).
 """
 import numpy as np
 import pytest
