@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_euler2d_p4_256x256_pmc.md")
 KERNEL_SOURCES = ["paper_2004_08503_amd/csrc/stage_kernel.hpp",
                   "paper_2004_08503_amd/csrc/common.hpp",
-                  "paper_2004_08503_amd/csrc/kernels_euler2.hip"]
+                  "paper_2004_08503_amd/csrc/kernels_euler75_2.hip"]
 
 
 def kernel_hash():
@@ -175,7 +175,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "stage_kernel<EULER,2,4,5>",
+                     "kernel": "stage_kernel<EULER75,2,4,5>",
                      "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn)},
     }
     if not args.no_cpu:

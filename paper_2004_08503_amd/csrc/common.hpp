@@ -4,7 +4,12 @@
 
 namespace idp {
 
-enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2 };
+// Equation codes of the kernels.  Euler comes in three instantiations:
+// generic gamma, and gamma = 1 + 2/n with n = 3 (5/3) or n = 5 (7/5), where
+// the fractional powers become integer powers of one inverse root.
+enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2, EQ_EULER53 = 3, EQ_EULER75 = 4 };
+constexpr bool is_euler(int eq) { return eq >= EQ_EULER; }
+constexpr int gn_of(int eq) { return eq == EQ_EULER53 ? 3 : eq == EQ_EULER75 ? 5 : 0; }
 enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2 };
 constexpr int MAXP = 8;
 
@@ -12,6 +17,7 @@ constexpr int MAXP = 8;
 struct Tables {
   double w[MAXP + 1];             // Gauss-Lobatto weights on [0,1]
   double Q[MAXP * (MAXP + 1)];    // Q[a][e] = sum_{c<=a} D[c][e], a < p; rows of p+1
+  double iw[MAXP + 1];            // 1 / w
 };
 
 // Physics constants of one problem.
@@ -21,7 +27,6 @@ struct Phys {
   double ex;           // (gamma-1)/(2 gamma)
   double inv_ex;       // 2 gamma/(gamma-1)
   int inv_ex_int;      // inv_ex when it is an integer (7 for gamma = 1.4), else 0
-  int gn;              // n when gamma = 1 + 2/n with n = 3 or 5 (gamma = 5/3, 7/5), else 0
 };
 
 // Diagnostics words in device memory.  Counters are spread over slots
@@ -46,6 +51,7 @@ struct Solve {
   int nx, ny, ne;       // elements
   int ntiles;           // element tiles of this solve
   double hx, hy;
+  double ihx, ihy;      // 1/hx, 1/hy
 };
 
 struct StageArgs {
@@ -84,6 +90,10 @@ IDP_DECLARE_LAUNCHERS(burg1)
 IDP_DECLARE_LAUNCHERS(burg2)
 IDP_DECLARE_LAUNCHERS(euler1)
 IDP_DECLARE_LAUNCHERS(euler2)
+IDP_DECLARE_LAUNCHERS(euler53_1)
+IDP_DECLARE_LAUNCHERS(euler53_2)
+IDP_DECLARE_LAUNCHERS(euler75_1)
+IDP_DECLARE_LAUNCHERS(euler75_2)
 
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);

@@ -97,6 +97,7 @@ struct idp_dg {
   long long nn = 0;
   int ne = 0;
   int variant = 0;
+  int kcode = 0;   // kernel equation code (EQ_*), Euler split by gamma
   Tables T{};
   Phys ph{};
   double* buf1 = nullptr;   // stage buffers of idp_dg_step
@@ -143,41 +144,56 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   return true;
 }
 
+// kernel family: equation code (with the gamma specialisation) and dimension
+int family(const idp_dg* h) { return h->kcode * 2 + (h->d.dim - 1); }
+
 hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
   const int p = h->d.p;
-  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+  switch (family(h)) {
     case 0: return launch_stage_adv1(p, h->variant, a, s);
     case 1: return launch_stage_adv2(p, h->variant, a, s);
     case 2: return launch_stage_burg1(p, h->variant, a, s);
     case 3: return launch_stage_burg2(p, h->variant, a, s);
     case 4: return launch_stage_euler1(p, h->variant, a, s);
     case 5: return launch_stage_euler2(p, h->variant, a, s);
+    case 6: return launch_stage_euler53_1(p, h->variant, a, s);
+    case 7: return launch_stage_euler53_2(p, h->variant, a, s);
+    case 8: return launch_stage_euler75_1(p, h->variant, a, s);
+    case 9: return launch_stage_euler75_2(p, h->variant, a, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
   const int p = h->d.p;
-  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+  switch (family(h)) {
     case 0: return launch_maxdt_adv1(p, a, s);
     case 1: return launch_maxdt_adv2(p, a, s);
     case 2: return launch_maxdt_burg1(p, a, s);
     case 3: return launch_maxdt_burg2(p, a, s);
     case 4: return launch_maxdt_euler1(p, a, s);
     case 5: return launch_maxdt_euler2(p, a, s);
+    case 6: return launch_maxdt_euler53_1(p, a, s);
+    case 7: return launch_maxdt_euler53_2(p, a, s);
+    case 8: return launch_maxdt_euler75_1(p, a, s);
+    case 9: return launch_maxdt_euler75_2(p, a, s);
   }
   return hipErrorInvalidValue;
 }
 
 int tile_elems(const idp_dg* h) {
   const int p = h->d.p;
-  switch (h->d.eq * 2 + (h->d.dim - 1)) {
+  switch (family(h)) {
     case 0: return tile_elems_adv1(p, h->variant);
     case 1: return tile_elems_adv2(p, h->variant);
     case 2: return tile_elems_burg1(p, h->variant);
     case 3: return tile_elems_burg2(p, h->variant);
     case 4: return tile_elems_euler1(p, h->variant);
     case 5: return tile_elems_euler2(p, h->variant);
+    case 6: return tile_elems_euler53_1(p, h->variant);
+    case 7: return tile_elems_euler53_2(p, h->variant);
+    case 8: return tile_elems_euler75_1(p, h->variant);
+    case 9: return tile_elems_euler75_2(p, h->variant);
   }
   return 1;
 }
@@ -201,6 +217,8 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.S.ntiles = (h->ne + tile_elems(h) - 1) / tile_elems(h);
   a.S.hx = h->d.lx / h->d.nx;
   a.S.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
+  a.S.ihx = 1.0 / a.S.hx;
+  a.S.ihy = 1.0 / a.S.hy;
   a.ph = h->ph;
   a.T = h->T;
   a.a_s = As[stage];
@@ -309,9 +327,14 @@ int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
   h->ph.inv_ex = 1.0 / h->ph.ex;
   const double r = std::nearbyint(h->ph.inv_ex);
   h->ph.inv_ex_int = (std::fabs(h->ph.inv_ex - r) < 1e-12 && r > 0 && r < 64) ? (int)r : 0;
-  const double gn = std::nearbyint(2.0 / (h->ph.gamma - 1.0));
-  h->ph.gn = ((gn == 3.0 || gn == 5.0) &&
-              std::fabs(h->ph.gamma - (1.0 + 2.0 / gn)) <= 4e-16 * h->ph.gamma) ? (int)gn : 0;
+  h->kcode = desc->eq;
+  if (desc->eq == IDP_DG_EULER) {
+    const double gn = std::nearbyint(2.0 / (h->ph.gamma - 1.0));
+    const bool exact = std::fabs(h->ph.gamma - (1.0 + 2.0 / gn)) <= 4e-16 * h->ph.gamma;
+    if (exact && gn == 5.0) h->kcode = EQ_EULER75;
+    if (exact && gn == 3.0) h->kcode = EQ_EULER53;
+  }
+  for (int k = 0; k <= desc->p; ++k) h->T.iw[k] = 1.0 / h->T.w[k];
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
   const size_t bytes = sizeof(double) * h->nc * h->nn;

@@ -37,8 +37,8 @@ struct Cfg {
   static constexpr int TJ = DIM == 2 ? N1 : 1;          // nodes per face trace
   static constexpr int NT = 2 * DIM * TJ;               // trace nodes per element
   static constexpr int NS = NP + NT;                    // LDS slots per element
-  static constexpr int NC = EQ == EQ_EULER ? DIM + 2 : 1;
-  static constexpr int NAUX = EQ == EQ_EULER ? 5 : 0;   // 1/rho, p, c, p^-ex, K
+  static constexpr int NC = is_euler(EQ) ? DIM + 2 : 1;
+  static constexpr int NAUX = is_euler(EQ) ? 5 : 0;   // 1/rho, p, c, p^-ex, K
   static constexpr int NFL = P + 2;                     // subcell faces per line
   static constexpr int NL = DIM == 2 ? N1 : 1;          // lines per direction
   static constexpr int NF = NFL * NL;                   // faces per direction
@@ -54,18 +54,19 @@ struct Cfg {
   static constexpr int B_RB = B_FL + DIM * NC * EPB * NF;
   static constexpr int B_UB = B_RB + DIM * NC * EPB * NF;
   static constexpr int B_KF = B_UB + DIM * EPB * NF;
-  static constexpr int B_END = B_KF + (EQ == EQ_EULER ? DIM * EPB * NF : 0);
+  static constexpr int B_END = B_KF + (is_euler(EQ) ? DIM * EPB * NF : 0);
   // region C (after B, aliases the dead tail of A): Euler search data
   static constexpr int C_UL = B_END;                                   // [NC][EPB*NP]
-  static constexpr int C_KM = C_UL + (EQ == EQ_EULER ? NC * EPB * NP : 0);
-  static constexpr int C_AZ = C_KM + (EQ == EQ_EULER ? EPB * NP : 0);
-  static constexpr int C_LIST = C_AZ + (EQ == EQ_EULER ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
-  static constexpr int C_END = C_LIST + (EQ == EQ_EULER ? DIM * EPB * NP : 0);
+  static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * EPB * NP : 0);
+  static constexpr int C_AZ = C_KM + (is_euler(EQ) ? EPB * NP : 0);
+  static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
+  static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * EPB * NP : 0);
   static constexpr int AB = A_END > C_END ? A_END : C_END;
   static constexpr int S_AL = AB;                       // nodal alpha
   static constexpr int S_W = S_AL + EPB * NP;           // weights
   static constexpr int S_Q = S_W + N1;                  // cumulative D
-  static constexpr int S_LN = S_Q + P * N1;             // search list length (int)
+  static constexpr int S_IW = S_Q + P * N1;             // 1/w
+  static constexpr int S_LN = S_IW + N1;                // search list length (int)
   static constexpr int LDS = S_LN + 1;
   static_assert(LDS * 8 <= 160 * 1024, "tile does not fit in LDS");
 };
@@ -134,30 +135,20 @@ __device__ inline double inv_root(double x) {
   return y;
 }
 
-// p^-(gamma-1)/(2 gamma), rho^gamma and rho^-gamma.  For gamma = 1 + 2/n
-// (n = 5: 7/5, n = 3: 5/3) these are p^(-1/(n+2)), rho^2 z^(n-2) and
-// z^(n+2) with z = rho^(-1/n); other gammas use pow.
-__device__ inline double pow_neg_ex(double p, const Phys& ph) {
-  if (ph.gn == 5) return inv_root<7>(p);
-  if (ph.gn == 3) return inv_root<5>(p);
-  return pow(p, -ph.ex);
-}
-__device__ inline double rho_pow_gamma(double r, const Phys& ph) {
-  if (ph.gn == 5) { const double z = inv_root<5>(r); return (r * r) * (z * z * z); }
-  if (ph.gn == 3) { const double z = inv_root<3>(r); return (r * r) * z; }
-  return pow(r, ph.gamma);
-}
-__device__ inline double rho_pow_neg_gamma(double r, const Phys& ph) {
-  if (ph.gn == 5) return ipow_c<7>(inv_root<5>(r));
-  if (ph.gn == 3) return ipow_c<5>(inv_root<3>(r));
-  return pow(r, -ph.gamma);
-}
-
-// Euler auxiliaries of one state: 1/rho, p, c, p^-ex, K = p rho^-gamma
-// (K only when WITHK).
-template <int DIM, bool WITHK = true>
+// Euler auxiliaries of one state: X = (1/rho, p, c, p^-(gamma-1)/(2gamma),
+// K = p rho^-gamma) (K only when WITHK).  For gamma = 1 + 2/n (GN = n = 5:
+// 7/5, n = 3: 5/3) every fractional power is an integer power of
+// z = rho^(-1/n) or of p^(-1/(n+2)): 1/rho = z^n, K = p z^(n+2); otherwise
+// pow and a division are used.
+template <int DIM, int GN, bool WITHK = true>
 __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, bool& bad) {
-  const double rinv = 1.0 / U[0];
+  double rinv, z = 0.0;
+  if constexpr (GN > 0) {
+    z = inv_root<GN>(U[0]);
+    rinv = ipow_c<GN>(z);
+  } else {
+    rinv = 1.0 / U[0];
+  }
   double mm = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) mm += U[1 + k] * U[1 + k];
@@ -166,8 +157,13 @@ __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, boo
   X[0] = rinv;
   X[1] = p;
   X[2] = sqrt(ph.gamma * p * rinv);
-  X[3] = pow_neg_ex(p, ph);
-  if constexpr (WITHK) X[4] = p * rho_pow_neg_gamma(U[0], ph);
+  if constexpr (GN > 0) {
+    X[3] = inv_root<GN + 2>(p);
+    if constexpr (WITHK) X[4] = p * ipow_c<GN + 2>(z);
+  } else {
+    X[3] = pow(p, -ph.ex);
+    if constexpr (WITHK) X[4] = p * pow(U[0], -ph.gamma);
+  }
 }
 
 // flux in direction k of one state (X: Euler auxiliaries)
@@ -205,10 +201,20 @@ __device__ inline double lambda_k(int k, const double* UL, const double* XL, con
     num = num < 0.0 ? 0.0 : num;
     const double den = cl * XL[3] + cr * XR[3];
     const double base = num / den;
-    const double pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
+    constexpr int GN = gn_of(EQ);
+    double pstar, ipl, ipr;
+    if constexpr (GN > 0) {  // 2 gamma/(gamma-1) = n + 2; 1/p = (p^-1/(n+2))^(n+2)
+      pstar = ipow_c<GN + 2>(base);
+      ipl = ipow_c<GN + 2>(XL[3]);
+      ipr = ipow_c<GN + 2>(XR[3]);
+    } else {
+      pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
+      ipl = 1.0 / pl;
+      ipr = 1.0 / pr;
+    }
     const double fac = (g + 1.0) / (2.0 * g);
-    const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) / pl);
-    const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) / pr);
+    const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) * ipl);
+    const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) * ipr);
     return fmax(fmax(-lam_l, 0.0), fmax(lam_r, 0.0));
   }
 }
@@ -220,7 +226,7 @@ struct PhiVal {
   double rho, phi, dphi;
 };
 
-template <int DIM>
+template <int DIM, int GN>
 __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, double kmin,
                                 const Phys& ph) {
   PhiVal r;
@@ -231,7 +237,15 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
     return r;
   }
   const double g = ph.gamma;
-  const double rinv = 1.0 / r.rho;
+  double rinv, rg;
+  if constexpr (GN > 0) {  // z = rho^(-1/n): 1/rho = z^n, rho^gamma = rho^2 z^(n-2)
+    const double z = inv_root<GN>(r.rho);
+    rinv = ipow_c<GN>(z);
+    rg = (r.rho * r.rho) * ipow_c<GN - 2>(z);
+  } else {
+    rinv = 1.0 / r.rho;
+    rg = pow(r.rho, g);
+  }
   double mm = 0.0, mp = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -240,7 +254,6 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
     mp += m * P[1 + k];
   }
   const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
-  const double rg = rho_pow_gamma(r.rho, ph);
   const double kg = kmin / (g - 1.0);
   r.phi = E - 0.5 * mm * rinv - kg * rg;
   r.dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
@@ -255,10 +268,10 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
 // from the last infeasible point to the nearest feasible one.  The result
 // is feasible and within a few rounding widths of the supremum.
 // Called for a partial state that is admissible at t = 0 and not at t = T.
-template <int DIM>
+template <int DIM, int GN>
 __device__ double entropy_root(const double* uL, const double* P, double T, double kmin,
                                const Phys& ph) {
-  PhiVal er = phi_at<DIM>(T, uL, P, kmin, ph);
+  PhiVal er = phi_at<DIM, GN>(T, uL, P, kmin, ph);
   double tl = 0.0, tr = T;
   bool done = false;
   for (int it = 0; it < 64; ++it) {
@@ -273,7 +286,7 @@ __device__ double entropy_root(const double* uL, const double* P, double T, doub
         done = true;
         break;
       }
-      const PhiVal en = phi_at<DIM>(tn, uL, P, kmin, ph);
+      const PhiVal en = phi_at<DIM, GN>(tn, uL, P, kmin, ph);
       if (en.rho > 0.0 && en.phi >= 0.0) {
         tl = tn;  // a tangent step lands feasible only within rounding of the root
         done = true;
@@ -285,7 +298,7 @@ __device__ double entropy_root(const double* uL, const double* P, double T, doub
       if (step <= 1e-14) break;
     } else {  // no usable tangent (density not positive at tr): bisect
       const double tn = 0.5 * (tl + tr);
-      const PhiVal en = phi_at<DIM>(tn, uL, P, kmin, ph);
+      const PhiVal en = phi_at<DIM, GN>(tn, uL, P, kmin, ph);
       if (en.rho > 0.0 && en.phi >= 0.0) {
         tl = tn;
       } else {
@@ -299,7 +312,7 @@ __device__ double entropy_root(const double* uL, const double* P, double T, doub
     for (int j = 0; j < 64; ++j) {
       const double tb = tr - d;
       if (!(tb > tl)) break;
-      const PhiVal eb = phi_at<DIM>(tb, uL, P, kmin, ph);
+      const PhiVal eb = phi_at<DIM, GN>(tb, uL, P, kmin, ph);
       if (eb.rho > 0.0 && eb.phi >= 0.0) {
         tl = tb;
         break;
@@ -355,9 +368,9 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
     double U[NC], X[C::NAUX > 0 ? C::NAUX : 1];
 #pragma unroll
     for (int c = 0; c < NC; ++c) U[c] = lds[C::A_U + c * EPB * NS + t];
-    if constexpr (EQ == EQ_EULER) {
+    if constexpr (is_euler(EQ)) {
       bool b;
-      euler_aux<DIM, FLUX>(U, ph, X, b);
+      euler_aux<DIM, gn_of(EQ), FLUX>(U, ph, X, b);
       bad |= b;
 #pragma unroll
       for (int q = 0; q < (FLUX ? C::NAUX : C::NAUX - 1); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
@@ -385,9 +398,13 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
 
 // copy the per-degree tables into LDS
 template <int P>
-__device__ inline void load_tables(double* sw, double* sq, const Tables& T, int nthreads) {
+__device__ inline void load_tables(double* sw, double* sq, double* siw, const Tables& T,
+                                   int nthreads) {
   constexpr int N1 = P + 1;
-  for (int t = threadIdx.x; t < N1; t += nthreads) sw[t] = T.w[t];
+  for (int t = threadIdx.x; t < N1; t += nthreads) {
+    sw[t] = T.w[t];
+    siw[t] = T.iw[t];
+  }
   for (int t = threadIdx.x; t < P * N1; t += nthreads) sq[t] = T.Q[t];
 }
 
@@ -411,7 +428,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
   double dt = S.dt_dev ? S.dt_scale * S.dt_dev[0] : S.dt;
   if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
 
-  load_tables<P>(lds + C::S_W, lds + C::S_Q, A.T, C::BS);
+  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, A.T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
   load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
@@ -460,7 +477,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
       for (int c = 0; c < NC; ++c) rFL[it][c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
       const double avg = 0.5 * (UL[0] + UR[0]);
       rUB[it] = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
-      if constexpr (EQ == EQ_EULER) rKF[it] = fmin(XL[4], XR[4]);
+      if constexpr (is_euler(EQ)) rKF[it] = fmin(XL[4], XR[4]);
       if (f >= 1 && f <= P) {
         const double sc = DIM == 2 ? lds[C::S_W + l] * (k == 0 ? S.hy : S.hx) : 1.0;
         const double* q = lds + C::S_Q + (f - 1) * N1;
@@ -491,7 +508,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         lds[C::B_RB + (k * NC + c) * EPB * NF + o] = rRB[it][c];
       }
       lds[C::B_UB + k * EPB * NF + o] = rUB[it];
-      if constexpr (EQ == EQ_EULER) lds[C::B_KF + k * EPB * NF + o] = rKF[it];
+      if constexpr (is_euler(EQ)) lds[C::B_KF + k * EPB * NF + o] = rKF[it];
     }
   }
   __syncthreads();
@@ -510,12 +527,15 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
   }
   bool lov = false;
   double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
+  const double idt = dt > 0.0 ? 1.0 / dt : 0.0;
+  double dtm = 0.0;
   if (own) {
     const double wa = lds[C::S_W + a];
     const double wb = DIM == 2 ? lds[C::S_W + b] : 1.0;
     m = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
-    const double cx = dt / (wa * S.hx);
-    const double cy = DIM == 2 ? dt / (wb * S.hy) : 0.0;
+    const double cx = dt * (lds[C::S_IW + a] * S.ihx);
+    const double cy = DIM == 2 ? dt * (lds[C::S_IW + b] * S.ihy) : 0.0;
+    dtm = DIM == 2 ? cx * (lds[C::S_IW + b] * S.ihy) : cx;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double d = (lds[C::B_FL + c * EPB * NF + fl[0]] - lds[C::B_FL + c * EPB * NF + fr[0]]) * cx;
@@ -547,7 +567,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         Pp += fmax(cp, 0.0) + fmax(cm, 0.0);
         Pm += fmin(cp, 0.0) + fmin(cm, 0.0);
       }
-      const double mdt = m / dt;
+      const double mdt = m * idt;
       const double Qp = fmax(0.0, mdt * (umax - uL[0]));
       const double Qm = fmin(0.0, mdt * (umin - uL[0]));
       const double Rp = Pp == 0.0 ? 1.0 : fmin(1.0, Qp / Pp);
@@ -555,7 +575,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
       alpha = fmin(Rp, Rm);
       alpha = alpha > 0.0 ? alpha : 0.0;  // no negative zero: alpha is ordered as a u64 below
       az_dbg = alpha;
-      if constexpr (EQ == EQ_EULER) {
+      if constexpr (is_euler(EQ)) {
         // every partial state uL + t 2d dt/m (+-rbar) must stay admissible
         // for t <= alpha (eq. convex-provisional); faces whose partial
         // state fails at t = alpha go to the workgroup's search list
@@ -564,7 +584,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         for (int k = 0; k < DIM; ++k)
           kmin = fmin(kmin, fmin(lds[C::B_KF + k * EPB * NF + fl[k]], lds[C::B_KF + k * EPB * NF + fr[k]]));
         kmin_dbg = kmin;
-        const double g2 = 2.0 * DIM * dt / m;
+        const double g2 = 2.0 * DIM * dtm;
         int act = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -581,14 +601,14 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
               Pv[c] = g2 * cf;
             }
             if (nz) {
-              const PhiVal e = phi_at<DIM>(alpha, uL, Pv, kmin, ph_of(A));
+              const PhiVal e = phi_at<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ph_of(A));
               if (!(e.rho > 0.0 && e.phi >= 0.0)) act |= 1 << (2 * k + sd);
             }
           }
         }
         if (act) {
           const double zero[NC] = {};
-          const PhiVal e0 = phi_at<DIM>(0.0, uL, zero, kmin, ph_of(A));
+          const PhiVal e0 = phi_at<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ph_of(A));
           if (!(e0.rho > 0.0 && e0.phi >= 0.0)) {  // u^L itself off the set by rounding
             alpha = 0.0;
             act = 0;
@@ -609,7 +629,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
     }
     lds[C::S_AL + tid] = alpha;
   }
-  if constexpr (EQ == EQ_EULER) {
+  if constexpr (is_euler(EQ)) {
     __syncthreads();
     // ---- phase 4b: entropy line searches, spread over the workgroup ----
     const int nact = *reinterpret_cast<const int*>(lds + C::S_LN);
@@ -620,10 +640,8 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
       const int nle = node / NP, ns = node - nle * NP;
       const int na = DIM == 2 ? ns % N1 : ns;
       const int nb = DIM == 2 ? ns / N1 : 0;
-      const double wa = lds[C::S_W + na];
-      const double wb = DIM == 2 ? lds[C::S_W + nb] : 1.0;
-      const double mm = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
-      const double g2 = 2.0 * DIM * dt / mm;
+      const double cxn = dt * (lds[C::S_IW + na] * S.ihx);
+      const double g2 = 2.0 * DIM * (DIM == 2 ? cxn * (lds[C::S_IW + nb] * S.ihy) : cxn);
       const int fidx = k == 0 ? nle * NF + nb * NFL + na + sd : nle * NF + na * NFL + nb + sd;
       double ul[NC], Pv[NC];
 #pragma unroll
@@ -631,7 +649,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         ul[c] = lds[C::C_UL + c * EPB * NP + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
       }
-      const double t = entropy_root<DIM>(ul, Pv, lds[C::C_AZ + node], lds[C::C_KM + node], ph_of(A));
+      const double t = entropy_root<DIM, gn_of(EQ)>(ul, Pv, lds[C::C_AZ + node], lds[C::C_KM + node], ph_of(A));
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
     }
@@ -643,7 +661,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
   if (own) {
     alpha = lds[C::S_AL + tid];
     limited = alpha < 1.0;
-    ent = EQ == EQ_EULER && A.limiter == LIM_SUBCELL && alpha < az_dbg;
+    ent = is_euler(EQ) && A.limiter == LIM_SUBCELL && alpha < az_dbg;
     if (A.trace) {
       const long long g = (long long)e0 * NP + tid;
       A.trace[g] = umin;
@@ -670,7 +688,6 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
         for (int c = 0; c < NC; ++c) corr[c] -= am * lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
       }
     }
-    const double dtm = dt / m;
     const long long g = (long long)e0 * NP + tid;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {

@@ -258,3 +258,17 @@ def test_limiter_intermediates_match_oracle(wl):
     np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
     assert (tr["alpha"] < 1).any()
     sv.close()
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.3], ids=["gamma5/3", "gamma1.3"])
+@pytest.mark.parametrize("dim,p", [(1, 3), (2, 2), (2, 4), (2, 7)])
+def test_stage_parity_other_gamma(gamma, dim, p):
+    """The gamma = 5/3 instantiation (integer powers of rho^-1/3) and the
+    generic-gamma one (pow)."""
+    rng = np.random.default_rng(7 * p + dim)
+    if dim == 1:
+        prob = W.Problem(dim=1, nx=9, ny=1, p=p, eq=W.EULER, gamma=gamma)
+    else:
+        prob = W.Problem(dim=2, nx=6, ny=5, p=p, eq=W.EULER, gamma=gamma)
+    u = W.euler_quadrants(prob, rng)
+    stage_parity(prob, u, 0.5 * oracle.max_dt(prob, u))
