@@ -157,6 +157,45 @@ int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out);
  * NULL).  Never NULL. */
 const char* idp_dg_last_error(const idp_dg* h);
 
+/* ------------------------------------------------------------------ */
+/* Batched execution: many independent solves of uneven mesh size and  */
+/* degree advance together, one persistent launch per RK stage over a  */
+/* work list of (solve, element tile) items.                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct idp_dg_batch idp_dg_batch;
+
+/* Group n >= 1 distinct handles for batched stepping on hip_stream.  The
+ * handles are borrowed (they must outlive the batch) and must share the
+ * equation, dimension, gamma kind (7/5, 5/3 or other) and device, and have
+ * p >= 2; mesh size, p, limiter mode and velocity may differ.  Each solve keeps using
+ * its handle's stage buffers and diagnostics. */
+int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream,
+                        idp_dg_batch** out);
+void idp_dg_batch_destroy(idp_dg_batch* b);
+
+/* Work items (element tiles over all solves) of one batched launch. */
+int idp_dg_batch_num_items(const idp_dg_batch* b);
+
+/* One SSP-RK3 step of every solve i: u[i] (device, in place, layout as for
+ * idp_dg_stage) advanced by dt[i] (host array of n values >= 0).  The
+ * result of each solve is bitwise identical to idp_dg_step on its own.
+ * States must not overlap each other or any solve's stage buffers. */
+int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt);
+
+/* One step of every solve with dt_i = cfl * (CFL bound of u[i]) computed
+ * on the device; the five launches replay from a HIP graph cached for the
+ * pointer set and cfl.  Bitwise identical to idp_dg_step_cfl per solve. */
+int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl);
+
+/* The n time steps used by the last idp_dg_batch_step_cfl (host array;
+ * synchronises the stream). */
+int idp_dg_batch_last_dt(idp_dg_batch* b, double* dt);
+
+/* Message of the last failure on b (or of the last failed batch create
+ * when b is NULL).  Never NULL. */
+const char* idp_dg_batch_last_error(const idp_dg_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

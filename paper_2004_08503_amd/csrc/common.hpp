@@ -48,6 +48,7 @@ struct Solve {
   const double* dt_dev; // when non-null: dt = dt_scale * dt_dev[0]
   double dt, dt_scale;
   long long nn;         // nodes
+  int p;                // polynomial degree
   int nx, ny, ne;       // elements
   int ntiles;           // element tiles of this solve
   double hx, hy;
@@ -69,10 +70,27 @@ struct MaxDtArgs {
   const double* u;
   double* partial;           // one minimum per workgroup
   long long nn;
+  int p;
   int nx, ny, ne, ntiles;
   double hx, hy;
   Phys ph;
   Tables T;
+};
+
+// Batched execution: a work list of (solve, tile) items split into eight
+// contiguous chunks, one per XCD (workgroup b runs on XCD b mod 8).
+struct BatchArgs {
+  const StageArgs* args;     // per solve (this stage's pointers and dt)
+  const int* item_solve;
+  const int* item_tile;
+  int chunk[9];
+};
+struct BatchDtArgs {
+  const MaxDtArgs* args;     // per solve
+  const int* item_solve;
+  const int* item_tile;
+  double* partial;           // one minimum per item
+  int chunk[9];
 };
 
 // Kernel launchers, one translation unit per (equation, dimension).
@@ -82,7 +100,12 @@ struct MaxDtArgs {
                                  hipStream_t s);                                  \
   hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s);       \
   int tile_elems_##NAME(int p, int variant);                                      \
-  int num_variants_##NAME(int p);
+  int num_variants_##NAME(int p);                                                 \
+  hipError_t launch_batch_stage_##NAME(const BatchArgs& b, int grid, int lds, hipStream_t s); \
+  hipError_t launch_batch_maxdt_##NAME(const BatchDtArgs& b, int grid, int lds, hipStream_t s); \
+  int batch_tile_elems_##NAME(int p);                                             \
+  int batch_lds_bytes_##NAME(int p);                                              \
+  int batch_blocks_per_cu_##NAME(int lds);
 
 IDP_DECLARE_LAUNCHERS(adv1)
 IDP_DECLARE_LAUNCHERS(adv2)
@@ -97,5 +120,7 @@ IDP_DECLARE_LAUNCHERS(euler75_2)
 
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);
+// per solve s: min over partial[begin[s]..begin[s+1]) -> out[s] (one workgroup per solve)
+__global__ void segmented_min_kernel(const double* partial, const int* begin, double* out);
 
 }  // namespace idp

@@ -1,0 +1,53 @@
+// Private host-side definitions shared by the translation units of the
+// runtime (plain and batched paths).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/idp_dg.h"
+#include "common.hpp"
+
+using idp::Tables;
+using idp::Phys;
+using idp::Diag;
+
+struct idp_dg {
+  idp_dg_desc d{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nc = 1;
+  long long nn = 0;
+  int ne = 0;
+  int variant = 0;
+  int kcode = 0;   // kernel equation code (EQ_*), Euler split by gamma
+  Tables T{};
+  Phys ph{};
+  double* buf1 = nullptr;   // stage buffers of idp_dg_step
+  double* buf2 = nullptr;
+  Diag* diag = nullptr;
+  double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
+  double* partial = nullptr;   // per-workgroup minima of the time-step kernel
+  // cached graph of one device-timestepped step
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* g_u = nullptr;
+  double g_cfl = 0.0;
+  std::string err = "no error";
+};
+
+
+namespace idp_host {
+int family(const idp_dg* h);
+int tile_elems(const idp_dg* h);
+idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s, double* u_out,
+                               double dt, const double* dt_dev, double dt_scale, int stage);
+idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
+int fail(idp_dg* h, int code, const std::string& msg);
+hipError_t launch_batch_stage(int fam, const idp::BatchArgs& b, int grid, int lds, hipStream_t s);
+hipError_t launch_batch_maxdt(int fam, const idp::BatchDtArgs& b, int grid, int lds, hipStream_t s);
+int batch_tile_elems(int fam, int p);
+int batch_lds_bytes(int fam, int p);
+int batch_blocks_per_cu(int fam, int lds);
+}  // namespace idp_host

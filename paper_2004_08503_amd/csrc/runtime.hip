@@ -14,6 +14,7 @@
 
 #include "../../include/idp_dg.h"
 #include "common.hpp"
+#include "handle.hpp"
 
 using namespace idp;
 
@@ -89,32 +90,7 @@ void gl_tables(int p, double* xi01, double* w01, double* D) {
 
 }  // namespace
 
-struct idp_dg {
-  idp_dg_desc d{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int nc = 1;
-  long long nn = 0;
-  int ne = 0;
-  int variant = 0;
-  int kcode = 0;   // kernel equation code (EQ_*), Euler split by gamma
-  Tables T{};
-  Phys ph{};
-  double* buf1 = nullptr;   // stage buffers of idp_dg_step
-  double* buf2 = nullptr;
-  Diag* diag = nullptr;
-  double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
-  double* partial = nullptr;   // per-workgroup minima of the time-step kernel
-  // cached graph of one device-timestepped step
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  double* g_u = nullptr;
-  double g_cfl = 0.0;
-  std::string err = "no error";
-};
-
-namespace {
+namespace idp_host {
 
 int fail(idp_dg* h, int code, const std::string& msg) {
   if (h) h->err = msg; else g_create_error = msg;
@@ -211,6 +187,7 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.S.dt = dt;
   a.S.dt_scale = dt_scale;
   a.S.nn = h->nn;
+  a.S.p = h->d.p;
   a.S.nx = h->d.nx;
   a.S.ny = h->d.ny;
   a.S.ne = h->ne;
@@ -235,6 +212,7 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   a.u = u;
   a.partial = h->partial;
   a.nn = h->nn;
+  a.p = h->d.p;
   a.nx = h->d.nx;
   a.ny = h->d.ny;
   a.ne = h->ne;
@@ -245,6 +223,92 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   a.T = h->T;
   return a;
 }
+
+hipError_t launch_batch_stage(int fam, const BatchArgs& b, int grid, int lds, hipStream_t s) {
+  switch (fam) {
+    case 0: return launch_batch_stage_adv1(b, grid, lds, s);
+    case 1: return launch_batch_stage_adv2(b, grid, lds, s);
+    case 2: return launch_batch_stage_burg1(b, grid, lds, s);
+    case 3: return launch_batch_stage_burg2(b, grid, lds, s);
+    case 4: return launch_batch_stage_euler1(b, grid, lds, s);
+    case 5: return launch_batch_stage_euler2(b, grid, lds, s);
+    case 6: return launch_batch_stage_euler53_1(b, grid, lds, s);
+    case 7: return launch_batch_stage_euler53_2(b, grid, lds, s);
+    case 8: return launch_batch_stage_euler75_1(b, grid, lds, s);
+    case 9: return launch_batch_stage_euler75_2(b, grid, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_maxdt(int fam, const BatchDtArgs& b, int grid, int lds, hipStream_t s) {
+  switch (fam) {
+    case 0: return launch_batch_maxdt_adv1(b, grid, lds, s);
+    case 1: return launch_batch_maxdt_adv2(b, grid, lds, s);
+    case 2: return launch_batch_maxdt_burg1(b, grid, lds, s);
+    case 3: return launch_batch_maxdt_burg2(b, grid, lds, s);
+    case 4: return launch_batch_maxdt_euler1(b, grid, lds, s);
+    case 5: return launch_batch_maxdt_euler2(b, grid, lds, s);
+    case 6: return launch_batch_maxdt_euler53_1(b, grid, lds, s);
+    case 7: return launch_batch_maxdt_euler53_2(b, grid, lds, s);
+    case 8: return launch_batch_maxdt_euler75_1(b, grid, lds, s);
+    case 9: return launch_batch_maxdt_euler75_2(b, grid, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int batch_tile_elems(int fam, int p) {
+  switch (fam) {
+    case 0: return batch_tile_elems_adv1(p);
+    case 1: return batch_tile_elems_adv2(p);
+    case 2: return batch_tile_elems_burg1(p);
+    case 3: return batch_tile_elems_burg2(p);
+    case 4: return batch_tile_elems_euler1(p);
+    case 5: return batch_tile_elems_euler2(p);
+    case 6: return batch_tile_elems_euler53_1(p);
+    case 7: return batch_tile_elems_euler53_2(p);
+    case 8: return batch_tile_elems_euler75_1(p);
+    case 9: return batch_tile_elems_euler75_2(p);
+  }
+  return 1;
+}
+
+int batch_lds_bytes(int fam, int p) {
+  switch (fam) {
+    case 0: return batch_lds_bytes_adv1(p);
+    case 1: return batch_lds_bytes_adv2(p);
+    case 2: return batch_lds_bytes_burg1(p);
+    case 3: return batch_lds_bytes_burg2(p);
+    case 4: return batch_lds_bytes_euler1(p);
+    case 5: return batch_lds_bytes_euler2(p);
+    case 6: return batch_lds_bytes_euler53_1(p);
+    case 7: return batch_lds_bytes_euler53_2(p);
+    case 8: return batch_lds_bytes_euler75_1(p);
+    case 9: return batch_lds_bytes_euler75_2(p);
+  }
+  return -1;
+}
+
+int batch_blocks_per_cu(int fam, int lds) {
+  switch (fam) {
+    case 0: return batch_blocks_per_cu_adv1(lds);
+    case 1: return batch_blocks_per_cu_adv2(lds);
+    case 2: return batch_blocks_per_cu_burg1(lds);
+    case 3: return batch_blocks_per_cu_burg2(lds);
+    case 4: return batch_blocks_per_cu_euler1(lds);
+    case 5: return batch_blocks_per_cu_euler2(lds);
+    case 6: return batch_blocks_per_cu_euler53_1(lds);
+    case 7: return batch_blocks_per_cu_euler53_2(lds);
+    case 8: return batch_blocks_per_cu_euler75_1(lds);
+    case 9: return batch_blocks_per_cu_euler75_2(lds);
+  }
+  return 1;
+}
+
+}  // namespace idp_host
+
+using namespace idp_host;
+
+namespace {
 
 bool overlaps(const double* a, const double* b, long long n) {
   return a < b + n && b < a + n;
@@ -282,6 +346,18 @@ hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
 }  // namespace
 
 namespace idp {
+__global__ __launch_bounds__(256) void segmented_min_kernel(const double* partial, const int* begin,
+                                                             double* out) {
+  __shared__ double red[4];
+  const int s = blockIdx.x;
+  double v = INFINITY;
+  for (int i = begin[s] + threadIdx.x; i < begin[s + 1]; i += 256) v = fmin(v, partial[i]);
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[s] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
 __global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial, int n, double* out) {
   __shared__ double red[16];
   double v = INFINITY;

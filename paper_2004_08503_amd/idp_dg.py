@@ -54,6 +54,13 @@ def _declare(lib):
         "idp_dg_stage_dt": (ctypes.c_int, [H, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
+        "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
+        "idp_dg_batch_destroy": (None, [H]),
+        "idp_dg_batch_num_items": (ctypes.c_int, [H]),
+        "idp_dg_batch_step": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_double)]),
+        "idp_dg_batch_step_cfl": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.c_double]),
+        "idp_dg_batch_last_dt": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
+        "idp_dg_batch_last_error": (ctypes.c_char_p, [H]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -201,3 +208,55 @@ class Solver:
         self._check(lib.idp_dg_diagnostics(self._h, ctypes.byref(d)))
         return {"limited_nodes": d.limited_nodes, "entropy_nodes": d.entropy_nodes,
                 "bad_input": bool(d.bad_input), "low_order_violation": bool(d.low_order_violation)}
+
+
+class Batch:
+    """Many solves of one equation family stepped together: one persistent
+    launch per RK stage over all their element tiles."""
+
+    def __init__(self, solvers, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.solvers = list(solvers)
+        self.n = len(self.solvers)
+        hs = (ctypes.c_void_p * self.n)(*[s.handle for s in self.solvers])
+        self._b = ctypes.c_void_p()
+        rc = lib.idp_dg_batch_create(hs, self.n, ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(self._b))
+        if rc:
+            raise IdpError(rc, lib.idp_dg_batch_last_error(None).decode())
+        self.num_items = lib.idp_dg_batch_num_items(self._b)
+
+    def close(self):
+        if self._b:
+            lib.idp_dg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise IdpError(rc, lib.idp_dg_batch_last_error(self._b).decode())
+
+    def _ptrs(self, us):
+        if len(us) != self.n:
+            raise ValueError("need %d states" % self.n)
+        return (ctypes.c_void_p * self.n)(*[s._ptr(u, "u[%d]" % i).value
+                                            for i, (s, u) in enumerate(zip(self.solvers, us))])
+
+    def step(self, us, dts):
+        d = (ctypes.c_double * self.n)(*[float(x) for x in dts])
+        self._check(lib.idp_dg_batch_step(self._b, self._ptrs(us), d))
+
+    def step_cfl(self, us, cfl):
+        self._check(lib.idp_dg_batch_step_cfl(self._b, self._ptrs(us), float(cfl)))
+
+    def last_dt(self):
+        d = (ctypes.c_double * self.n)()
+        self._check(lib.idp_dg_batch_last_dt(self._b, d))
+        return list(d)
