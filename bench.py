@@ -66,6 +66,66 @@ def cpu_baseline(wl, dt):
                       "state on the host, %.1f s" % el}
 
 
+def batched_leg(steps, count=64):
+    """The batched workload: `count` independent Euler solves (n in
+    [32, 256], p in {2..6}, seeded quadrant data), stepped (a) one solve per
+    launch, each through its own cached graph, and (b) all together, one
+    persistent launch per stage through one cached graph.  Per-round (one
+    step of every solve) latencies from HIP events."""
+    import torch
+    from paper_2004_08503_amd import idp_dg, workloads as W
+
+    mix = W.batch_mix(count)
+    solvers = [idp_dg.Solver(w.prob) for w in mix]
+    u_plain = [torch.from_numpy(w.u0).to("cuda") for w in mix]
+    u_batch = [t.clone() for t in u_plain]
+    nodes = sum(w.prob.num_nodes for w in mix)
+    batch = idp_dg.Batch(solvers)
+    n_items = batch.num_items
+    stream = torch.cuda.current_stream()
+
+    def run(fn, k):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in evs:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return el, np.array([a.elapsed_time(b) for a, b in evs])
+
+    def plain_round():
+        for sv, u in zip(solvers, u_plain):
+            sv.step_cfl(u, 0.5)
+
+    def batch_round():
+        batch.step_cfl(u_batch, 0.5)
+
+    for _ in range(2):
+        plain_round()
+        batch_round()
+    el_p, ms_p = run(plain_round, steps)
+    el_b, ms_b = run(batch_round, steps)
+    same = all(torch.equal(a, b) for a, b in zip(u_plain, u_batch))
+    batch.close()
+    for sv in solvers:
+        sv.close()
+    return {
+        "workload": "euler_2d_batch_%d_solves_n32-256_p2-6" % count,
+        "solves": count, "nodes": nodes, "work_items": n_items,
+        "value": 3 * nodes * steps / el_b, "unit": "DOF-updates/s",
+        "plain_value": 3 * nodes * steps / el_p,
+        "speedup_vs_plain": el_p / el_b,
+        "round_ms_p50": float(np.percentile(ms_b, 50)), "round_ms_p99": float(np.percentile(ms_b, 99)),
+        "plain_round_ms_p50": float(np.percentile(ms_p, 50)),
+        "plain_round_ms_p99": float(np.percentile(ms_p, 99)),
+        "steps": steps, "bitwise_equal_to_plain": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +134,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="elements per direction")
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-solve leg")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (4 times), the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -178,6 +240,10 @@ def main():
                      "kernel": "stage_kernel<EULER75,2,4,5>",
                      "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn)},
     }
+    sv.close()
+    del u, b1, b2
+    if not args.no_batch:
+        out["batched"] = batched_leg(args.batch_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, dt_last)
     print(json.dumps(out))

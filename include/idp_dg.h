@@ -159,16 +159,18 @@ const char* idp_dg_last_error(const idp_dg* h);
 
 /* ------------------------------------------------------------------ */
 /* Batched execution: many independent solves of uneven mesh size and  */
-/* degree advance together, one persistent launch per RK stage over a  */
-/* work list of (solve, element tile) items.                           */
+/* degree advance together.  Per degree present, one work-list launch  */
+/* per RK stage covers the element tiles of all solves of that degree; */
+/* a step is one HIP graph whose degree groups run as parallel         */
+/* branches.                                                           */
 /* ------------------------------------------------------------------ */
 
 typedef struct idp_dg_batch idp_dg_batch;
 
 /* Group n >= 1 distinct handles for batched stepping on hip_stream.  The
  * handles are borrowed (they must outlive the batch) and must share the
- * equation, dimension, gamma kind (7/5, 5/3 or other) and device, and have
- * p >= 2; mesh size, p, limiter mode and velocity may differ.  Each solve keeps using
+ * equation, dimension, gamma kind (7/5, 5/3 or other) and device; mesh
+ * size, p, limiter mode and velocity may differ.  Each solve keeps using
  * its handle's stage buffers and diagnostics. */
 int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream,
                         idp_dg_batch** out);
@@ -184,7 +186,7 @@ int idp_dg_batch_num_items(const idp_dg_batch* b);
 int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt);
 
 /* One step of every solve with dt_i = cfl * (CFL bound of u[i]) computed
- * on the device; the five launches replay from a HIP graph cached for the
+ * on the device; the launches replay from a HIP graph cached for the
  * pointer set and cfl.  Bitwise identical to idp_dg_step_cfl per solve. */
 int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl);
 

@@ -1,15 +1,17 @@
 // Batched execution: many independent solves of one equation family (any
-// mix of mesh sizes and degrees) advance together.  Every RK stage is one
-// persistent launch over a work list of (solve, tile) items; the work list
-// is cut into eight contiguous chunks, one per XCD, so that each XCD sweeps
-// the tiles of a few solves in order and their face traces stay in its L2.
-// The time-step bounds of all solves come from one persistent launch plus a
-// segmented minimum.  A device-timestepped batched step is captured once in
-// a HIP graph per (pointer set, cfl) and replayed.
+// mix of mesh sizes and degrees) advance together.  The solves are grouped
+// by degree; each group has a work list of (solve, element tile) items over
+// all its solves and one work-list kernel per RK stage (the plain path's
+// tile shape, mapped XCD-aware over the list).  A batched step is one HIP
+// graph, built once per (pointer set, time-step mode, cfl): the groups'
+// kernels of a stage are parallel branches, the stages follow each other,
+// and in the device-timestepped mode the groups' time-step kernels and one
+// segmented minimum come first.  Host time steps reach the device through
+// a pinned ring before the graph launch.
 //
 // Results are bitwise identical to the plain path: a tile's arithmetic does
-// not depend on how many elements share its workgroup, and the only
-// reductions (alpha over faces, dt over nodes) are minima.
+// not depend on which workgroup or launch runs it, and the only reductions
+// (alpha over faces, dt over nodes) are minima.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,21 +31,26 @@ namespace {
 constexpr int kRing = 32;  // pinned staging slots for host time steps
 }
 
+struct BatchGroup {
+  int p = 0;
+  BatchKernels k{};
+  int nitems = 0;
+  int ofs = 0;        // first item of the group in the item arrays / partials
+};
+
 struct idp_dg_batch {
   std::vector<idp_dg*> s;
   hipStream_t stream = nullptr;
   int fam = 0;
   int n = 0;
   int nitems = 0;
-  int grid = 8;
-  int lds = 0;   // dynamic LDS bytes of the persistent kernels
-  int chunk[9] = {};
+  std::vector<BatchGroup> groups;
   // device
   StageArgs* d_args = nullptr;     // [3][n]
   MaxDtArgs* d_dtargs = nullptr;   // [n]
-  int* d_item_solve = nullptr;
+  int* d_item_solve = nullptr;     // [nitems], grouped by degree
   int* d_item_tile = nullptr;
-  int* d_begin = nullptr;          // [n+1]
+  int* d_range = nullptr;          // [2n] item range of each solve
   double* d_partial = nullptr;     // [nitems]
   double* d_dt = nullptr;          // [0,n) host time steps, [n,2n) device bounds
   // host mirrors of what d_args / d_dtargs hold
@@ -56,8 +63,7 @@ struct idp_dg_batch {
   double* h_ring = nullptr;
   hipEvent_t ring_ev[kRing] = {};
   int ring_next = 0;
-  // graph of one device-timestepped step
-  hipStream_t cap = nullptr;
+  // graph of one step in the current mode
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err = "no error";
@@ -117,34 +123,76 @@ int set_args(idp_dg_batch* b, double* const* u, double* dt_dev, double dt_scale,
   return 0;
 }
 
-BatchArgs stage_args_of(const idp_dg_batch* b, int stage) {
-  BatchArgs a;
-  a.args = b->d_args + stage * b->n;
-  a.item_solve = b->d_item_solve;
-  a.item_tile = b->d_item_tile;
-  for (int x = 0; x < 9; ++x) a.chunk[x] = b->chunk[x];
-  return a;
+hipError_t add_kernel(hipGraph_t g, hipGraphNode_t* node, const std::vector<hipGraphNode_t>& deps,
+                      const void* func, dim3 grid, dim3 block, void** args) {
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(func);
+  kp.gridDim = grid;
+  kp.blockDim = block;
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
 }
 
-hipError_t enqueue_batch_stages(const idp_dg_batch* b, hipStream_t s) {
-  for (int st = 0; st < 3; ++st) {
-    hipError_t e = launch_batch_stage(b->fam, stage_args_of(b, st), b->grid, b->lds, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t enqueue_batch_maxdt(const idp_dg_batch* b, double* out, hipStream_t s) {
-  BatchDtArgs a;
-  a.args = b->d_dtargs;
-  a.item_solve = b->d_item_solve;
-  a.item_tile = b->d_item_tile;
-  a.partial = b->d_partial;
-  for (int x = 0; x < 9; ++x) a.chunk[x] = b->chunk[x];
-  hipError_t e = launch_batch_maxdt(b->fam, a, b->grid, b->lds, s);
+// One batched step as a graph: [time-step kernels of every group ->
+// segmented min ->] stage 0 of every group -> stage 1 -> stage 2.
+hipError_t build_graph(idp_dg_batch* b, bool device_dt) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(segmented_min_kernel, dim3(b->n), dim3(256), 0, s, b->d_partial, b->d_begin, out);
-  return hipGetLastError();
+  std::vector<hipGraphNode_t> prev;
+  if (device_dt) {
+    std::vector<hipGraphNode_t> dts;
+    for (const BatchGroup& gr : b->groups) {
+      BatchDtArgs a;
+      a.args = b->d_dtargs;
+      a.item_solve = b->d_item_solve + gr.ofs;
+      a.item_tile = b->d_item_tile + gr.ofs;
+      a.partial = b->d_partial + gr.ofs;
+      a.nitems = gr.nitems;
+      void* args[] = {&a};
+      hipGraphNode_t nd;
+      e = add_kernel(g, &nd, {}, gr.k.maxdt, dim3(gr.nitems), dim3(gr.k.block), args);
+      if (e != hipSuccess) break;
+      dts.push_back(nd);
+    }
+    if (e == hipSuccess) {
+      const double* part = b->d_partial;
+      const int* range = b->d_range;
+      double* out = b->d_dt + b->n;
+      void* args[] = {&part, &range, &out};
+      hipGraphNode_t nd;
+      e = add_kernel(g, &nd, dts, reinterpret_cast<const void*>(&segmented_min_kernel), dim3(b->n),
+                     dim3(256), args);
+      prev.assign(1, nd);
+    }
+  }
+  for (int st = 0; st < 3 && e == hipSuccess; ++st) {
+    std::vector<hipGraphNode_t> cur;
+    for (const BatchGroup& gr : b->groups) {
+      BatchArgs a;
+      a.args = b->d_args + st * b->n;
+      a.item_solve = b->d_item_solve + gr.ofs;
+      a.item_tile = b->d_item_tile + gr.ofs;
+      a.nitems = gr.nitems;
+      void* args[] = {&a};
+      hipGraphNode_t nd;
+      e = add_kernel(g, &nd, prev, gr.k.stage, dim3(gr.nitems), dim3(gr.k.block), args);
+      if (e != hipSuccess) break;
+      cur.push_back(nd);
+    }
+    prev.swap(cur);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    b->exec = nullptr;
+    return e;
+  }
+  b->graph = g;
+  return hipSuccess;
 }
 
 int check_states(idp_dg_batch* b, double* const* u) {
@@ -183,40 +231,36 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_b
   for (int i = 1; i < n; ++i)
     if (family(solves[i]) != fam || solves[i]->device != solves[0]->device)
       return bfail(nullptr, IDP_DG_EINVAL, "solves of one batch must share equation, gamma kind, dimension and device");
-  int lds = 0;
-  for (int i = 0; i < n; ++i) {
-    const int l = batch_lds_bytes(fam, solves[i]->d.p);
-    if (l < 0) return bfail(nullptr, IDP_DG_EINVAL, "batched solves need p >= 2 (use the plain path for p = 1)");
-    lds = l > lds ? l : lds;
-  }
   idp_dg_batch* b = new (std::nothrow) idp_dg_batch;
   if (!b) return bfail(nullptr, IDP_DG_ENOMEM, "host allocation failed");
   b->s.assign(solves, solves + n);
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
   b->fam = fam;
   b->n = n;
-  b->lds = lds;
-  std::vector<int> item_solve, item_tile, begin(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    const int epb = batch_tile_elems(fam, solves[i]->d.p);
-    const int nt = (solves[i]->ne + epb - 1) / epb;
-    begin[i] = (int)item_solve.size();
-    for (int t = 0; t < nt; ++t) {
-      item_solve.push_back(i);
-      item_tile.push_back(t);
+  std::vector<int> item_solve, item_tile, range(2 * n, 0);
+  for (int p = 1; p <= MAXP; ++p) {
+    BatchGroup gr;
+    gr.p = p;
+    gr.ofs = (int)item_solve.size();
+    for (int i = 0; i < n; ++i) {
+      if (solves[i]->d.p != p) continue;
+      if (batch_kernels(fam, p, &gr.k)) {
+        delete b;
+        return bfail(nullptr, IDP_DG_EINVAL, "no batched kernel for this degree");
+      }
+      const int epb = gr.k.tile_elems;
+      const int nt = (solves[i]->ne + epb - 1) / epb;
+      range[2 * i] = (int)item_solve.size();
+      for (int t = 0; t < nt; ++t) {
+        item_solve.push_back(i);
+        item_tile.push_back(t);
+      }
+      range[2 * i + 1] = (int)item_solve.size();
     }
+    gr.nitems = (int)item_solve.size() - gr.ofs;
+    if (gr.nitems > 0) b->groups.push_back(gr);
   }
-  begin[n] = (int)item_solve.size();
-  b->nitems = begin[n];
-  // tiles of 128 threads carry about the same work: equal counts per XCD
-  for (int x = 0; x <= 8; ++x) b->chunk[x] = (int)((long long)b->nitems * x / 8);
-  int cus = 0;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, solves[0]->device);
-  const int per_cu = batch_blocks_per_cu(fam, lds);
-  int grid = (cus > 0 ? cus : 256) * per_cu;
-  const int cap_items = ((b->nitems + 7) / 8) * 8;
-  if (grid > cap_items) grid = cap_items;
-  b->grid = grid < 8 ? 8 : (grid / 8) * 8;
+  b->nitems = (int)item_solve.size();
   b->h_args.resize(3 * n);
   b->h_dtargs.resize(n);
   b->cur_u.assign(n, nullptr);
@@ -224,7 +268,7 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_b
   if (e == hipSuccess) e = hipMalloc(&b->d_dtargs, sizeof(MaxDtArgs) * n);
   if (e == hipSuccess) e = hipMalloc(&b->d_item_solve, sizeof(int) * b->nitems);
   if (e == hipSuccess) e = hipMalloc(&b->d_item_tile, sizeof(int) * b->nitems);
-  if (e == hipSuccess) e = hipMalloc(&b->d_begin, sizeof(int) * (n + 1));
+  if (e == hipSuccess) e = hipMalloc(&b->d_range, sizeof(int) * 2 * n);
   if (e == hipSuccess) e = hipMalloc(&b->d_partial, sizeof(double) * b->nitems);
   if (e == hipSuccess) e = hipMalloc(&b->d_dt, sizeof(double) * 2 * n);
   if (e == hipSuccess) e = hipHostMalloc(&b->h_ring, sizeof(double) * kRing * n, hipHostMallocDefault);
@@ -233,7 +277,7 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_b
     e = hipMemcpy(b->d_item_solve, item_solve.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_item_tile, item_tile.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_begin, begin.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_range, range.data(), sizeof(int) * 2 * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? IDP_DG_ENOMEM : IDP_DG_EHIP;
     bfail(nullptr, code, std::string("batch allocation: ") + hipGetErrorString(e));
@@ -247,17 +291,16 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_b
 void idp_dg_batch_destroy(idp_dg_batch* b) {
   if (!b) return;
   drop_batch_graph(b);
-  if (b->cap) hipStreamDestroy(b->cap);
   for (int r = 0; r < kRing; ++r)
     if (b->ring_ev[r]) hipEventDestroy(b->ring_ev[r]);
   hipFree(b->d_args);
   hipFree(b->d_dtargs);
   hipFree(b->d_item_solve);
   hipFree(b->d_item_tile);
-  hipFree(b->d_begin);
+  hipFree(b->d_range);
   hipFree(b->d_partial);
   hipFree(b->d_dt);
-  if (b->h_ring) hipHostFree(b->h_ring);
+  if (b->h_ring) (void)hipHostFree(b->h_ring);
   delete b;
 }
 
@@ -283,8 +326,12 @@ int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt) {
   e = hipMemcpyAsync(b->d_dt, slot, sizeof(double) * b->n, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipEventRecord(b->ring_ev[r], b->stream);
   if (e != hipSuccess) return bhip(b, e, "dt upload");
-  e = enqueue_batch_stages(b, b->stream);
-  if (e != hipSuccess) return bhip(b, e, "batch stage launch");
+  if (!b->exec) {
+    e = build_graph(b, false);
+    if (e != hipSuccess) return bhip(b, e, "batch graph");
+  }
+  e = hipGraphLaunch(b->exec, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
   return 0;
 }
 
@@ -298,21 +345,8 @@ int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl) {
   if (rc) return rc;
   hipError_t e;
   if (!b->exec) {
-    if (!b->cap) {
-      e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-      if (e != hipSuccess) return bhip(b, e, "hipStreamCreate");
-    }
-    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return bhip(b, e, "hipStreamBeginCapture");
-    hipError_t le = enqueue_batch_maxdt(b, bounds, b->cap);
-    if (le == hipSuccess) le = enqueue_batch_stages(b, b->cap);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->cap, &g);
-    if (le != hipSuccess) { if (g) hipGraphDestroy(g); return bhip(b, le, "batch capture"); }
-    if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
-    b->graph = g;
-    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) { drop_batch_graph(b); return bhip(b, e, "hipGraphInstantiate"); }
+    e = build_graph(b, true);
+    if (e != hipSuccess) return bhip(b, e, "batch graph");
   }
   e = hipGraphLaunch(b->exec, b->stream);
   if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");

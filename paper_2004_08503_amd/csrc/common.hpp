@@ -77,20 +77,27 @@ struct MaxDtArgs {
   Tables T;
 };
 
-// Batched execution: a work list of (solve, tile) items split into eight
-// contiguous chunks, one per XCD (workgroup b runs on XCD b mod 8).
+// Batched execution: per degree, a work list of (solve, tile) items over
+// every solve of that degree.
 struct BatchArgs {
   const StageArgs* args;     // per solve (this stage's pointers and dt)
   const int* item_solve;
   const int* item_tile;
-  int chunk[9];
+  int nitems;
 };
 struct BatchDtArgs {
   const MaxDtArgs* args;     // per solve
   const int* item_solve;
   const int* item_tile;
   double* partial;           // one minimum per item
-  int chunk[9];
+  int nitems;
+};
+// The work-list kernels of one degree, for building graph nodes.
+struct BatchKernels {
+  const void* stage;         // __global__ void(BatchArgs)
+  const void* maxdt;         // __global__ void(BatchDtArgs)
+  int block;                 // threads per workgroup
+  int tile_elems;            // elements per tile
 };
 
 // Kernel launchers, one translation unit per (equation, dimension).
@@ -101,11 +108,7 @@ struct BatchDtArgs {
   hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s);       \
   int tile_elems_##NAME(int p, int variant);                                      \
   int num_variants_##NAME(int p);                                                 \
-  hipError_t launch_batch_stage_##NAME(const BatchArgs& b, int grid, int lds, hipStream_t s); \
-  hipError_t launch_batch_maxdt_##NAME(const BatchDtArgs& b, int grid, int lds, hipStream_t s); \
-  int batch_tile_elems_##NAME(int p);                                             \
-  int batch_lds_bytes_##NAME(int p);                                              \
-  int batch_blocks_per_cu_##NAME(int lds);
+  int batch_kernels_##NAME(int p, BatchKernels* k);
 
 IDP_DECLARE_LAUNCHERS(adv1)
 IDP_DECLARE_LAUNCHERS(adv2)
@@ -120,7 +123,7 @@ IDP_DECLARE_LAUNCHERS(euler75_2)
 
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);
-// per solve s: min over partial[begin[s]..begin[s+1]) -> out[s] (one workgroup per solve)
-__global__ void segmented_min_kernel(const double* partial, const int* begin, double* out);
+// per solve s: min over partial[range[2s]..range[2s+1]) -> out[s] (one workgroup per solve)
+__global__ void segmented_min_kernel(const double* partial, const int* range, double* out);
 
 }  // namespace idp

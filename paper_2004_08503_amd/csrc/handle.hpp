@@ -45,9 +45,5 @@ idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double*
                                double dt, const double* dt_dev, double dt_scale, int stage);
 idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
-hipError_t launch_batch_stage(int fam, const idp::BatchArgs& b, int grid, int lds, hipStream_t s);
-hipError_t launch_batch_maxdt(int fam, const idp::BatchDtArgs& b, int grid, int lds, hipStream_t s);
-int batch_tile_elems(int fam, int p);
-int batch_lds_bytes(int fam, int p);
-int batch_blocks_per_cu(int fam, int lds);
+int batch_kernels(int fam, int p, idp::BatchKernels* k);
 }  // namespace idp_host

@@ -224,84 +224,20 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   return a;
 }
 
-hipError_t launch_batch_stage(int fam, const BatchArgs& b, int grid, int lds, hipStream_t s) {
+int batch_kernels(int fam, int p, BatchKernels* k) {
   switch (fam) {
-    case 0: return launch_batch_stage_adv1(b, grid, lds, s);
-    case 1: return launch_batch_stage_adv2(b, grid, lds, s);
-    case 2: return launch_batch_stage_burg1(b, grid, lds, s);
-    case 3: return launch_batch_stage_burg2(b, grid, lds, s);
-    case 4: return launch_batch_stage_euler1(b, grid, lds, s);
-    case 5: return launch_batch_stage_euler2(b, grid, lds, s);
-    case 6: return launch_batch_stage_euler53_1(b, grid, lds, s);
-    case 7: return launch_batch_stage_euler53_2(b, grid, lds, s);
-    case 8: return launch_batch_stage_euler75_1(b, grid, lds, s);
-    case 9: return launch_batch_stage_euler75_2(b, grid, lds, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_batch_maxdt(int fam, const BatchDtArgs& b, int grid, int lds, hipStream_t s) {
-  switch (fam) {
-    case 0: return launch_batch_maxdt_adv1(b, grid, lds, s);
-    case 1: return launch_batch_maxdt_adv2(b, grid, lds, s);
-    case 2: return launch_batch_maxdt_burg1(b, grid, lds, s);
-    case 3: return launch_batch_maxdt_burg2(b, grid, lds, s);
-    case 4: return launch_batch_maxdt_euler1(b, grid, lds, s);
-    case 5: return launch_batch_maxdt_euler2(b, grid, lds, s);
-    case 6: return launch_batch_maxdt_euler53_1(b, grid, lds, s);
-    case 7: return launch_batch_maxdt_euler53_2(b, grid, lds, s);
-    case 8: return launch_batch_maxdt_euler75_1(b, grid, lds, s);
-    case 9: return launch_batch_maxdt_euler75_2(b, grid, lds, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-int batch_tile_elems(int fam, int p) {
-  switch (fam) {
-    case 0: return batch_tile_elems_adv1(p);
-    case 1: return batch_tile_elems_adv2(p);
-    case 2: return batch_tile_elems_burg1(p);
-    case 3: return batch_tile_elems_burg2(p);
-    case 4: return batch_tile_elems_euler1(p);
-    case 5: return batch_tile_elems_euler2(p);
-    case 6: return batch_tile_elems_euler53_1(p);
-    case 7: return batch_tile_elems_euler53_2(p);
-    case 8: return batch_tile_elems_euler75_1(p);
-    case 9: return batch_tile_elems_euler75_2(p);
-  }
-  return 1;
-}
-
-int batch_lds_bytes(int fam, int p) {
-  switch (fam) {
-    case 0: return batch_lds_bytes_adv1(p);
-    case 1: return batch_lds_bytes_adv2(p);
-    case 2: return batch_lds_bytes_burg1(p);
-    case 3: return batch_lds_bytes_burg2(p);
-    case 4: return batch_lds_bytes_euler1(p);
-    case 5: return batch_lds_bytes_euler2(p);
-    case 6: return batch_lds_bytes_euler53_1(p);
-    case 7: return batch_lds_bytes_euler53_2(p);
-    case 8: return batch_lds_bytes_euler75_1(p);
-    case 9: return batch_lds_bytes_euler75_2(p);
+    case 0: return batch_kernels_adv1(p, k);
+    case 1: return batch_kernels_adv2(p, k);
+    case 2: return batch_kernels_burg1(p, k);
+    case 3: return batch_kernels_burg2(p, k);
+    case 4: return batch_kernels_euler1(p, k);
+    case 5: return batch_kernels_euler2(p, k);
+    case 6: return batch_kernels_euler53_1(p, k);
+    case 7: return batch_kernels_euler53_2(p, k);
+    case 8: return batch_kernels_euler75_1(p, k);
+    case 9: return batch_kernels_euler75_2(p, k);
   }
   return -1;
-}
-
-int batch_blocks_per_cu(int fam, int lds) {
-  switch (fam) {
-    case 0: return batch_blocks_per_cu_adv1(lds);
-    case 1: return batch_blocks_per_cu_adv2(lds);
-    case 2: return batch_blocks_per_cu_burg1(lds);
-    case 3: return batch_blocks_per_cu_burg2(lds);
-    case 4: return batch_blocks_per_cu_euler1(lds);
-    case 5: return batch_blocks_per_cu_euler2(lds);
-    case 6: return batch_blocks_per_cu_euler53_1(lds);
-    case 7: return batch_blocks_per_cu_euler53_2(lds);
-    case 8: return batch_blocks_per_cu_euler75_1(lds);
-    case 9: return batch_blocks_per_cu_euler75_2(lds);
-  }
-  return 1;
 }
 
 }  // namespace idp_host
@@ -346,12 +282,12 @@ hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
 }  // namespace
 
 namespace idp {
-__global__ __launch_bounds__(256) void segmented_min_kernel(const double* partial, const int* begin,
+__global__ __launch_bounds__(256) void segmented_min_kernel(const double* partial, const int* range,
                                                              double* out) {
   __shared__ double red[4];
   const int s = blockIdx.x;
   double v = INFINITY;
-  for (int i = begin[s] + threadIdx.x; i < begin[s + 1]; i += 256) v = fmin(v, partial[i]);
+  for (int i = range[2 * s] + threadIdx.x; i < range[2 * s + 1]; i += 256) v = fmin(v, partial[i]);
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();

@@ -810,101 +810,42 @@ constexpr int epb_for(int dim, int p, int variant) {
 #define IDP_NUM_VARIANTS 1
 
 // ----------------------------------------------------------------------
-// batched persistent kernels: 128 threads, EPB = floor(128 / (p+1)^d)
+// batched work-list kernels: one kernel per degree, its work list holding
+// the element tiles of every solve of that degree (same tile shape as the
+// plain kernel); workgroups map to items XCD-aware, and a workgroup walks
+// further items with a stride of the grid when the grid is smaller.
 // ----------------------------------------------------------------------
-constexpr int BATCH_BS = 128;
-constexpr int epb_batch(int dim, int p) {
-  return dim == 1 ? BATCH_BS / (p + 1) : BATCH_BS / ((p + 1) * (p + 1));
-}
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
-// LDS (bytes) a batched tile of degree P needs: the stage tile or the
-// time-step tile, whichever is larger.
-template <int EQ, int DIM, int P>
-constexpr int batch_lds_bytes_p() {
-  return 8 * cmax(Cfg<EQ, DIM, P, epb_batch(DIM, P)>::LDS, DtCfg<EQ, DIM, P, epb_batch(DIM, P)>::LDS);
-}
-
-// Each degree's tile body is a separate (non-inlined) function so that its
-// registers are allocated on their own rather than as the union of all
-// eight bodies.
-template <int EQ, int DIM, int P>
-__device__ __noinline__ void batch_stage_item(double* lds, const StageArgs& A, int tile) {
-  constexpr int EPB = epb_batch(DIM, P);
-  static_assert(Cfg<EQ, DIM, P, EPB>::BS == BATCH_BS, "batch tiles use 128 threads");
-  stage_tile<EQ, DIM, P, EPB>(lds, A, tile);
-}
-
-template <int EQ, int DIM, int P>
-__device__ __noinline__ void batch_maxdt_item(double* lds, const MaxDtArgs& A, int tile, double* out) {
-  maxdt_tile<EQ, DIM, P, epb_batch(DIM, P)>(lds, A, tile, out);
-}
-
-// Persistent kernels: workgroup b runs on XCD b mod 8 and walks that XCD's
-// chunk of the work list with stride gridDim/8.  Degrees 2..8 (p = 1 tiles
-// of 128 threads would need 32 elements and too much LDS; p = 1 solves use
-// the plain path).
-template <int EQ, int DIM>
-__global__ __launch_bounds__(BATCH_BS) void batch_stage_kernel(BatchArgs B) {
-  extern __shared__ double lds[];
-  const int x = blockIdx.x & 7, per = gridDim.x >> 3;
-  for (int it = B.chunk[x] + (int)(blockIdx.x >> 3); it < B.chunk[x + 1]; it += per) {
-    __syncthreads();  // the previous item's phase 5 may still read LDS
-    const StageArgs& A = B.args[B.item_solve[it]];
-    const int t = B.item_tile[it];
-    switch (A.S.p) {
-      case 2: batch_stage_item<EQ, DIM, 2>(lds, A, t); break;
-      case 3: batch_stage_item<EQ, DIM, 3>(lds, A, t); break;
-      case 4: batch_stage_item<EQ, DIM, 4>(lds, A, t); break;
-      case 5: batch_stage_item<EQ, DIM, 5>(lds, A, t); break;
-      case 6: batch_stage_item<EQ, DIM, 6>(lds, A, t); break;
-      case 7: batch_stage_item<EQ, DIM, 7>(lds, A, t); break;
-      case 8: batch_stage_item<EQ, DIM, 8>(lds, A, t); break;
-    }
+template <int EQ, int DIM, int P, int EPB>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel(BatchArgs B) {
+  __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
+  const int off = xcd_tile(blockIdx.x, gridDim.x);
+  for (int base = 0; base < B.nitems; base += gridDim.x) {
+    const int it = base + off;
+    if (it >= B.nitems) break;              // uniform over the workgroup
+    if (base > 0) __syncthreads();          // the previous item may still read LDS
+    stage_tile<EQ, DIM, P, EPB>(lds, B.args[B.item_solve[it]], B.item_tile[it]);
   }
 }
 
-template <int EQ, int DIM>
-__global__ __launch_bounds__(BATCH_BS) void batch_maxdt_kernel(BatchDtArgs B) {
-  extern __shared__ double lds[];
-  const int x = blockIdx.x & 7, per = gridDim.x >> 3;
-  for (int it = B.chunk[x] + (int)(blockIdx.x >> 3); it < B.chunk[x + 1]; it += per) {
-    __syncthreads();
-    const MaxDtArgs& A = B.args[B.item_solve[it]];
-    const int t = B.item_tile[it];
-    double* out = B.partial + it;
-    switch (A.p) {
-      case 2: batch_maxdt_item<EQ, DIM, 2>(lds, A, t, out); break;
-      case 3: batch_maxdt_item<EQ, DIM, 3>(lds, A, t, out); break;
-      case 4: batch_maxdt_item<EQ, DIM, 4>(lds, A, t, out); break;
-      case 5: batch_maxdt_item<EQ, DIM, 5>(lds, A, t, out); break;
-      case 6: batch_maxdt_item<EQ, DIM, 6>(lds, A, t, out); break;
-      case 7: batch_maxdt_item<EQ, DIM, 7>(lds, A, t, out); break;
-      case 8: batch_maxdt_item<EQ, DIM, 8>(lds, A, t, out); break;
-    }
+template <int EQ, int DIM, int P, int EPB>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel(BatchDtArgs B) {
+  __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
+  const int off = xcd_tile(blockIdx.x, gridDim.x);
+  for (int base = 0; base < B.nitems; base += gridDim.x) {
+    const int it = base + off;
+    if (it >= B.nitems) break;
+    if (base > 0) __syncthreads();
+    maxdt_tile<EQ, DIM, P, EPB>(lds, B.args[B.item_solve[it]], B.item_tile[it], B.partial + it);
   }
 }
 
-template <int EQ, int DIM>
-int batch_lds_bytes_t(int p) {
-  switch (p) {
-    case 2: return batch_lds_bytes_p<EQ, DIM, 2>();
-    case 3: return batch_lds_bytes_p<EQ, DIM, 3>();
-    case 4: return batch_lds_bytes_p<EQ, DIM, 4>();
-    case 5: return batch_lds_bytes_p<EQ, DIM, 5>();
-    case 6: return batch_lds_bytes_p<EQ, DIM, 6>();
-    case 7: return batch_lds_bytes_p<EQ, DIM, 7>();
-    case 8: return batch_lds_bytes_p<EQ, DIM, 8>();
-  }
-  return -1;
-}
-
-template <int EQ, int DIM>
-int batch_blocks_per_cu_t(int lds_bytes) {
-  int a = 0, b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_stage_kernel<EQ, DIM>, BATCH_BS, lds_bytes) != hipSuccess) a = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_maxdt_kernel<EQ, DIM>, BATCH_BS, lds_bytes) != hipSuccess) b = 1;
-  return cmax(1, a < b ? a : b);
+template <int EQ, int DIM, int P>
+void batch_kernels_t(BatchKernels* k) {
+  constexpr int EPB = epb_for(DIM, P, 0);
+  k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, EPB>);
+  k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, EPB>);
+  k->block = Cfg<EQ, DIM, P, EPB>::BS;
+  k->tile_elems = EPB;
 }
 
 template <int EQ, int DIM, int P, int EPB>
@@ -960,17 +901,19 @@ hipError_t launch_stage_v(int variant, const StageArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;                                                         \
   }                                                                                      \
   int tile_elems_##NAME(int p, int variant) { return epb_for(DIM, p, variant); }         \
-  hipError_t launch_batch_stage_##NAME(const BatchArgs& b, int grid, int lds, hipStream_t s) { \
-    hipLaunchKernelGGL((batch_stage_kernel<EQ, DIM>), dim3(grid), dim3(BATCH_BS), lds, s, b); \
-    return hipGetLastError();                                                            \
+  int batch_kernels_##NAME(int p, BatchKernels* k) {                                     \
+    switch (p) {                                                                         \
+      case 1: batch_kernels_t<EQ, DIM, 1>(k); return 0;                                  \
+      case 2: batch_kernels_t<EQ, DIM, 2>(k); return 0;                                  \
+      case 3: batch_kernels_t<EQ, DIM, 3>(k); return 0;                                  \
+      case 4: batch_kernels_t<EQ, DIM, 4>(k); return 0;                                  \
+      case 5: batch_kernels_t<EQ, DIM, 5>(k); return 0;                                  \
+      case 6: batch_kernels_t<EQ, DIM, 6>(k); return 0;                                  \
+      case 7: batch_kernels_t<EQ, DIM, 7>(k); return 0;                                  \
+      case 8: batch_kernels_t<EQ, DIM, 8>(k); return 0;                                  \
+    }                                                                                    \
+    return -1;                                                                           \
   }                                                                                      \
-  hipError_t launch_batch_maxdt_##NAME(const BatchDtArgs& b, int grid, int lds, hipStream_t s) { \
-    hipLaunchKernelGGL((batch_maxdt_kernel<EQ, DIM>), dim3(grid), dim3(BATCH_BS), lds, s, b); \
-    return hipGetLastError();                                                            \
-  }                                                                                      \
-  int batch_tile_elems_##NAME(int p) { return epb_batch(DIM, p); }                       \
-  int batch_lds_bytes_##NAME(int p) { return batch_lds_bytes_t<EQ, DIM>(p); }            \
-  int batch_blocks_per_cu_##NAME(int lds) { return batch_blocks_per_cu_t<EQ, DIM>(lds); } \
   int num_variants_##NAME(int p) {                                                       \
     (void)p;                                                                             \
     return IDP_NUM_VARIANTS;                                                             \
