@@ -126,6 +126,24 @@ def batched_leg(steps, count=64):
     }
 
 
+def serving_leg(count, load, capacity, budget_gb=64.0):
+    """The served workload: a seeded Poisson stream of `count` requests (half
+    Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps), rate set
+    for the given offered load of `capacity` DOF-updates/s.  Run once through
+    the continuous-batching server and once FIFO through the plain path."""
+    from paper_2004_08503_amd import serve, workloads as W
+    probe = W.request_stream(count, rate=1.0, seed=5)
+    mean_work = np.mean([3.0 * r.problem().num_nodes * r.steps for r in probe])
+    rate = load * capacity / mean_work
+    reqs = W.request_stream(count, rate=rate, seed=5)
+    srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
+    served = serve.summarize(srv.run(reqs))
+    fifo = serve.summarize(serve.run_fifo_plain(reqs))
+    return {"workload": "served_stream_%d_requests_burgers_euler_n16-512_p2-6_steps20-200" % count,
+            "offered_load": load, "rate_per_s": rate, "hbm_budget_gb": budget_gb,
+            "served": served, "fifo_plain": fifo}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +154,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-solve leg")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests in the served stream (0 skips the serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (4 times), the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -244,6 +265,9 @@ def main():
     del u, b1, b2
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_steps)
+    if args.serve_requests > 0:
+        cap = out["batched"]["value"] if "batched" in out else value
+        out["serving"] = serving_leg(args.serve_requests, args.serve_load, cap)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, dt_last)
     print(json.dumps(out))

@@ -92,7 +92,23 @@ typedef struct {
  * *out receives the handle, or NULL on failure. */
 int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out);
 
-/* Release the handle and its buffers.  NULL-safe. */
+/* Device bytes idp_dg_create_in needs for desc: the two stage buffers,
+ * the diagnostics and the time-step partial minima.  Negative
+ * (IDP_DG_EINVAL) for a bad desc. */
+long long idp_dg_workspace_bytes(const idp_dg_desc* desc);
+
+/* idp_dg_create with every device buffer of the handle placed in the
+ * caller's workspace (device memory of at least idp_dg_workspace_bytes
+ * bytes, 256-byte aligned, caller-owned, kept alive until idp_dg_destroy
+ * has returned and the handle's queued work has run).  The handle then
+ * allocates and frees no device memory, so a caller that creates and drops
+ * many handles (a serving loop) can take the memory from its own
+ * stream-ordered allocator.  The diagnostics are cleared with an
+ * asynchronous memset on hip_stream. */
+int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream,
+                     void* workspace, long long bytes, idp_dg** out);
+
+/* Release the handle and the buffers it allocated.  NULL-safe. */
 void idp_dg_destroy(idp_dg* h);
 
 /* Number of nodes Nn and of components nc of the handle's problem. */
@@ -176,7 +192,13 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream,
                         idp_dg_batch** out);
 void idp_dg_batch_destroy(idp_dg_batch* b);
 
-/* Work items (element tiles over all solves) of one batched launch. */
+/* Replace the batch's solves by solves[0..n) (same rules as for create),
+ * keeping its device storage: for a serving loop whose set of running
+ * solves changes from step to step.  Takes effect at the next step; work
+ * already enqueued is unaffected. */
+int idp_dg_batch_update(idp_dg_batch* b, idp_dg* const* solves, int n);
+
+/* Work items (element tiles over all solves) of the current membership. */
 int idp_dg_batch_num_items(const idp_dg_batch* b);
 
 /* One SSP-RK3 step of every solve i: u[i] (device, in place, layout as for

@@ -2,12 +2,18 @@
 // mix of mesh sizes and degrees) advance together.  The solves are grouped
 // by degree; each group has a work list of (solve, element tile) items over
 // all its solves and one work-list kernel per RK stage (the plain path's
-// tile shape, mapped XCD-aware over the list).  A batched step is one HIP
-// graph, built once per (pointer set, time-step mode, cfl): the groups'
-// kernels of a stage are parallel branches, the stages follow each other,
-// and in the device-timestepped mode the groups' time-step kernels and one
-// segmented minimum come first.  Host time steps reach the device through
-// a pinned ring before the graph launch.
+// tile shape, mapped XCD-aware over the list).  A batched step runs, per
+// stage, the groups' kernels; in the device-timestepped mode the groups'
+// time-step kernels and one segmented minimum come first.
+//
+// Everything a launch reads (per-solve stage arguments, work lists, item
+// ranges) lives in one device blob that is rewritten by a single
+// asynchronous copy from a pinned staging ring whenever the membership, the
+// state pointers or the time-step mode change, so changing a batch never
+// synchronises the host with the device.  While a configuration keeps
+// changing the kernels are launched directly; once the same configuration
+// is stepped twice in a row its step is captured as a HIP graph (the
+// degree groups of a stage as parallel branches) and replayed.
 //
 // Results are bitwise identical to the plain path: a tile's arithmetic does
 // not depend on which workgroup or launch runs it, and the only reductions
@@ -28,14 +34,16 @@ using namespace idp;
 using namespace idp_host;
 
 namespace {
-constexpr int kRing = 32;  // pinned staging slots for host time steps
-}
+constexpr int kRing = 4;   // pinned staging slots
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
 
 struct BatchGroup {
   int p = 0;
   BatchKernels k{};
   int nitems = 0;
-  int ofs = 0;        // first item of the group in the item arrays / partials
+  int ofs = 0;        // first item of the group in the work-list arrays
 };
 
 struct idp_dg_batch {
@@ -45,27 +53,25 @@ struct idp_dg_batch {
   int n = 0;
   int nitems = 0;
   std::vector<BatchGroup> groups;
-  // device
-  StageArgs* d_args = nullptr;     // [3][n]
-  MaxDtArgs* d_dtargs = nullptr;   // [n]
-  int* d_item_solve = nullptr;     // [nitems], grouped by degree
-  int* d_item_tile = nullptr;
-  int* d_range = nullptr;          // [2n] item range of each solve
-  double* d_partial = nullptr;     // [nitems]
-  double* d_dt = nullptr;          // [0,n) host time steps, [n,2n) device bounds
-  // host mirrors of what d_args / d_dtargs hold
-  std::vector<StageArgs> h_args;
-  std::vector<MaxDtArgs> h_dtargs;
+  bool dirty = true;               // membership changed since the last upload
+  // blob layout (offsets in bytes) for the current n / nitems
+  size_t o_args = 0, o_dtargs = 0, o_isolve = 0, o_itile = 0, o_range = 0, o_partial = 0,
+         o_dt = 0, blob_bytes = 0, stage_bytes = 0;
+  char* d_blob = nullptr;
+  size_t d_cap = 0;
+  char* h_ring = nullptr;          // kRing pinned slots of h_cap bytes
+  size_t h_cap = 0;
+  hipEvent_t ring_ev[kRing] = {};
+  int ring_next = 0;
+  // what the device blob currently describes
   std::vector<double*> cur_u;
   double cur_scale = -1.0;
   int cur_mode = -1;               // 0: host time steps, 1: device bounds
-  // pinned ring of host time steps
-  double* h_ring = nullptr;
-  hipEvent_t ring_ev[kRing] = {};
-  int ring_next = 0;
-  // graph of one step in the current mode
+  // reuse of the previous configuration's step as a graph
+  int repeats = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int graph_mode = -1;
   std::string err = "no error";
 };
 
@@ -83,116 +89,236 @@ int bhip(idp_dg_batch* b, hipError_t e, const char* where) {
 }
 
 void drop_batch_graph(idp_dg_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  b->graph_mode = -1;
 }
 
 bool overlap(const double* a, long long na, const double* c, long long nc) {
   return a < c + nc && c < a + na;
 }
 
-// Point the per-stage arguments of every solve at u[i] and at the time
-// steps in dt_dev (+ i) scaled by dt_scale, and upload them if they changed.
-int set_args(idp_dg_batch* b, double* const* u, double* dt_dev, double dt_scale, int mode) {
-  bool same = b->cur_scale == dt_scale && b->cur_mode == mode;
-  for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i];
-  if (same) return 0;
-  for (int i = 0; i < b->n; ++i) {
-    idp_dg* h = b->s[i];
-    const double* dtp = dt_dev + i;
-    b->h_args[0 * b->n + i] = make_stage_args(h, nullptr, u[i], h->buf1, 0.0, dtp, dt_scale, 0);
-    b->h_args[1 * b->n + i] = make_stage_args(h, u[i], h->buf1, h->buf2, 0.0, dtp, dt_scale, 1);
-    b->h_args[2 * b->n + i] = make_stage_args(h, u[i], h->buf2, u[i], 0.0, dtp, dt_scale, 2);
-    b->h_dtargs[i] = make_dt_args(h, u[i]);
-    b->h_dtargs[i].partial = b->d_partial;  // tiles write partial[item]
+template <class T>
+T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
+
+// Work lists and blob layout for the current membership.
+int plan(idp_dg_batch* b, std::vector<int>* isolve, std::vector<int>* itile, std::vector<int>* range) {
+  b->groups.clear();
+  isolve->clear();
+  itile->clear();
+  range->assign(2 * b->n, 0);
+  for (int p = 1; p <= MAXP; ++p) {
+    BatchGroup gr;
+    gr.p = p;
+    gr.ofs = (int)isolve->size();
+    for (int i = 0; i < b->n; ++i) {
+      if (b->s[i]->d.p != p) continue;
+      if (batch_kernels(b->fam, p, &gr.k)) return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
+      const int nt = (b->s[i]->ne + gr.k.tile_elems - 1) / gr.k.tile_elems;
+      (*range)[2 * i] = (int)isolve->size();
+      for (int t = 0; t < nt; ++t) {
+        isolve->push_back(i);
+        itile->push_back(t);
+      }
+      (*range)[2 * i + 1] = (int)isolve->size();
+    }
+    gr.nitems = (int)isolve->size() - gr.ofs;
+    if (gr.nitems > 0) b->groups.push_back(gr);
   }
-  hipError_t e = hipMemcpyAsync(b->d_args, b->h_args.data(), sizeof(StageArgs) * 3 * b->n,
-                                hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b->d_dtargs, b->h_dtargs.data(), sizeof(MaxDtArgs) * b->n,
-                       hipMemcpyHostToDevice, b->stream);
-  // the mirrors are rewritten on the next change: let the copies finish
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return bhip(b, e, "batch argument upload");
-  for (int i = 0; i < b->n; ++i) b->cur_u[i] = u[i];
-  b->cur_scale = dt_scale;
-  b->cur_mode = mode;
-  drop_batch_graph(b);
+  b->nitems = (int)isolve->size();
+  const size_t n = b->n, ni = b->nitems;
+  b->o_args = 0;
+  b->o_dtargs = up(b->o_args + sizeof(StageArgs) * 3 * n);
+  b->o_isolve = up(b->o_dtargs + sizeof(MaxDtArgs) * n);
+  b->o_itile = up(b->o_isolve + sizeof(int) * ni);
+  b->o_range = up(b->o_itile + sizeof(int) * ni);
+  b->stage_bytes = up(b->o_range + sizeof(int) * 2 * n);   // the part uploaded from the host
+  b->o_partial = b->stage_bytes;
+  b->o_dt = up(b->o_partial + sizeof(double) * ni);
+  b->blob_bytes = up(b->o_dt + sizeof(double) * 2 * n);
   return 0;
 }
 
-hipError_t add_kernel(hipGraph_t g, hipGraphNode_t* node, const std::vector<hipGraphNode_t>& deps,
-                      const void* func, dim3 grid, dim3 block, void** args) {
-  hipKernelNodeParams kp;
-  std::memset(&kp, 0, sizeof(kp));
-  kp.func = const_cast<void*>(func);
-  kp.gridDim = grid;
-  kp.blockDim = block;
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = args;
-  kp.extra = nullptr;
-  return hipGraphAddKernelNode(node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
+// Rewrite the device blob for (membership, u, mode, scale) through a pinned
+// staging slot with one asynchronous copy.
+int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
+  std::vector<int> isolve, itile, range;
+  int rc = plan(b, &isolve, &itile, &range);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  if (b->blob_bytes > b->d_cap) {
+    // growing: the old blob may still be read by queued launches
+    if (b->d_blob) {
+      e = hipStreamSynchronize(b->stream);
+      if (e == hipSuccess) e = hipFree(b->d_blob);
+      b->d_blob = nullptr;
+      b->d_cap = 0;
+    }
+    const size_t cap = b->blob_bytes + b->blob_bytes / 2;
+    if (e == hipSuccess) e = hipMalloc(&b->d_blob, cap);
+    if (e != hipSuccess) return bhip(b, e, "batch blob");
+    b->d_cap = cap;
+  }
+  const size_t need = b->stage_bytes > sizeof(double) * b->n ? b->stage_bytes : sizeof(double) * b->n;
+  if (need > b->h_cap) {
+    if (b->h_ring) {
+      for (int r = 0; r < kRing; ++r) (void)hipEventSynchronize(b->ring_ev[r]);
+      (void)hipHostFree(b->h_ring);
+      b->h_ring = nullptr;
+    }
+    const size_t cap = up(need + need / 2);
+    e = hipHostMalloc(&b->h_ring, cap * kRing, hipHostMallocDefault);
+    if (e != hipSuccess) return bhip(b, e, "batch staging");
+    b->h_cap = cap;
+  }
+  const int r = b->ring_next;
+  b->ring_next = (r + 1) % kRing;
+  e = hipEventSynchronize(b->ring_ev[r]);   // the slot's previous copy has run
+  if (e != hipSuccess) return bhip(b, e, "staging event");
+  char* h = b->h_ring + (size_t)r * b->h_cap;
+  char* d = b->d_blob;
+  double* dt_dev = at<double>(d, b->o_dt) + (mode == 1 ? b->n : 0);
+  StageArgs* a = at<StageArgs>(h, b->o_args);
+  MaxDtArgs* m = at<MaxDtArgs>(h, b->o_dtargs);
+  for (int i = 0; i < b->n; ++i) {
+    idp_dg* hd = b->s[i];
+    const double* dtp = dt_dev + i;
+    a[0 * b->n + i] = make_stage_args(hd, nullptr, u[i], hd->buf1, 0.0, dtp, scale, 0);
+    a[1 * b->n + i] = make_stage_args(hd, u[i], hd->buf1, hd->buf2, 0.0, dtp, scale, 1);
+    a[2 * b->n + i] = make_stage_args(hd, u[i], hd->buf2, u[i], 0.0, dtp, scale, 2);
+    m[i] = make_dt_args(hd, u[i]);
+    m[i].partial = at<double>(d, b->o_partial);
+  }
+  if (b->nitems) {
+    std::memcpy(h + b->o_isolve, isolve.data(), sizeof(int) * b->nitems);
+    std::memcpy(h + b->o_itile, itile.data(), sizeof(int) * b->nitems);
+  }
+  std::memcpy(h + b->o_range, range.data(), sizeof(int) * 2 * b->n);
+  e = hipMemcpyAsync(d, h, b->stage_bytes, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ring_ev[r], b->stream);
+  if (e != hipSuccess) return bhip(b, e, "batch upload");
+  b->cur_u.assign(u, u + b->n);
+  b->cur_mode = mode;
+  b->cur_scale = scale;
+  b->dirty = false;
+  drop_batch_graph(b);
+  b->repeats = 0;
+  return 0;
 }
 
-// One batched step as a graph: [time-step kernels of every group ->
-// segmented min ->] stage 0 of every group -> stage 1 -> stage 2.
-hipError_t build_graph(idp_dg_batch* b, bool device_dt) {
-  hipGraph_t g = nullptr;
-  hipError_t e = hipGraphCreate(&g, 0);
-  if (e != hipSuccess) return e;
-  std::vector<hipGraphNode_t> prev;
-  if (device_dt) {
-    std::vector<hipGraphNode_t> dts;
-    for (const BatchGroup& gr : b->groups) {
-      BatchDtArgs a;
-      a.args = b->d_dtargs;
-      a.item_solve = b->d_item_solve + gr.ofs;
-      a.item_tile = b->d_item_tile + gr.ofs;
-      a.partial = b->d_partial + gr.ofs;
-      a.nitems = gr.nitems;
-      void* args[] = {&a};
-      hipGraphNode_t nd;
-      e = add_kernel(g, &nd, {}, gr.k.maxdt, dim3(gr.nitems), dim3(gr.k.block), args);
-      if (e != hipSuccess) break;
-      dts.push_back(nd);
-    }
-    if (e == hipSuccess) {
-      const double* part = b->d_partial;
-      const int* range = b->d_range;
-      double* out = b->d_dt + b->n;
-      void* args[] = {&part, &range, &out};
-      hipGraphNode_t nd;
-      e = add_kernel(g, &nd, dts, reinterpret_cast<const void*>(&segmented_min_kernel), dim3(b->n),
-                     dim3(256), args);
-      prev.assign(1, nd);
-    }
+int prepare(idp_dg_batch* b, double* const* u, int mode, double scale) {
+  bool same = !b->dirty && b->cur_mode == mode && b->cur_scale == scale;
+  for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i];
+  if (same) {
+    ++b->repeats;
+    return 0;
   }
-  for (int st = 0; st < 3 && e == hipSuccess; ++st) {
-    std::vector<hipGraphNode_t> cur;
-    for (const BatchGroup& gr : b->groups) {
-      BatchArgs a;
-      a.args = b->d_args + st * b->n;
-      a.item_solve = b->d_item_solve + gr.ofs;
-      a.item_tile = b->d_item_tile + gr.ofs;
-      a.nitems = gr.nitems;
-      void* args[] = {&a};
-      hipGraphNode_t nd;
-      e = add_kernel(g, &nd, prev, gr.k.stage, dim3(gr.nitems), dim3(gr.k.block), args);
-      if (e != hipSuccess) break;
-      cur.push_back(nd);
-    }
-    prev.swap(cur);
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    hipGraphDestroy(g);
-    b->exec = nullptr;
+  return upload(b, u, mode, scale);
+}
+
+BatchArgs group_args(const idp_dg_batch* b, const BatchGroup& gr, int stage) {
+  BatchArgs a;
+  a.args = at<StageArgs>(b->d_blob, b->o_args) + stage * b->n;
+  a.item_solve = at<int>(b->d_blob, b->o_isolve) + gr.ofs;
+  a.item_tile = at<int>(b->d_blob, b->o_itile) + gr.ofs;
+  a.nitems = gr.nitems;
+  return a;
+}
+
+BatchDtArgs group_dt_args(const idp_dg_batch* b, const BatchGroup& gr) {
+  BatchDtArgs a;
+  a.args = at<MaxDtArgs>(b->d_blob, b->o_dtargs);
+  a.item_solve = at<int>(b->d_blob, b->o_isolve) + gr.ofs;
+  a.item_tile = at<int>(b->d_blob, b->o_itile) + gr.ofs;
+  a.partial = at<double>(b->d_blob, b->o_partial) + gr.ofs;
+  a.nitems = gr.nitems;
+  return a;
+}
+
+// The launches of one step, enqueued directly on s, or added to graph g
+// with every stage depending on all launches of the one before.
+hipError_t emit_step(idp_dg_batch* b, bool device_dt, hipStream_t s, hipGraph_t g) {
+  std::vector<hipGraphNode_t> prev, cur;
+  auto launch = [&](const void* func, dim3 grid, dim3 block, void** args) -> hipError_t {
+    if (!g) return hipLaunchKernel(func, grid, block, args, 0, s);
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void*>(func);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.kernelParams = args;
+    hipGraphNode_t nd;
+    hipError_t e = hipGraphAddKernelNode(&nd, g, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
+    if (e == hipSuccess) cur.push_back(nd);
     return e;
+  };
+  auto frontier = [&]() {
+    prev.swap(cur);
+    cur.clear();
+  };
+  hipError_t e = hipSuccess;
+  if (device_dt) {
+    for (const BatchGroup& gr : b->groups) {
+      BatchDtArgs a = group_dt_args(b, gr);
+      void* args[] = {&a};
+      e = launch(gr.k.maxdt, dim3(gr.nitems), dim3(gr.k.block), args);
+      if (e != hipSuccess) return e;
+    }
+    frontier();
+    const double* part = at<double>(b->d_blob, b->o_partial);
+    const int* range = at<int>(b->d_blob, b->o_range);
+    double* out = at<double>(b->d_blob, b->o_dt) + b->n;
+    void* args[] = {&part, &range, &out};
+    e = launch(reinterpret_cast<const void*>(&segmented_min_kernel), dim3(b->n), dim3(256), args);
+    if (e != hipSuccess) return e;
+    frontier();
   }
-  b->graph = g;
+  for (int st = 0; st < 3; ++st) {
+    for (const BatchGroup& gr : b->groups) {
+      BatchArgs a = group_args(b, gr, st);
+      void* args[] = {&a};
+      e = launch(gr.k.stage, dim3(gr.nitems), dim3(gr.k.block), args);
+      if (e != hipSuccess) return e;
+    }
+    frontier();
+  }
   return hipSuccess;
+}
+
+hipError_t run_step(idp_dg_batch* b, int mode) {
+  if (b->nitems == 0) return hipSuccess;
+  if (b->exec && b->graph_mode == mode) return hipGraphLaunch(b->exec, b->stream);
+  if (b->repeats >= 1) {  // the same configuration again: capture it
+    drop_batch_graph(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e == hipSuccess) e = emit_step(b, mode == 1, nullptr, g);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      b->exec = nullptr;
+      return e;
+    }
+    b->graph = g;
+    b->graph_mode = mode;
+    return hipGraphLaunch(b->exec, b->stream);
+  }
+  return emit_step(b, mode == 1, b->stream, nullptr);
+}
+
+int check_members(idp_dg* const* solves, int n, idp_dg_batch* b) {
+  if (!solves || n < 1) return bfail(b, IDP_DG_EINVAL, "need at least one solve");
+  for (int i = 0; i < n; ++i) {
+    if (!solves[i]) return bfail(b, IDP_DG_EINVAL, "NULL solve handle");
+    for (int j = 0; j < i; ++j)
+      if (solves[j] == solves[i]) return bfail(b, IDP_DG_EINVAL, "a handle appears twice");
+  }
+  for (int i = 1; i < n; ++i)
+    if (family(solves[i]) != family(solves[0]) || solves[i]->device != solves[0]->device)
+      return bfail(b, IDP_DG_EINVAL, "solves of one batch must share equation, gamma kind, dimension and device");
+  return 0;
 }
 
 int check_states(idp_dg_batch* b, double* const* u) {
@@ -221,70 +347,40 @@ extern "C" {
 int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_batch** out) {
   if (!out) return bfail(nullptr, IDP_DG_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!solves || n < 1) return bfail(nullptr, IDP_DG_EINVAL, "need at least one solve");
-  for (int i = 0; i < n; ++i) {
-    if (!solves[i]) return bfail(nullptr, IDP_DG_EINVAL, "NULL solve handle");
-    for (int j = 0; j < i; ++j)
-      if (solves[j] == solves[i]) return bfail(nullptr, IDP_DG_EINVAL, "a handle appears twice");
-  }
-  const int fam = family(solves[0]);
-  for (int i = 1; i < n; ++i)
-    if (family(solves[i]) != fam || solves[i]->device != solves[0]->device)
-      return bfail(nullptr, IDP_DG_EINVAL, "solves of one batch must share equation, gamma kind, dimension and device");
+  int rc = check_members(solves, n, nullptr);
+  if (rc) return rc;
   idp_dg_batch* b = new (std::nothrow) idp_dg_batch;
   if (!b) return bfail(nullptr, IDP_DG_ENOMEM, "host allocation failed");
-  b->s.assign(solves, solves + n);
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  b->fam = fam;
-  b->n = n;
-  std::vector<int> item_solve, item_tile, range(2 * n, 0);
-  for (int p = 1; p <= MAXP; ++p) {
-    BatchGroup gr;
-    gr.p = p;
-    gr.ofs = (int)item_solve.size();
-    for (int i = 0; i < n; ++i) {
-      if (solves[i]->d.p != p) continue;
-      if (batch_kernels(fam, p, &gr.k)) {
-        delete b;
-        return bfail(nullptr, IDP_DG_EINVAL, "no batched kernel for this degree");
-      }
-      const int epb = gr.k.tile_elems;
-      const int nt = (solves[i]->ne + epb - 1) / epb;
-      range[2 * i] = (int)item_solve.size();
-      for (int t = 0; t < nt; ++t) {
-        item_solve.push_back(i);
-        item_tile.push_back(t);
-      }
-      range[2 * i + 1] = (int)item_solve.size();
-    }
-    gr.nitems = (int)item_solve.size() - gr.ofs;
-    if (gr.nitems > 0) b->groups.push_back(gr);
-  }
-  b->nitems = (int)item_solve.size();
-  b->h_args.resize(3 * n);
-  b->h_dtargs.resize(n);
-  b->cur_u.assign(n, nullptr);
-  hipError_t e = hipMalloc(&b->d_args, sizeof(StageArgs) * 3 * n);
-  if (e == hipSuccess) e = hipMalloc(&b->d_dtargs, sizeof(MaxDtArgs) * n);
-  if (e == hipSuccess) e = hipMalloc(&b->d_item_solve, sizeof(int) * b->nitems);
-  if (e == hipSuccess) e = hipMalloc(&b->d_item_tile, sizeof(int) * b->nitems);
-  if (e == hipSuccess) e = hipMalloc(&b->d_range, sizeof(int) * 2 * n);
-  if (e == hipSuccess) e = hipMalloc(&b->d_partial, sizeof(double) * b->nitems);
-  if (e == hipSuccess) e = hipMalloc(&b->d_dt, sizeof(double) * 2 * n);
-  if (e == hipSuccess) e = hipHostMalloc(&b->h_ring, sizeof(double) * kRing * n, hipHostMallocDefault);
-  for (int r = 0; e == hipSuccess && r < kRing; ++r) e = hipEventCreateWithFlags(&b->ring_ev[r], hipEventDisableTiming);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_item_solve, item_solve.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_item_tile, item_tile.data(), sizeof(int) * b->nitems, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_range, range.data(), sizeof(int) * 2 * n, hipMemcpyHostToDevice);
+  hipError_t e = hipSuccess;
+  for (int r = 0; e == hipSuccess && r < kRing; ++r)
+    e = hipEventCreateWithFlags(&b->ring_ev[r], hipEventDisableTiming);
   if (e != hipSuccess) {
-    const int code = e == hipErrorOutOfMemory ? IDP_DG_ENOMEM : IDP_DG_EHIP;
-    bfail(nullptr, code, std::string("batch allocation: ") + hipGetErrorString(e));
+    bfail(nullptr, IDP_DG_EHIP, std::string("batch events: ") + hipGetErrorString(e));
     idp_dg_batch_destroy(b);
-    return code;
+    return IDP_DG_EHIP;
+  }
+  rc = idp_dg_batch_update(b, solves, n);
+  if (rc) {
+    g_batch_create_error = b->err;
+    idp_dg_batch_destroy(b);
+    return rc;
   }
   *out = b;
+  return 0;
+}
+
+int idp_dg_batch_update(idp_dg_batch* b, idp_dg* const* solves, int n) {
+  if (!b) return IDP_DG_EINVAL;
+  int rc = check_members(solves, n, b);
+  if (rc) return rc;
+  b->s.assign(solves, solves + n);
+  b->fam = family(solves[0]);
+  b->n = n;
+  std::vector<int> isolve, itile, range;
+  rc = plan(b, &isolve, &itile, &range);   // validates the degrees, sizes the blob
+  if (rc) return rc;
+  b->dirty = true;
   return 0;
 }
 
@@ -292,14 +388,11 @@ void idp_dg_batch_destroy(idp_dg_batch* b) {
   if (!b) return;
   drop_batch_graph(b);
   for (int r = 0; r < kRing; ++r)
-    if (b->ring_ev[r]) hipEventDestroy(b->ring_ev[r]);
-  hipFree(b->d_args);
-  hipFree(b->d_dtargs);
-  hipFree(b->d_item_solve);
-  hipFree(b->d_item_tile);
-  hipFree(b->d_range);
-  hipFree(b->d_partial);
-  hipFree(b->d_dt);
+    if (b->ring_ev[r]) {
+      (void)hipEventSynchronize(b->ring_ev[r]);
+      (void)hipEventDestroy(b->ring_ev[r]);
+    }
+  if (b->d_blob) (void)hipFree(b->d_blob);
   if (b->h_ring) (void)hipHostFree(b->h_ring);
   delete b;
 }
@@ -313,25 +406,20 @@ int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt) {
     if (!(dt[i] >= 0.0) || !std::isfinite(dt[i])) return bfail(b, IDP_DG_EINVAL, "dt must be finite and >= 0");
   int rc = check_states(b, u);
   if (rc) return rc;
-  // stage the time steps through a pinned ring slot (the slot is reused
-  // only after its copy has run)
+  rc = prepare(b, u, 0, 1.0);
+  if (rc) return rc;
+  // the time steps go through a staging slot of their own
   const int r = b->ring_next;
   b->ring_next = (r + 1) % kRing;
   hipError_t e = hipEventSynchronize(b->ring_ev[r]);
-  if (e != hipSuccess) return bhip(b, e, "ring event");
-  double* slot = b->h_ring + (size_t)r * b->n;
-  std::memcpy(slot, dt, sizeof(double) * b->n);
-  rc = set_args(b, u, b->d_dt, 1.0, 0);
-  if (rc) return rc;
-  e = hipMemcpyAsync(b->d_dt, slot, sizeof(double) * b->n, hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "staging event");
+  double* h = reinterpret_cast<double*>(b->h_ring + (size_t)r * b->h_cap);
+  std::memcpy(h, dt, sizeof(double) * b->n);
+  e = hipMemcpyAsync(at<double>(b->d_blob, b->o_dt), h, sizeof(double) * b->n, hipMemcpyHostToDevice,
+                     b->stream);
   if (e == hipSuccess) e = hipEventRecord(b->ring_ev[r], b->stream);
-  if (e != hipSuccess) return bhip(b, e, "dt upload");
-  if (!b->exec) {
-    e = build_graph(b, false);
-    if (e != hipSuccess) return bhip(b, e, "batch graph");
-  }
-  e = hipGraphLaunch(b->exec, b->stream);
-  if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+  if (e == hipSuccess) e = run_step(b, 0);
+  if (e != hipSuccess) return bhip(b, e, "batch step");
   return 0;
 }
 
@@ -340,28 +428,23 @@ int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl) {
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return bfail(b, IDP_DG_EINVAL, "cfl must be finite and > 0");
   int rc = check_states(b, u);
   if (rc) return rc;
-  double* bounds = b->d_dt + b->n;
-  rc = set_args(b, u, bounds, cfl, 1);
+  rc = prepare(b, u, 1, cfl);
   if (rc) return rc;
-  hipError_t e;
-  if (!b->exec) {
-    e = build_graph(b, true);
-    if (e != hipSuccess) return bhip(b, e, "batch graph");
-  }
-  e = hipGraphLaunch(b->exec, b->stream);
-  if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+  hipError_t e = run_step(b, 1);
+  if (e != hipSuccess) return bhip(b, e, "batch step");
   return 0;
 }
 
 int idp_dg_batch_last_dt(idp_dg_batch* b, double* dt) {
   if (!b || !dt) return IDP_DG_EINVAL;
+  if (!b->d_blob || b->cur_mode != 1) return bfail(b, IDP_DG_EINVAL, "no device-timestepped step has run");
   std::vector<double> v(b->n);
-  const double* bounds = b->d_dt + b->n;
+  const double* bounds = at<double>(b->d_blob, b->o_dt) + b->n;
   hipError_t e = hipMemcpyAsync(v.data(), bounds, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bhip(b, e, "batch dt copy");
   for (int i = 0; i < b->n; ++i) {
-    double d = b->cur_scale * v[i];  // the product the stage kernels form
+    const double d = b->cur_scale * v[i];  // the product the stage kernels form
     dt[i] = d < INFINITY ? d : 0.0;
   }
   return 0;

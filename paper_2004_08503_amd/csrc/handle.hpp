@@ -34,6 +34,7 @@ struct idp_dg {
   hipGraphExec_t exec = nullptr;
   double* g_u = nullptr;
   double g_cfl = 0.0;
+  bool owns = true;             // device buffers allocated by the handle (not a workspace)
   std::string err = "no error";
 };
 

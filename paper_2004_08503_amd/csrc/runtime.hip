@@ -310,7 +310,58 @@ __global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial,
 
 extern "C" {
 
+namespace {
+constexpr long long kWsAlign = 256;
+long long ws_up(long long x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// Offsets of the handle's device buffers in one workspace.
+struct WsLayout {
+  long long buf1, buf2, diag, dtdev, partial, total;
+};
+
+WsLayout ws_layout(const idp_dg_desc* d) {
+  const long long n1 = d->p + 1;
+  const long long ne = (long long)d->nx * d->ny;
+  const long long nn = ne * (d->dim == 2 ? n1 * n1 : n1);
+  const long long nc = d->eq == IDP_DG_EULER ? d->dim + 2 : 1;
+  WsLayout L;
+  L.buf1 = 0;
+  L.buf2 = ws_up(L.buf1 + 8 * nc * nn);
+  L.diag = ws_up(L.buf2 + 8 * nc * nn);
+  L.dtdev = ws_up(L.diag + (long long)sizeof(Diag));
+  L.partial = ws_up(L.dtdev + 64);
+  L.total = ws_up(L.partial + 8 * (ne + 64));
+  return L;
+}
+
+int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long ws_bytes, idp_dg** out);
+}  // namespace
+
 int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
+  return create_impl(desc, hip_stream, nullptr, 0, out);
+}
+
+long long idp_dg_workspace_bytes(const idp_dg_desc* desc) {
+  std::string why;
+  if (!desc_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  return ws_layout(desc).total;
+}
+
+int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream, void* workspace, long long bytes,
+                     idp_dg** out) {
+  if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kWsAlign)
+    return fail(nullptr, IDP_DG_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  std::string why;
+  if (!desc_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  if (bytes < ws_layout(desc).total) return fail(nullptr, IDP_DG_EINVAL, "workspace too small");
+  return create_impl(desc, hip_stream, static_cast<char*>(workspace), bytes, out);
+}
+
+namespace {
+int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long ws_bytes, idp_dg** out) {
+  (void)ws_bytes;
   if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
   *out = nullptr;
   std::string why;
@@ -349,6 +400,23 @@ int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
   for (int k = 0; k <= desc->p; ++k) h->T.iw[k] = 1.0 / h->T.w[k];
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
+  if (ws) {  // caller workspace: no allocation, diagnostics cleared on the stream
+    const WsLayout L = ws_layout(desc);
+    h->owns = false;
+    h->buf1 = reinterpret_cast<double*>(ws + L.buf1);
+    h->buf2 = reinterpret_cast<double*>(ws + L.buf2);
+    h->diag = reinterpret_cast<Diag*>(ws + L.diag);
+    h->dtdev = reinterpret_cast<double*>(ws + L.dtdev);
+    h->partial = reinterpret_cast<double*>(ws + L.partial);
+    e = hipMemsetAsync(h->diag, 0, sizeof(Diag), h->stream);
+    if (e != hipSuccess) {
+      fail(nullptr, IDP_DG_EHIP, std::string("workspace clear: ") + hipGetErrorString(e));
+      delete h;
+      return IDP_DG_EHIP;
+    }
+    *out = h;
+    return 0;
+  }
   const size_t bytes = sizeof(double) * h->nc * h->nn;
   e = hipMalloc(&h->buf1, bytes);
   if (e == hipSuccess) e = hipMalloc(&h->buf2, bytes);
@@ -366,16 +434,19 @@ int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
   *out = h;
   return 0;
 }
+}  // namespace
 
 void idp_dg_destroy(idp_dg* h) {
   if (!h) return;
   drop_graph(h);
   if (h->cap) hipStreamDestroy(h->cap);
-  hipFree(h->buf1);
-  hipFree(h->buf2);
-  hipFree(h->diag);
-  hipFree(h->dtdev);
-  hipFree(h->partial);
+  if (h->owns) {
+    hipFree(h->buf1);
+    hipFree(h->buf2);
+    hipFree(h->diag);
+    hipFree(h->dtdev);
+    hipFree(h->partial);
+  }
   delete h;
 }
 

@@ -41,6 +41,9 @@ def _declare(lib):
     H = ctypes.c_void_p
     sig = {
         "idp_dg_create": (ctypes.c_int, [ctypes.POINTER(Desc), _VP, ctypes.POINTER(H)]),
+        "idp_dg_workspace_bytes": (ctypes.c_longlong, [ctypes.POINTER(Desc)]),
+        "idp_dg_create_in": (ctypes.c_int, [ctypes.POINTER(Desc), _VP, _VP, ctypes.c_longlong,
+                                            ctypes.POINTER(H)]),
         "idp_dg_destroy": (None, [H]),
         "idp_dg_num_nodes": (ctypes.c_long, [H]),
         "idp_dg_num_comp": (ctypes.c_int, [H]),
@@ -56,6 +59,7 @@ def _declare(lib):
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
         "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
         "idp_dg_batch_destroy": (None, [H]),
+        "idp_dg_batch_update": (ctypes.c_int, [H, ctypes.POINTER(H), ctypes.c_int]),
         "idp_dg_batch_num_items": (ctypes.c_int, [H]),
         "idp_dg_batch_step": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_double)]),
         "idp_dg_batch_step_cfl": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.c_double]),
@@ -68,6 +72,13 @@ def _declare(lib):
         f.argtypes = args
     return lib
 
+
+# torch bundles its own HIP runtime (SONAME libamdhip64.so.7, loaded by
+# torch under another file name).  Loading torch first makes this library
+# bind to that same runtime by SONAME; loading this library first would put
+# a second HIP/HSA runtime into the process, and device initialisation in
+# one of them fails.
+import torch  # noqa: E402,F401
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libidp_dg.so is not built (run python -m paper_2004_08503_amd.build)")
@@ -99,6 +110,16 @@ def make_desc(prob):
     return d
 
 
+def family_of(prob):
+    """Batches group solves of one kernel family: equation (Euler split by
+    gamma = 7/5, 5/3 or other) and dimension."""
+    eq = int(prob.eq)
+    if eq == EULER:
+        g = float(prob.gamma)
+        eq = 10 + (0 if g == 1.4 else 1 if abs(g - 5.0 / 3.0) < 1e-15 else 2)
+    return eq * 10 + int(prob.dim)
+
+
 def _torch():
     import torch
     return torch
@@ -107,16 +128,29 @@ def _torch():
 class Solver:
     """One problem on the current device and torch stream."""
 
-    def __init__(self, prob, stream=None):
+    def __init__(self, prob, stream=None, workspace=False):
+        """workspace=True places the handle's device buffers in a torch
+        allocation (stream-ordered, no hipMalloc/hipFree by the library)."""
         torch = _torch()
         self.prob = prob
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
+        self._ws = None
         desc = make_desc(prob)
-        rc = lib.idp_dg_create(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream),
-                               ctypes.byref(self._h))
+        if workspace:
+            nbytes = lib.idp_dg_workspace_bytes(ctypes.byref(desc))
+            if nbytes < 0:
+                raise IdpError(int(nbytes), lib.idp_dg_last_error(None).decode())
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            ofs = (-base) % 256
+            rc = lib.idp_dg_create_in(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream),
+                                      ctypes.c_void_p(base + ofs), nbytes, ctypes.byref(self._h))
+        else:
+            rc = lib.idp_dg_create(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(self._h))
         if rc:
             raise IdpError(rc, lib.idp_dg_last_error(None).decode())
         self.nc = lib.idp_dg_num_comp(self._h)
@@ -130,6 +164,7 @@ class Solver:
         if self._h:
             lib.idp_dg_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None   # torch frees it in stream order
 
     def __del__(self):
         try:
@@ -242,6 +277,15 @@ class Batch:
     def _check(self, rc):
         if rc:
             raise IdpError(rc, lib.idp_dg_batch_last_error(self._b).decode())
+
+    def update(self, solvers):
+        """Change the member solves, keeping the batch's device storage."""
+        solvers = list(solvers)
+        hs = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
+        self._check(lib.idp_dg_batch_update(self._b, hs, len(solvers)))
+        self.solvers = solvers
+        self.n = len(solvers)
+        self.num_items = lib.idp_dg_batch_num_items(self._b)
 
     def _ptrs(self, us):
         if len(us) != self.n:

@@ -202,3 +202,78 @@ def small_cases():
         burgers_2d(n=16, p=3),
         euler_2d(n=16, p=4),
     ]
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: a seeded Poisson stream of solve requests (Burgers and
+# Euler), with initial states generated on the device so that admitting a
+# large request does not stall on the host.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Request:
+    rid: int
+    kind: str           # "euler" or "burgers"
+    n: int              # elements per direction
+    p: int
+    steps: int
+    arrival: float      # seconds after the start of the stream
+    seed: int
+
+    def problem(self) -> Problem:
+        if self.kind == "euler":
+            return Problem(dim=2, nx=self.n, ny=self.n, p=self.p, eq=EULER, gamma=1.4)
+        return Problem(dim=2, nx=self.n, ny=self.n, p=self.p, eq=BURGERS, vel=(1.0, 1.0))
+
+
+def request_stream(count: int, rate: float, n_range=(16, 512), p_range=(2, 6),
+                   steps_range=(20, 200), seed: int = 5) -> List[Request]:
+    """Poisson arrivals at `rate` requests/s; half Burgers, half Euler."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        out.append(Request(rid=i, kind="euler" if rng.random() < 0.5 else "burgers",
+                           n=int(rng.integers(n_range[0], n_range[1] + 1)),
+                           p=int(rng.integers(p_range[0], p_range[1] + 1)),
+                           steps=int(rng.integers(steps_range[0], steps_range[1] + 1)),
+                           arrival=t, seed=int(rng.integers(1 << 31))))
+    return out
+
+
+def initial_state_device(req: Request, device="cuda"):
+    """The request's initial state, generated with torch on the device:
+    Euler four-quadrant data with 1% density noise, or the Burgers recipe
+    (0.5 + 0.5 sin sin + 0.05 noise + 0.5 step)."""
+    import torch
+    prob = req.problem()
+    n1 = prob.p + 1
+    xi = torch.tensor(gl_points(prob.p), dtype=torch.float64, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(req.seed)
+    h = 1.0 / req.n
+    e = torch.arange(req.n, dtype=torch.float64, device=device)
+    # node coordinates in layout [ey][ex][b][a]
+    x = ((e[None, :, None, None] + xi[None, None, None, :]) * h).expand(req.n, req.n, n1, n1)
+    y = ((e[:, None, None, None] + xi[None, None, :, None]) * h).expand(req.n, req.n, n1, n1)
+    xc = ((e[None, :, None, None] + 0.5) * h).expand(req.n, req.n, n1, n1)
+    yc = ((e[:, None, None, None] + 0.5) * h).expand(req.n, req.n, n1, n1)
+    if req.kind == "burgers":
+        u = 0.5 + 0.5 * torch.sin(2 * np.pi * x) * torch.sin(2 * np.pi * y)
+        u = u + 0.05 * (2 * torch.rand(u.shape, generator=gen, dtype=torch.float64, device=device) - 1)
+        u = u + 0.5 * (xc > 0.5).double()
+        return u.reshape(1, -1).contiguous()
+    rng = np.random.default_rng(req.seed)
+    rho_p = torch.tensor(rng.uniform(0.1, 1.5, size=(4, 2)), dtype=torch.float64, device=device)
+    vel = torch.tensor(rng.uniform(-0.8, 0.8, size=(4, 2)), dtype=torch.float64, device=device)
+    q = ((xc > 0.5).long() + 2 * (yc > 0.5).long()).reshape(-1)
+    noise = 2 * torch.rand(q.shape, generator=gen, dtype=torch.float64, device=device) - 1
+    rho = rho_p[q, 0] * (1.0 + 0.01 * noise)
+    pr = rho_p[q, 1]
+    u = torch.empty((4, q.numel()), dtype=torch.float64, device=device)
+    u[0] = rho
+    u[1] = rho * vel[q, 0]
+    u[2] = rho * vel[q, 1]
+    u[3] = pr / (prob.gamma - 1.0) + 0.5 * rho * (vel[q, 0] ** 2 + vel[q, 1] ** 2)
+    return u

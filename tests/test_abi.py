@@ -50,3 +50,25 @@ def test_null_safety():
     assert lib.idp_dg_create(None, None, ctypes.byref(h)) == idp_dg.EINVAL
     d = idp_dg.make_desc(Problem(dim=2, nx=4, ny=4, p=3, eq=BURGERS))
     assert lib.idp_dg_create(ctypes.byref(d), None, None) == idp_dg.EINVAL
+
+
+def test_workspace_size_and_validation():
+    lib = idp_dg.lib
+    prob = Problem(dim=2, nx=8, ny=6, p=4, eq=EULER)
+    d = idp_dg.make_desc(prob)
+    n = lib.idp_dg_workspace_bytes(ctypes.byref(d))
+    # two stage buffers of nc * Nn doubles dominate
+    assert n >= 2 * 8 * 4 * prob.num_nodes
+    assert n % 256 == 0
+    bad = idp_dg.make_desc(prob.replace(p=0))
+    assert lib.idp_dg_workspace_bytes(ctypes.byref(bad)) == idp_dg.EINVAL
+    h = ctypes.c_void_p()
+    # NULL, misaligned or too small workspaces are rejected before any GPU call
+    assert lib.idp_dg_create_in(ctypes.byref(d), None, None, n, ctypes.byref(h)) == idp_dg.EINVAL
+    assert lib.idp_dg_create_in(ctypes.byref(d), None, ctypes.c_void_p(256 + 8), n,
+                                ctypes.byref(h)) == idp_dg.EINVAL
+    assert lib.idp_dg_create_in(ctypes.byref(d), None, ctypes.c_void_p(4096), n - 1,
+                                ctypes.byref(h)) == idp_dg.EINVAL
+    assert not h.value
+    assert lib.idp_dg_batch_update(None, None, 0) == idp_dg.EINVAL
+    assert lib.idp_dg_batch_create(None, 0, None, ctypes.byref(h)) == idp_dg.EINVAL

@@ -1,0 +1,50 @@
+"""Serving loop: requests that arrive while others run are admitted by HBM
+footprint and co-batched; every result must be bitwise the same as the
+request solved alone through the plain path."""
+import pytest
+
+from paper_2004_08503_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08503_amd import idp_dg, serve
+    return idp_dg, serve
+
+
+def alone(idp_dg, req):
+    sv = idp_dg.Solver(req.problem())
+    u = W.initial_state_device(req)
+    for _ in range(req.steps):
+        sv.step_cfl(u, 0.5)
+    out = u.cpu()
+    sv.close()
+    return out
+
+
+@pytest.mark.parametrize("budget_mb", [4096, 3], ids=["roomy", "one-at-a-time"])
+def test_served_results_equal_alone(budget_mb):
+    idp_dg, serve = _mods()
+    reqs = W.request_stream(10, rate=400.0, n_range=(4, 14), p_range=(2, 5),
+                            steps_range=(3, 9), seed=11)
+    srv = serve.Server(hbm_budget=budget_mb * 2 ** 20, keep_results=True)
+    done = srv.run(reqs)
+    assert [d.rid for d in done] == [r.rid for r in reqs]
+    for d, r in zip(done, reqs):
+        assert d.finished >= d.arrival - 1e-3
+        assert torch.equal(d.result, alone(idp_dg, r)), r
+    s = serve.summarize(done)
+    assert s["tts_s_p99"] >= s["tts_s_p50"] > 0
+
+
+def test_fifo_plain_matches():
+    idp_dg, serve = _mods()
+    reqs = W.request_stream(4, rate=1000.0, n_range=(4, 8), p_range=(2, 3),
+                            steps_range=(2, 4), seed=3)
+    done = serve.run_fifo_plain(reqs, keep_results=True)
+    for d, r in zip(done, reqs):
+        assert torch.equal(d.result, alone(idp_dg, r))
