@@ -71,7 +71,9 @@ struct idp_dg_batch {
   int repeats = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t graph_done = nullptr;  // recorded after every launch of exec
   int graph_mode = -1;
+  std::vector<RetiredGraph> retired;
   std::string err = "no error";
 };
 
@@ -89,11 +91,14 @@ int bhip(idp_dg_batch* b, hipError_t e, const char* where) {
 }
 
 void drop_batch_graph(idp_dg_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  retire_graph(&b->retired, &b->graph, &b->exec, &b->graph_done);
   b->graph_mode = -1;
+}
+
+hipError_t launch_graph(idp_dg_batch* b) {
+  hipError_t e = hipGraphLaunch(b->exec, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->graph_done, b->stream);
+  return e;
 }
 
 bool overlap(const double* a, long long na, const double* c, long long nc) {
@@ -289,21 +294,21 @@ hipError_t emit_step(idp_dg_batch* b, bool device_dt, hipStream_t s, hipGraph_t 
 
 hipError_t run_step(idp_dg_batch* b, int mode) {
   if (b->nitems == 0) return hipSuccess;
-  if (b->exec && b->graph_mode == mode) return hipGraphLaunch(b->exec, b->stream);
+  if (b->exec && b->graph_mode == mode) return launch_graph(b);
   if (b->repeats >= 1) {  // the same configuration again: capture it
     drop_batch_graph(b);
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     if (e == hipSuccess) e = emit_step(b, mode == 1, nullptr, g);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->graph_done, hipEventDisableTiming);
+    b->graph = g;
     if (e != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      b->exec = nullptr;
+      drop_batch_graph(b);
       return e;
     }
-    b->graph = g;
     b->graph_mode = mode;
-    return hipGraphLaunch(b->exec, b->stream);
+    return launch_graph(b);
   }
   return emit_step(b, mode == 1, b->stream, nullptr);
 }
@@ -387,6 +392,7 @@ int idp_dg_batch_update(idp_dg_batch* b, idp_dg* const* solves, int n) {
 void idp_dg_batch_destroy(idp_dg_batch* b) {
   if (!b) return;
   drop_batch_graph(b);
+  reap_graphs(&b->retired, true);
   for (int r = 0; r < kRing; ++r)
     if (b->ring_ev[r]) {
       (void)hipEventSynchronize(b->ring_ev[r]);

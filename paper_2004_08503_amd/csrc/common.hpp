@@ -100,6 +100,15 @@ struct BatchKernels {
   int tile_elems;            // elements per tile
 };
 
+// A graph whose last launch may still run: destroyed only once its event
+// has completed (destroying a graph exec that is executing would free
+// runtime objects the launch still uses).
+struct RetiredGraph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipEvent_t done;
+};
+
 // Kernel launchers, one translation unit per (equation, dimension).
 // Return hipSuccess or the launch error; variant selects elements-per-block.
 #define IDP_DECLARE_LAUNCHERS(NAME)                                               \

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/idp_dg.h"
 #include "common.hpp"
@@ -32,8 +33,10 @@ struct idp_dg {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t g_done = nullptr;   // recorded after every launch of exec
   double* g_u = nullptr;
   double g_cfl = 0.0;
+  std::vector<idp::RetiredGraph> retired;
   bool owns = true;             // device buffers allocated by the handle (not a workspace)
   std::string err = "no error";
 };
@@ -47,4 +50,8 @@ idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double*
 idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
 int batch_kernels(int fam, int p, idp::BatchKernels* k);
+// Retire (graph, exec, event) and destroy retired graphs whose launches
+// have completed; with wait, block until all have completed.
+void retire_graph(std::vector<idp::RetiredGraph>* list, hipGraph_t* g, hipGraphExec_t* e, hipEvent_t* ev);
+void reap_graphs(std::vector<idp::RetiredGraph>* list, bool wait);
 }  // namespace idp_host

@@ -224,6 +224,33 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   return a;
 }
 
+void retire_graph(std::vector<RetiredGraph>* list, hipGraph_t* g, hipGraphExec_t* e, hipEvent_t* ev) {
+  if (*e || *g) list->push_back(RetiredGraph{*g, *e, *ev});
+  else if (*ev) (void)hipEventDestroy(*ev);
+  *g = nullptr;
+  *e = nullptr;
+  *ev = nullptr;
+  reap_graphs(list, false);
+}
+
+void reap_graphs(std::vector<RetiredGraph>* list, bool wait) {
+  size_t keep = 0;
+  for (size_t i = 0; i < list->size(); ++i) {
+    RetiredGraph& r = (*list)[i];
+    if (r.done) {
+      if (wait) (void)hipEventSynchronize(r.done);
+      else if (hipEventQuery(r.done) == hipErrorNotReady) {
+        (*list)[keep++] = r;
+        continue;
+      }
+    }
+    if (r.exec) (void)hipGraphExecDestroy(r.exec);
+    if (r.graph) (void)hipGraphDestroy(r.graph);
+    if (r.done) (void)hipEventDestroy(r.done);
+  }
+  list->resize(keep);
+}
+
 int batch_kernels(int fam, int p, BatchKernels* k) {
   switch (fam) {
     case 0: return batch_kernels_adv1(p, k);
@@ -251,10 +278,7 @@ bool overlaps(const double* a, const double* b, long long n) {
 }
 
 void drop_graph(idp_dg* h) {
-  if (h->exec) hipGraphExecDestroy(h->exec);
-  if (h->graph) hipGraphDestroy(h->graph);
-  h->exec = nullptr;
-  h->graph = nullptr;
+  retire_graph(&h->retired, &h->graph, &h->exec, &h->g_done);
   h->g_u = nullptr;
 }
 
@@ -439,6 +463,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
 void idp_dg_destroy(idp_dg* h) {
   if (!h) return;
   drop_graph(h);
+  reap_graphs(&h->retired, true);
   if (h->cap) hipStreamDestroy(h->cap);
   if (h->owns) {
     hipFree(h->buf1);
@@ -524,8 +549,11 @@ int idp_dg_step_cfl(idp_dg* h, double* u, double cfl) {
     if (e != hipSuccess) { drop_graph(h); return hip_fail(h, e, "hipGraphInstantiate"); }
     h->g_u = u;
     h->g_cfl = cfl;
+    e = hipEventCreateWithFlags(&h->g_done, hipEventDisableTiming);
+    if (e != hipSuccess) { drop_graph(h); return hip_fail(h, e, "hipEventCreate"); }
   }
   e = hipGraphLaunch(h->exec, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(h->g_done, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
   return 0;
 }

@@ -124,3 +124,35 @@ def test_batch_scalar_family():
     torch.cuda.synchronize()
     for a, b in zip(ub, up):
         assert torch.equal(a, b)
+
+
+def test_batch_membership_changes_while_graphs_run():
+    """Alternating memberships without host synchronisation: each change
+    retires a step graph whose launch is still queued.  Every solve must
+    still equal its plain run, step for step."""
+    idp_dg = _lib()
+    cases = mix(count=6, seed=9)
+    solvers = [idp_dg.Solver(p) for p, _ in cases]
+    ub = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    up = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    counts = [0] * len(cases)
+    batch = idp_dg.Batch(solvers)
+    subsets = [list(range(6)), list(range(6)), [0, 2, 4], [0, 2, 4], [0, 2, 4], [1, 5]]
+    prev = subsets[0]
+    for rnd in range(5):
+        for ids in subsets:
+            if ids != prev:   # same membership twice in a row: the step runs as a graph
+                batch.update([solvers[i] for i in ids])
+                prev = ids
+            batch.step_cfl([ub[i] for i in ids], 0.5)
+            for i in ids:
+                counts[i] += 1
+    for sv, u, k in zip(solvers, up, counts):
+        for _ in range(k):
+            sv.step_cfl(u, 0.5)
+    torch.cuda.synchronize()
+    for a, b in zip(ub, up):
+        assert torch.equal(a, b)
+    batch.close()
+    for sv in solvers:
+        sv.close()
