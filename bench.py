@@ -126,22 +126,24 @@ def batched_leg(steps, count=64):
     }
 
 
-def serving_leg(count, load, capacity, budget_gb=64.0):
+def serving_leg(count, load, budget_gb=64.0):
     """The served workload: a seeded Poisson stream of `count` requests (half
-    Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps), rate set
-    for the given offered load of `capacity` DOF-updates/s.  Run once through
-    the continuous-batching server and once FIFO through the plain path."""
+    Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps).  The
+    arrival rate is set for the given offered load of the plain path's own
+    capacity on this stream, measured by running the same requests back to
+    back, one at a time.  The stream then runs once through the
+    continuous-batching server and once FIFO through the plain path."""
     from paper_2004_08503_amd import serve, workloads as W
-    probe = W.request_stream(count, rate=1.0, seed=5)
-    mean_work = np.mean([3.0 * r.problem().num_nodes * r.steps for r in probe])
-    rate = load * capacity / mean_work
+    back_to_back = W.request_stream(count, rate=1e9, seed=5)
+    busy = serve.summarize(serve.run_fifo_plain(back_to_back))["makespan_s"]
+    rate = load * count / busy
     reqs = W.request_stream(count, rate=rate, seed=5)
     srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
     served = serve.summarize(srv.run(reqs))
     fifo = serve.summarize(serve.run_fifo_plain(reqs))
     return {"workload": "served_stream_%d_requests_burgers_euler_n16-512_p2-6_steps20-200" % count,
-            "offered_load": load, "rate_per_s": rate, "hbm_budget_gb": budget_gb,
-            "served": served, "fifo_plain": fifo}
+            "offered_load": load, "plain_service_s": busy, "rate_per_s": rate,
+            "hbm_budget_gb": budget_gb, "served": served, "fifo_plain": fifo}
 
 
 def main():
@@ -266,8 +268,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_steps)
     if args.serve_requests > 0:
-        cap = out["batched"]["value"] if "batched" in out else value
-        out["serving"] = serving_leg(args.serve_requests, args.serve_load, cap)
+        out["serving"] = serving_leg(args.serve_requests, args.serve_load)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, dt_last)
     print(json.dumps(out))
