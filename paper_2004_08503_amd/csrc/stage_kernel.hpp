@@ -58,7 +58,7 @@ struct Cfg {
   // region C (after B, aliases the dead tail of A): Euler search data
   static constexpr int C_UL = B_END;                                   // [NC][EPB*NP]
   static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * EPB * NP : 0);
-  static constexpr int C_AZ = C_KM + (is_euler(EQ) ? EPB * NP : 0);
+  static constexpr int C_AZ = C_KM + (is_euler(EQ) ? EPB * NP : 0);   // bound U of the node
   static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
   static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * EPB * NP : 0);
   static constexpr int AB = A_END > C_END ? A_END : C_END;
@@ -118,21 +118,26 @@ __device__ inline double ipow_c(double x) {
   else return x * ipow_c<N - 1>(x);
 }
 
-// x^(-1/N) in binary64 for x > 0: a single-precision seed from the hardware
-// log2/exp2, then three Newton steps y <- y (1 + (1 - x y^N)/N), which
-// converge quadratically from the seed's ~1e-7 to a few ulp.  Arguments
-// outside the normal single-precision range use pow.
+// x^(-1/N) in binary64 for x > 0, without branches.  Range reduction:
+// x = m 2^e with m in [1/2, 1) and e = N q + r (0 <= r < N), so that
+// x^(-1/N) = 2^-q (m 2^r)^(-1/N) with m 2^r in [1/2, 2^(N-1)).  On that
+// range the single-precision log2/exp2 seed is within 1e-6 (relative), and
+// two Newton steps y <- y (1 + (1 - x y^N)/N) bring the error to
+// ((N+1)/2)^3 1e-24, below the binary64 rounding of the last step.
+// Non-positive, infinite or NaN x give NaN or infinity.
 template <int N>
 __device__ inline double inv_root(double x) {
-  const float xf = (float)x;
-  if (!(xf > 1e-36f && xf < 1e36f)) return pow(x, -1.0 / N);
-  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (-1.0f / N));
+  int e;
+  const double m = frexp(x, &e);
+  const int q = (e + 1100 * N) / N - 1100;   // floor(e / N) for e >= -1100 N
+  const double xr = ldexp(m, e - N * q);
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)xr) * (-1.0f / N));
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const double e = fma(-x, ipow_c<N>(y), 1.0);
-    y = fma(y * e, 1.0 / N, y);
+  for (int i = 0; i < 2; ++i) {
+    const double r = fma(-xr, ipow_c<N>(y), 1.0);
+    y = fma(y * r, 1.0 / N, y);
   }
-  return y;
+  return ldexp(y, -q);
 }
 
 // Euler auxiliaries of one state: X = (1/rho, p, c, p^-(gamma-1)/(2gamma),
@@ -229,22 +234,21 @@ struct PhiVal {
 template <int DIM, int GN>
 __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, double kmin,
                                 const Phys& ph) {
+  // straight-line code (no branches), so that independent evaluations
+  // interleave; a non-positive density gives phi = -infinity
   PhiVal r;
   r.rho = fma(t, P[0], uL[0]);
-  if (!(r.rho > 0.0)) {
-    r.phi = -INFINITY;
-    r.dphi = 0.0;
-    return r;
-  }
+  const bool pos = r.rho > 0.0;
+  const double rho = pos ? r.rho : 1.0;
   const double g = ph.gamma;
   double rinv, rg;
   if constexpr (GN > 0) {  // z = rho^(-1/n): 1/rho = z^n, rho^gamma = rho^2 z^(n-2)
-    const double z = inv_root<GN>(r.rho);
+    const double z = inv_root<GN>(rho);
     rinv = ipow_c<GN>(z);
-    rg = (r.rho * r.rho) * ipow_c<GN - 2>(z);
+    rg = (rho * rho) * ipow_c<GN - 2>(z);
   } else {
-    rinv = 1.0 / r.rho;
-    rg = pow(r.rho, g);
+    rinv = 1.0 / rho;
+    rg = pow(rho, g);
   }
   double mm = 0.0, mp = 0.0;
 #pragma unroll
@@ -255,72 +259,85 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
   }
   const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
   const double kg = kmin / (g - 1.0);
-  r.phi = E - 0.5 * mm * rinv - kg * rg;
-  r.dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
+  const double phi = E - 0.5 * mm * rinv - kg * rg;
+  const double dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
+  r.phi = pos ? phi : -INFINITY;
+  r.dphi = pos ? dphi : 0.0;
   return r;
 }
 
-// sup { t in [0,T] : uL + t P admissible }.  Newton from the infeasible
-// side: the tangent of a concave function overshoots its root from above,
-// so the iterates decrease monotonically onto the root (bisection steps
-// while the density is not positive).  Near the root Phi is only known to
-// rounding, so once the steps stall the search steps back geometrically
-// from the last infeasible point to the nearest feasible one.  The result
-// is feasible and within a few rounding widths of the supremum.
-// Called for a partial state that is admissible at t = 0 and not at t = T.
+__device__ inline bool admissible(const PhiVal& e) { return e.rho > 0.0 && e.phi >= 0.0; }
+
+// The smallest root over the faces of one node.  The node's search data
+// (from the checks at t = alpha): U, the smallest tangent bound over its
+// failing faces (every root lies below its own face's tangent bound, so the
+// node's answer is at most U).  A face searches
+// sup { t in [0, U] : uL + t P admissible }:
+//  - the first point is U itself: for the face that set U it is a Newton
+//    step from alpha (tangent), for the others a probe, and an admissible
+//    probe means the face cannot lower the node's answer below U;
+//  - then Newton steps from the infeasible end hi (Phi is concave wherever
+//    rho > 0, so the tangent at hi cuts zero at or above the root), each a
+//    single evaluation; a tangent step that lands admissible is within
+//    rounding of the root and ends the search; without a usable tangent
+//    (rho <= 0 at hi), or after three Newton steps in a row that do not
+//    halve (convergence slower than quadratic), one bisection; once the
+//    Newton step is below half the tolerance, hi sits on the root and the
+//    next points are probes under hi at half the tolerance, doubling the
+//    distance after each inadmissible probe;
+//  - the search stops once the bracket is narrower than 1e-15 or than
+//    1e-14 max|uL| / max|P| (the admissible end it returns then moves the
+//    state by less than 1e-14 of its size from any point of the bracket,
+//    the supremum included), and returns the admissible end.
 template <int DIM, int GN>
-__device__ double entropy_root(const double* uL, const double* P, double T, double kmin,
+__device__ double entropy_root(const double* uL, const double* P, double U, bool tang, double kmin,
                                const Phys& ph) {
-  PhiVal er = phi_at<DIM, GN>(T, uL, P, kmin, ph);
-  double tl = 0.0, tr = T;
-  bool done = false;
+  double us = 0.0, ps = 0.0;
+#pragma unroll
+  for (int c = 0; c < DIM + 2; ++c) {
+    us = fmax(us, fabs(uL[c]));
+    ps = fmax(ps, fabs(P[c]));
+  }
+  const double tol = fmax(1e-15, 1e-14 * us / ps);
+  double lo = 0.0, hi = U, fhi = -INFINITY, dhi = 0.0, rhi = 0.0;
+  double t = U, prev = INFINITY, probe = 0.5 * tol;
+  int slow = 0;
   for (int it = 0; it < 64; ++it) {
-    if (tr - tl <= 1e-15) {
-      done = true;
-      break;
+    const PhiVal e = phi_at<DIM, GN>(t, uL, P, kmin, ph);
+    if (admissible(e)) {
+      if (tang || t >= U) return t;
+      lo = t;
+    } else {
+      hi = t;
+      fhi = e.phi;
+      dhi = e.dphi;
+      rhi = e.rho;
     }
-    if (er.rho > 0.0 && er.dphi < 0.0 && er.phi > -INFINITY) {
-      const double tn = tr - er.phi / er.dphi;
-      if (!(tn < tr)) break;  // step below rounding: tr sits on the root
-      if (!(tn > tl)) {       // the root is within rounding of tl
-        done = true;
-        break;
-      }
-      const PhiVal en = phi_at<DIM, GN>(tn, uL, P, kmin, ph);
-      if (en.rho > 0.0 && en.phi >= 0.0) {
-        tl = tn;  // a tangent step lands feasible only within rounding of the root
-        done = true;
-        break;
-      }
-      const double step = tr - tn;
-      tr = tn;
-      er = en;
-      if (step <= 1e-14) break;
-    } else {  // no usable tangent (density not positive at tr): bisect
-      const double tn = 0.5 * (tl + tr);
-      const PhiVal en = phi_at<DIM, GN>(tn, uL, P, kmin, ph);
-      if (en.rho > 0.0 && en.phi >= 0.0) {
-        tl = tn;
+    if (!(hi - lo > tol)) break;
+    tang = false;
+    if (rhi > 0.0 && dhi < 0.0) {
+      const double step = fhi / dhi;  // the Newton step from hi, >= 0
+      if (step < 0.5 * tol) {         // hi sits on the root: probe under it
+        t = hi - probe;
+        probe *= 2.0;
+      } else if (slow >= 3) {
+        t = 0.5 * (lo + hi);
+        slow = 0;
       } else {
-        tr = tn;
-        er = en;
+        t = hi - step;
+        tang = true;
+        slow = step > 0.5 * prev ? slow + 1 : 0;
+        prev = step;
       }
+    } else {
+      t = 0.5 * (lo + hi);
+    }
+    if (!(t > lo && t < hi)) {
+      t = 0.5 * (lo + hi);
+      tang = false;
     }
   }
-  if (!done) {
-    double d = 4.5e-16 * tr;
-    for (int j = 0; j < 64; ++j) {
-      const double tb = tr - d;
-      if (!(tb > tl)) break;
-      const PhiVal eb = phi_at<DIM, GN>(tb, uL, P, kmin, ph);
-      if (eb.rho > 0.0 && eb.phi >= 0.0) {
-        tl = tb;
-        break;
-      }
-      d *= 2.0;
-    }
-  }
-  return tl;
+  return lo;
 }
 
 __device__ inline const Phys& ph_of(const StageArgs& A) { return A.ph; }
@@ -579,8 +596,13 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
       az_dbg = alpha;
       if constexpr (is_euler(EQ)) {
         // every partial state uL + t 2d dt/m (+-rbar) must stay admissible
-        // for t <= alpha (eq. convex-provisional); faces whose partial
-        // state fails at t = alpha go to the workgroup's search list
+        // for t <= alpha (eq. convex-provisional).  Each face whose partial
+        // state fails at t = alpha brackets its own root: the tangent at
+        // alpha cuts zero above it, the chord from t = 0 below it (Phi is
+        // concave).  The node needs only the smallest root, which lies in
+        // [min of the lower bounds, U = min of the upper bounds]; faces whose
+        // lower bound is at least U cannot hold it, the others go to the
+        // workgroup's search list with the node's bracket.
         double kmin = INFINITY;
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
@@ -588,6 +610,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dtm;
         int act = 0;
+        PhiVal ef[2 * DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
 #pragma unroll
@@ -602,30 +625,47 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
               nz |= cf != 0.0;
               Pv[c] = g2 * cf;
             }
-            if (nz) {
-              const PhiVal e = phi_at<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ph_of(A));
-              if (!(e.rho > 0.0 && e.phi >= 0.0)) act |= 1 << (2 * k + sd);
-            }
+            ef[2 * k + sd] = phi_at<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ph_of(A));
+            if (nz && !admissible(ef[2 * k + sd])) act |= 1 << (2 * k + sd);
           }
         }
         if (act) {
           const double zero[NC] = {};
           const PhiVal e0 = phi_at<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ph_of(A));
-          if (!(e0.rho > 0.0 && e0.phi >= 0.0)) {  // u^L itself off the set by rounding
+          if (!admissible(e0)) {  // u^L itself off the set by rounding
             alpha = 0.0;
             act = 0;
+          } else {
+            double tup[2 * DIM], tlo[2 * DIM], ub = alpha;
+#pragma unroll
+            for (int f = 0; f < 2 * DIM; ++f) {
+              const PhiVal& e = ef[f];
+              double tn = e.rho > 0.0 && e.dphi < 0.0 ? alpha - e.phi / e.dphi : alpha;
+              tn = fmin(fmax(tn, 0.0), alpha);
+              double tl = e.rho > 0.0 ? alpha * (e0.phi / (e0.phi - e.phi)) : 0.0;
+              tl = fmin(fmax(tl, 0.0), tn);
+              tup[f] = tn;
+              tlo[f] = tl;
+              if (act & (1 << f)) ub = fmin(ub, tn);
+            }
+            int keep = 0;
+#pragma unroll
+            for (int f = 0; f < 2 * DIM; ++f)
+              if ((act & (1 << f)) && tlo[f] < ub) keep |= 1 << f;
+            if (!keep) {  // the bounds meet: the smallest root is ub
+              alpha = ub;
+            } else {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
+              lds[C::C_KM + tid] = kmin;
+              lds[C::C_AZ + tid] = ub;
+              int* list = reinterpret_cast<int*>(lds + C::C_LIST);
+              int* count = reinterpret_cast<int*>(lds + C::S_LN);
+#pragma unroll
+              for (int f = 0; f < 2 * DIM; ++f)
+                if (keep & (1 << f)) list[atomicAdd(count, 1)] = tid * 8 + f * 2 + (tup[f] <= ub ? 1 : 0);
+            }
           }
-        }
-        if (act) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
-          lds[C::C_KM + tid] = kmin;
-          lds[C::C_AZ + tid] = alpha;
-          int* list = reinterpret_cast<int*>(lds + C::C_LIST);
-          int* count = reinterpret_cast<int*>(lds + C::S_LN);
-#pragma unroll
-          for (int f = 0; f < 2 * DIM; ++f)
-            if (act & (1 << f)) list[atomicAdd(count, 1)] = tid * 4 + f;
         }
       }
     }
@@ -638,7 +678,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
     const int* list = reinterpret_cast<const int*>(lds + C::C_LIST);
     for (int w = tid; w < nact; w += C::BS) {
       const int item = list[w];
-      const int node = item >> 2, f = item & 3, k = f >> 1, sd = f & 1;
+      const int node = item >> 3, f = (item >> 1) & 3, k = f >> 1, sd = f & 1;
       const int nle = node / NP, ns = node - nle * NP;
       const int na = DIM == 2 ? ns % N1 : ns;
       const int nb = DIM == 2 ? ns / N1 : 0;
@@ -651,7 +691,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
         ul[c] = lds[C::C_UL + c * EPB * NP + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
       }
-      const double t = entropy_root<DIM, gn_of(EQ)>(ul, Pv, lds[C::C_AZ + node], lds[C::C_KM + node], ph_of(A));
+      const double t = entropy_root<DIM, gn_of(EQ)>(ul, Pv, lds[C::C_AZ + node], (item & 1) != 0,
+                                                    lds[C::C_KM + node], ph_of(A));
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
     }
