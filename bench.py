@@ -70,7 +70,7 @@ def batched_leg(steps, count=64):
     """The batched workload: `count` independent Euler solves (n in
     [32, 256], p in {2..6}, seeded quadrant data), stepped (a) one solve per
     launch, each through its own cached graph, and (b) all together, one
-    persistent launch per stage through one cached graph.  Per-round (one
+    work-list launch per degree and stage, through one cached graph.  Per-round (one
     step of every solve) latencies from HIP events."""
     import torch
     from paper_2004_08503_amd import idp_dg, workloads as W

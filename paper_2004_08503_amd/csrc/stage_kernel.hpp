@@ -429,11 +429,11 @@ __device__ inline void load_tables(double* sw, double* sq, double* siw, const Ta
 // the fused stage kernel
 // ----------------------------------------------------------------------
 // One tile of EPB elements of one solve, run by one workgroup of C::BS
-// threads on C::LDS doubles of LDS.  Shared by the plain kernel (one tile
-// per workgroup) and the batched persistent kernel (many tiles of many
-// solves per workgroup).
+// threads on C::LDS doubles of LDS, with the degree tables T.  Shared by
+// the plain kernel (the tiles of one solve) and the batched work-list
+// kernel (the tiles of every solve of one degree).
 template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int tile) {
+__device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, const Tables& T, int tile) {
   using C = Cfg<EQ, DIM, P, EPB>;
   constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
   constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
@@ -447,7 +447,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
   double dt = S.dt_dev ? S.dt_scale * S.dt_dev[0] : S.dt;
   if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
 
-  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, A.T, C::BS);
+  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
   load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
@@ -752,7 +752,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, int 
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(StageArgs A) {
   __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
-  stage_tile<EQ, DIM, P, EPB>(lds, A, xcd_tile(blockIdx.x, gridDim.x));
+  stage_tile<EQ, DIM, P, EPB>(lds, A, A.T, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------
@@ -769,7 +769,8 @@ struct DtCfg {
 
 // the minimum of one tile into *out
 template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, int tile, double* out) {
+__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, int tile,
+                                           double* out) {
   using C = Cfg<EQ, DIM, P, EPB>;
   using D = DtCfg<EQ, DIM, P, EPB>;
   constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
@@ -778,7 +779,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, int 
   const int e0 = tile * EPB;
   if (e0 >= A.ne) return;
   const int nel = min(EPB, A.ne - e0);
-  for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = A.T.w[t];
+  for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = T.w[t];
   double U[NC];
   load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, U, nullptr);
   __syncthreads();
@@ -835,7 +836,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, int 
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDtArgs A) {
   __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
-  maxdt_tile<EQ, DIM, P, EPB>(lds, A, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
+  maxdt_tile<EQ, DIM, P, EPB>(lds, A, A.T, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
 }
 
 // ----------------------------------------------------------------------
@@ -853,31 +854,48 @@ constexpr int epb_for(int dim, int p, int variant) {
 // ----------------------------------------------------------------------
 // batched work-list kernels: one kernel per degree, its work list holding
 // the element tiles of every solve of that degree (same tile shape as the
-// plain kernel); workgroups map to items XCD-aware, and a workgroup walks
-// further items with a stride of the grid when the grid is smaller.
+// plain kernel), one workgroup per item, mapped XCD-aware.  The item's
+// arguments are read once at entry, before any store, so that they can live
+// in scalar registers; the degree tables go straight from global memory to
+// LDS.
 // ----------------------------------------------------------------------
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel(BatchArgs B) {
   __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
-  const int off = xcd_tile(blockIdx.x, gridDim.x);
-  for (int base = 0; base < B.nitems; base += gridDim.x) {
-    const int it = base + off;
-    if (it >= B.nitems) break;              // uniform over the workgroup
-    if (base > 0) __syncthreads();          // the previous item may still read LDS
-    stage_tile<EQ, DIM, P, EPB>(lds, B.args[B.item_solve[it]], B.item_tile[it]);
-  }
+  const int it = xcd_tile(blockIdx.x, gridDim.x);
+  if (it >= B.nitems) return;
+  const StageArgs* pa = B.args + B.item_solve[it];
+  StageArgs A;
+  A.S = pa->S;
+  A.ph = pa->ph;
+  A.a_s = pa->a_s;
+  A.b_s = pa->b_s;
+  A.use_un = pa->use_un;
+  A.limiter = pa->limiter;
+  A.diag = pa->diag;
+  A.trace = pa->trace;
+  stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it]);
 }
 
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel(BatchDtArgs B) {
   __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
-  const int off = xcd_tile(blockIdx.x, gridDim.x);
-  for (int base = 0; base < B.nitems; base += gridDim.x) {
-    const int it = base + off;
-    if (it >= B.nitems) break;
-    if (base > 0) __syncthreads();
-    maxdt_tile<EQ, DIM, P, EPB>(lds, B.args[B.item_solve[it]], B.item_tile[it], B.partial + it);
-  }
+  const int it = xcd_tile(blockIdx.x, gridDim.x);
+  if (it >= B.nitems) return;
+  const MaxDtArgs* pa = B.args + B.item_solve[it];
+  MaxDtArgs A;
+  A.u = pa->u;
+  A.partial = pa->partial;
+  A.nn = pa->nn;
+  A.p = pa->p;
+  A.nx = pa->nx;
+  A.ny = pa->ny;
+  A.ne = pa->ne;
+  A.ntiles = pa->ntiles;
+  A.hx = pa->hx;
+  A.hy = pa->hy;
+  A.ph = pa->ph;
+  maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it], B.partial + it);
 }
 
 template <int EQ, int DIM, int P>

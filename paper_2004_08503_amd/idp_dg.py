@@ -246,8 +246,9 @@ class Solver:
 
 
 class Batch:
-    """Many solves of one equation family stepped together: one persistent
-    launch per RK stage over all their element tiles."""
+    """Many solves of one equation family stepped together: per RK stage,
+    one work-list launch per degree over all their element tiles, the
+    launches of a step replayed as one HIP graph."""
 
     def __init__(self, solvers, stream=None):
         torch = _torch()

@@ -1,7 +1,7 @@
-"""Batched path: many Euler solves of uneven mesh size and degree in one
-persistent launch per stage.  Each solve's result must be bitwise identical
-to the plain one-solve-per-launch path, which is itself parity-checked
-against the oracle."""
+"""Batched path: many Euler solves of uneven mesh size and degree stepped
+together (one work-list launch per degree and stage).  Each solve's result
+must be bitwise identical to the plain one-solve-per-launch path, which is
+itself parity-checked against the oracle."""
 import numpy as np
 import pytest
 
