@@ -44,24 +44,27 @@ struct Cfg {
   static constexpr int NF = NFL * NL;                   // faces per direction
   static constexpr int BS = ((EPB * NP + 63) / 64) * 64;
   static constexpr int NITEM = (EPB * DIM * NF + BS - 1) / BS;
-  // region A: phase 1-2 results, read in phase 3
+  // region A: phase 1-2 results, read in phase 3 (fluxes of own nodes only:
+  // the face-trace fluxes are formed where a face needs them)
   static constexpr int A_U = 0;
-  static constexpr int A_F = A_U + NC * EPB * NS;
-  static constexpr int A_X = A_F + DIM * NC * EPB * NS;
-  static constexpr int A_END = A_X + NAUX * EPB * NS;
+  static constexpr int A_X = A_U + NC * EPB * NS;
+  static constexpr int A_F = A_X + NAUX * EPB * NS;
+  static constexpr int A_END = A_F + DIM * NC * EPB * NP;
   // region B (aliases A): phase 3 results, read in phases 4-5
   static constexpr int B_FL = 0;
   static constexpr int B_RB = B_FL + DIM * NC * EPB * NF;
   static constexpr int B_UB = B_RB + DIM * NC * EPB * NF;
-  static constexpr int B_KF = B_UB + DIM * EPB * NF;
-  static constexpr int B_END = B_KF + (is_euler(EQ) ? DIM * EPB * NF : 0);
-  // region C (after B, aliases the dead tail of A): Euler search data
-  static constexpr int C_UL = B_END;                                   // [NC][EPB*NP]
+  static constexpr int B_END = B_UB + DIM * EPB * NF;
+  // region C: Euler search data, written once the low-order fluxes are
+  // consumed; it overwrites them where it fits
+  static constexpr int C_SIZE = is_euler(EQ) ? (NC + 2 + DIM) * EPB * NP : 0;
+  static constexpr int C_UL = C_SIZE <= DIM * NC * EPB * NF ? B_FL : B_END;   // [NC][EPB*NP]
   static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * EPB * NP : 0);
   static constexpr int C_AZ = C_KM + (is_euler(EQ) ? EPB * NP : 0);   // bound U of the node
   static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
   static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * EPB * NP : 0);
-  static constexpr int AB = A_END > C_END ? A_END : C_END;
+  static constexpr int AB0 = A_END > B_END ? A_END : B_END;
+  static constexpr int AB = AB0 > C_END ? AB0 : C_END;
   static constexpr int S_AL = AB;                       // nodal alpha
   static constexpr int S_W = S_AL + EPB * NP;           // weights
   static constexpr int S_Q = S_W + N1;                  // cumulative D
@@ -399,14 +402,8 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
           double F[NC];
           flux_k<EQ, DIM>(k, U, X, ph, F);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NS + t] = F[c];
+          for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NP + le * NP + s] = F[c];
         }
-      } else {
-        const int k = (s - NP) / (2 * C::TJ);   // normal direction of the trace
-        double F[NC];
-        flux_k<EQ, DIM>(k, U, X, ph, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NS + t] = F[c];
       }
     }
   }
@@ -460,12 +457,28 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   __syncthreads();
 
   // ---- phase 3: subcell faces ----
-  double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM], rKF[C::NITEM];
+  // K_min over the node and its 2d face neighbours (Euler)
+  double kmin = INFINITY;
+  if constexpr (is_euler(EQ)) {
+    if (own) {
+      const int le = tid / NP, s = tid - le * NP;
+      const int a = DIM == 2 ? s % N1 : s;
+      const int b = DIM == 2 ? s / N1 : 0;
+      const double* K = lds + C::A_X + 4 * EPB * NS + le * NS;
+      kmin = K[s];
+      kmin = fmin(kmin, K[a > 0 ? s - 1 : NP + b]);
+      kmin = fmin(kmin, K[a < P ? s + 1 : NP + C::TJ + b]);
+      if constexpr (DIM == 2) {
+        kmin = fmin(kmin, K[b > 0 ? s - N1 : NP + 2 * C::TJ + a]);
+        kmin = fmin(kmin, K[b < P ? s + N1 : NP + 3 * C::TJ + a]);
+      }
+    }
+  }
+  double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM];
 #pragma unroll
   for (int it = 0; it < C::NITEM; ++it) {
     const int w = tid + it * C::BS;
     rUB[it] = 0.0;
-    rKF[it] = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
     if (w < nel * DIM * NF) {
@@ -483,26 +496,36 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       for (int c = 0; c < NC; ++c) {
         UL[c] = lds[C::A_U + c * EPB * NS + sl];
         UR[c] = lds[C::A_U + c * EPB * NS + sr];
-        FL[c] = lds[C::A_F + (k * NC + c) * EPB * NS + sl];
-        FR[c] = lds[C::A_F + (k * NC + c) * EPB * NS + sr];
       }
 #pragma unroll
-      for (int q = 0; q < C::NAUX; ++q) {
+      for (int q = 0; q < C::NAUX - 1; ++q) {
         XL[q] = lds[C::A_X + q * EPB * NS + sl];
         XR[q] = lds[C::A_X + q * EPB * NS + sr];
+      }
+      const double* Fo = lds + C::A_F + k * NC * EPB * NP + le * NP;
+      if (f == 0) {
+        flux_k<EQ, DIM>(k, UL, XL, A.ph, FL);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) FL[c] = Fo[c * EPB * NP + sl - base];
+      }
+      if (f == P + 1) {
+        flux_k<EQ, DIM>(k, UR, XR, A.ph, FR);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) FR[c] = Fo[c * EPB * NP + sr - base];
       }
       const double lam = lambda_k<EQ, DIM>(k, UL, XL, UR, XR, A.ph);
 #pragma unroll
       for (int c = 0; c < NC; ++c) rFL[it][c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
       const double avg = 0.5 * (UL[0] + UR[0]);
       rUB[it] = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
-      if constexpr (is_euler(EQ)) rKF[it] = fmin(XL[4], XR[4]);
       if (f >= 1 && f <= P) {
         const double sc = DIM == 2 ? lds[C::S_W + l] * (k == 0 ? S.hy : S.hx) : 1.0;
         const double* q = lds + C::S_Q + (f - 1) * N1;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const double* Fl = lds + C::A_F + (k * NC + c) * EPB * NS + base;
+          const double* Fl = Fo + c * EPB * NP;
           double fh = Fl[own_slot<DIM, P>(k, l, 0)];
 #pragma unroll
           for (int e = 0; e <= P; ++e) fh += q[e] * Fl[own_slot<DIM, P>(k, l, e)];
@@ -527,7 +550,6 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         lds[C::B_RB + (k * NC + c) * EPB * NF + o] = rRB[it][c];
       }
       lds[C::B_UB + k * EPB * NF + o] = rUB[it];
-      if constexpr (is_euler(EQ)) lds[C::B_KF + k * EPB * NF + o] = rKF[it];
     }
   }
   __syncthreads();
@@ -546,6 +568,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   }
   bool lov = false;
   double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
+  int search = 0, tangent = 0;   // faces of this node for the search list
+  double ubound = 0.0;
   const double idt = dt > 0.0 ? 1.0 / dt : 0.0;
   double dtm = 0.0;
   if (own) {
@@ -603,10 +627,6 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         // [min of the lower bounds, U = min of the upper bounds]; faces whose
         // lower bound is at least U cannot hold it, the others go to the
         // workgroup's search list with the node's bracket.
-        double kmin = INFINITY;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-          kmin = fmin(kmin, fmin(lds[C::B_KF + k * EPB * NF + fl[k]], lds[C::B_KF + k * EPB * NF + fr[k]]));
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dtm;
         int act = 0;
@@ -655,15 +675,11 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
             if (!keep) {  // the bounds meet: the smallest root is ub
               alpha = ub;
             } else {
-#pragma unroll
-              for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
-              lds[C::C_KM + tid] = kmin;
-              lds[C::C_AZ + tid] = ub;
-              int* list = reinterpret_cast<int*>(lds + C::C_LIST);
-              int* count = reinterpret_cast<int*>(lds + C::S_LN);
+              search = keep;
+              ubound = ub;
 #pragma unroll
               for (int f = 0; f < 2 * DIM; ++f)
-                if (keep & (1 << f)) list[atomicAdd(count, 1)] = tid * 8 + f * 2 + (tup[f] <= ub ? 1 : 0);
+                if (tup[f] <= ub) tangent |= 1 << f;
             }
           }
         }
@@ -672,6 +688,18 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     lds[C::S_AL + tid] = alpha;
   }
   if constexpr (is_euler(EQ)) {
+    __syncthreads();  // the low-order fluxes are consumed: region C may overwrite them
+    if (search) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
+      lds[C::C_KM + tid] = kmin;
+      lds[C::C_AZ + tid] = ubound;
+      int* list = reinterpret_cast<int*>(lds + C::C_LIST);
+      int* count = reinterpret_cast<int*>(lds + C::S_LN);
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f)
+        if (search & (1 << f)) list[atomicAdd(count, 1)] = tid * 8 + f * 2 + ((tangent >> f) & 1);
+    }
     __syncthreads();
     // ---- phase 4b: entropy line searches, spread over the workgroup ----
     const int nact = *reinterpret_cast<const int*>(lds + C::S_LN);
@@ -761,7 +789,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
 template <int EQ, int DIM, int P, int EPB>
 struct DtCfg {
   using C = Cfg<EQ, DIM, P, EPB>;
-  static constexpr int L = C::A_END;                        // [DIM][EPB*NF] wave speeds
+  static constexpr int L = C::A_F;                          // [DIM][EPB*NF] wave speeds
   static constexpr int W = L + DIM * EPB * C::NF;
   static constexpr int R = W + C::N1;
   static constexpr int LDS = R + C::BS / 64;
