@@ -9,7 +9,8 @@ path never does.
 
 Problem descriptions are duck-typed: any object with the attributes
 ``dim, nx, ny, lx, ly, p, eq, vel, gamma, limiter`` (``eq`` and ``limiter``
-as the integer codes below) is accepted, e.g. the seeded workload objects.
+as the integer codes below; ``gmin, gmax`` too for SUBCELL_SI) is accepted,
+e.g. the seeded workload objects.
 State arrays are float64 of shape ``(nc, Nn)`` in the layout ``u[c][e][b][a]``.
 """
 import ctypes
@@ -23,7 +24,7 @@ _SRC = os.path.join(_HERE, "idp_ref.c")
 _LIB_PATH = os.path.join(_HERE, "libidp_ref.so")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET, LOW = 0, 1, 2
+SUBCELL, TARGET, LOW, SUBCELL_SI = 0, 1, 2, 3
 
 
 def build():
@@ -40,7 +41,8 @@ class _Desc(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("p", ctypes.c_int), ("eq", ctypes.c_int),
                 ("vel", ctypes.c_double * 2), ("gamma", ctypes.c_double),
-                ("limiter", ctypes.c_int)]
+                ("limiter", ctypes.c_int),
+                ("gmin", ctypes.c_double), ("gmax", ctypes.c_double)]
 
 
 class _Trace(ctypes.Structure):
@@ -76,6 +78,7 @@ def _load():
                                          ctypes.c_int]),
         "idp_ref_step": (ctypes.c_int, [D, _DP, ctypes.c_double]),
         "idp_ref_max_dt": (ctypes.c_int, [D, _DP, _DP]),
+        "idp_ref_smoothness": (ctypes.c_int, [D, _DP, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -94,6 +97,8 @@ def _desc(prob):
     d.vel[0], d.vel[1] = float(v[0]), float(v[1])
     d.gamma = float(prob.gamma)
     d.limiter = int(prob.limiter)
+    d.gmin = float(getattr(prob, "gmin", 0.0))
+    d.gmax = float(getattr(prob, "gmax", 0.0))
     return d
 
 
@@ -153,6 +158,18 @@ def lam(prob, uL, uR, n):
     uL, uR = _arr(uL), _arr(uR)
     n = _arr(list(n) + [0.0] * (2 - len(n)))
     return _load().idp_ref_lambda(ctypes.byref(_desc(prob)), _ptr(uL), _ptr(uR), _ptr(n))
+
+
+def smoothness(prob, u):
+    """Smoothness factor eps_K of every element (Sec. 4.4) for the limited
+    component of u (u, or rho for Euler); shape (nx*ny,)."""
+    nc, nn = sizes(prob)
+    u = _arr(u).reshape(nc, nn)
+    eps = np.empty(int(prob.nx) * int(prob.ny))
+    rc = _load().idp_ref_smoothness(ctypes.byref(_desc(prob)), _ptr(u), _ptr(eps))
+    if rc:
+        raise ValueError("idp_ref_smoothness failed with %d" % rc)
+    return eps
 
 
 def fe(prob, u, dt, trace=False):

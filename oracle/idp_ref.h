@@ -30,8 +30,11 @@ enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2 };
 
 /* Limiter modes: SUBCELL is the subcell convex limiter (Sec. 4.1.3 and
  * 4.2.2); TARGET returns the unlimited high-order update (eq. ho-update);
- * LOW returns the low-order IDP update (eq. lo-update / idp-fe). */
-enum { IDP_REF_SUBCELL = 0, IDP_REF_TARGET = 1, IDP_REF_LOW = 2 };
+ * LOW returns the low-order IDP update (eq. lo-update / idp-fe); SUBCELL_SI
+ * is SUBCELL with the local bounds of the limited component relaxed towards
+ * the global bounds [gmin, gmax] by the subcell-resolution smoothness
+ * indicator (Sec. 4.4, eq. relaxed-bounds). */
+enum { IDP_REF_SUBCELL = 0, IDP_REF_TARGET = 1, IDP_REF_LOW = 2, IDP_REF_SUBCELL_SI = 3 };
 
 typedef struct {
   int dim;          /* 1 or 2 */
@@ -41,7 +44,8 @@ typedef struct {
   int eq;           /* IDP_REF_ADVECTION / _BURGERS / _EULER */
   double vel[2];    /* advection velocity, or Burgers direction vector v */
   double gamma;     /* ratio of specific heats (Euler) */
-  int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW */
+  int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW / _SUBCELL_SI */
+  double gmin, gmax; /* global bounds of the limited component (SUBCELL_SI) */
 } idp_ref_desc;
 
 /* Optional per-node outputs of one forward-Euler sub-step.  Any pointer may
@@ -74,6 +78,14 @@ int idp_ref_dhat(int p, double* Dh);
 int idp_ref_flux(const idp_ref_desc* d, const double* u, double* F);
 double idp_ref_lambda(const idp_ref_desc* d, const double* uL,
                       const double* uR, const double* n);
+
+/* Smoothness factor eps_K in [0, 1] of every element (Sec. 4.4) for the
+ * limited component of u (u for scalar laws, rho for Euler): the element's
+ * polynomial in the Legendre basis, s_K = log10 of the L2 energy fraction in
+ * the modes of degree p in any variable, and eps_K rising from 0 at
+ * s_K = s0 - kappa to 1 at s0 + kappa, s0 = log10(p^-4), kappa = 1.
+ * eps has nx*ny entries.  Returns 0, or -1 on a bad argument. */
+int idp_ref_smoothness(const idp_ref_desc* d, const double* u, double* eps);
 
 /* One forward-Euler sub-step out = FE(u, dt) with the limiter mode of d. */
 int idp_ref_fe(const idp_ref_desc* d, const double* u, double* out,

@@ -28,9 +28,9 @@ from typing import List, Tuple
 import numpy as np
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET, LOW = 0, 1, 2
+SUBCELL, TARGET, LOW, SUBCELL_SI = 0, 1, 2, 3
 EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
-LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW}
+LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW, "subcell_si": SUBCELL_SI}
 
 
 @dataclass
@@ -45,6 +45,8 @@ class Problem:
     vel: Tuple[float, float] = (1.0, 1.0)
     gamma: float = 1.4
     limiter: int = SUBCELL
+    gmin: float = 0.0     # global bounds of the limited component (SUBCELL_SI)
+    gmax: float = 0.0
 
     @property
     def nc(self) -> int:
