@@ -58,7 +58,17 @@ enum {
 enum {
   IDP_DG_SUBCELL = 0,     /* subcell convex limiting (Sec. 4.1.3, 4.2.2) */
   IDP_DG_TARGET_ONLY = 1, /* alpha = 1: the unlimited high-order update */
-  IDP_DG_LOW_ONLY = 2     /* alpha = 0: the low-order IDP update */
+  IDP_DG_LOW_ONLY = 2,    /* alpha = 0: the low-order IDP update */
+  IDP_DG_SUBCELL_SI = 3   /* SUBCELL with the local bounds of the limited
+                             component (u, or rho for Euler) relaxed by the
+                             subcell-resolution smoothness indicator towards
+                             the global bounds [gmin, gmax] (Sec. 4.4,
+                             eq. relaxed-bounds): per element, s_K = log10
+                             of the L2 energy fraction of the degree-p
+                             Legendre modes (any variable), eps_K rising on
+                             1/2 + 1/2 sin(pi (s_K - s0)/2) from 0 at
+                             s0 - 1 to 1 at s0 + 1, s0 = log10(p^-4); p = 1
+                             keeps the strict bounds */
 };
 
 /* Problem description.  Periodic box [0,lx) x [0,ly) of nx x ny elements
@@ -74,6 +84,8 @@ typedef struct {
   double velocity[2];
   double gamma;
   int limiter;
+  double gmin, gmax;  /* global bounds of the limited component, used by
+                         IDP_DG_SUBCELL_SI (finite, gmin <= gmax) */
 } idp_dg_desc;
 
 typedef struct idp_dg idp_dg;

@@ -10,7 +10,7 @@ namespace idp {
 enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2, EQ_EULER53 = 3, EQ_EULER75 = 4 };
 constexpr bool is_euler(int eq) { return eq >= EQ_EULER; }
 constexpr int gn_of(int eq) { return eq == EQ_EULER53 ? 3 : eq == EQ_EULER75 ? 5 : 0; }
-enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2 };
+enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2, LIM_SUBCELL_SI = 3 };
 constexpr int MAXP = 8;
 
 // Per-degree constants, passed by value in the kernel arguments.
@@ -18,6 +18,9 @@ struct Tables {
   double w[MAXP + 1];             // Gauss-Lobatto weights on [0,1]
   double Q[MAXP * (MAXP + 1)];    // Q[a][e] = sum_{c<=a} D[c][e], a < p; rows of p+1
   double iw[MAXP + 1];            // 1 / w
+  double M[(MAXP + 1) * (MAXP + 1)];  // nodal -> Legendre modal: c_k = sum_a M[k][a] u_a
+  double nk[MAXP + 1];            // ||P_k||^2 on [-1,1] = 2/(2k+1)
+  double s0;                      // smoothness indicator centre log10(p^-4)
 };
 
 // Physics constants of one problem.
@@ -64,6 +67,7 @@ struct StageArgs {
   int limiter;
   Diag* diag;
   double* trace;   // optional per-node [umin, umax, kmin, alpha_z, alpha] x Nn
+  double gmin, gmax;   // global bounds (LIM_SUBCELL_SI)
 };
 
 struct MaxDtArgs {

@@ -101,6 +101,30 @@ int hip_fail(idp_dg* h, hipError_t e, const char* where) {
   return fail(h, IDP_DG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Nodal -> Legendre modal map on the Gauss-Lobatto points: the points'
+// quadrature is exact for P_j P_k with j + k <= 2p - 1, so the Legendre
+// polynomials are orthogonal in the discrete inner product and
+// c_k = sum_a w_a u_a P_k(x_a) / sum_a w_a P_k(x_a)^2 recovers the modal
+// coefficients of the interpolating polynomial exactly (for k = p too, with
+// the discrete norm in the denominator).  Also the L2 norms 2/(2k+1) on
+// [-1,1] and the smoothness indicator centre log10(p^-4) (Sec. 4.4).
+void modal_tables(int p, const double* xi01, const double* w01, Tables* T) {
+  const int n = p + 1;
+  for (int k = 0; k < n; ++k) {
+    double g = 0.0;
+    std::vector<double> pk(n);
+    for (int a = 0; a < n; ++a) {
+      double pn, pm;
+      legendre_pair(k, 2.0 * xi01[a] - 1.0, &pn, &pm);
+      pk[a] = pn;
+      g += w01[a] * pn * pn;
+    }
+    for (int a = 0; a < n; ++a) T->M[k * n + a] = w01[a] * pk[a] / g;
+    T->nk[k] = 2.0 / (2.0 * k + 1.0);
+  }
+  T->s0 = std::log10(std::pow((double)p, -4.0));
+}
+
 bool desc_ok(const idp_dg_desc* d, std::string* why) {
   if (!d) { *why = "desc is NULL"; return false; }
   if (d->dim != 1 && d->dim != 2) { *why = "dim must be 1 or 2"; return false; }
@@ -109,7 +133,11 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) { *why = "lx, ly must be > 0"; return false; }
   if (d->p < 1 || d->p > MAXP) { *why = "p must be in [1, 8]"; return false; }
   if (d->eq < IDP_DG_ADVECTION || d->eq > IDP_DG_EULER) { *why = "unknown equation"; return false; }
-  if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_LOW_ONLY) { *why = "unknown limiter"; return false; }
+  if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_SUBCELL_SI) { *why = "unknown limiter"; return false; }
+  if (d->limiter == IDP_DG_SUBCELL_SI && !(std::isfinite(d->gmin) && std::isfinite(d->gmax) && d->gmin <= d->gmax)) {
+    *why = "gmin, gmax must be finite with gmin <= gmax";
+    return false;
+  }
   if (d->eq == IDP_DG_EULER && !(d->gamma > 1.0 && d->gamma <= 5.0 / 3.0)) {
     *why = "gamma must be in (1, 5/3]";
     return false;
@@ -203,6 +231,8 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.use_un = stage > 0;
   a.limiter = h->d.limiter;
   a.diag = h->diag;
+  a.gmin = h->d.gmin;
+  a.gmax = h->d.gmax;
   return a;
 }
 
@@ -422,6 +452,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
     if (exact && gn == 3.0) h->kcode = EQ_EULER53;
   }
   for (int k = 0; k <= desc->p; ++k) h->T.iw[k] = 1.0 / h->T.w[k];
+  modal_tables(desc->p, xi, h->T.w, &h->T);
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
   if (ws) {  // caller workspace: no allocation, diagnostics cleared on the stream

@@ -69,7 +69,9 @@ struct Cfg {
   static constexpr int S_W = S_AL + EPB * NP;           // weights
   static constexpr int S_Q = S_W + N1;                  // cumulative D
   static constexpr int S_IW = S_Q + P * N1;             // 1/w
-  static constexpr int S_LN = S_IW + N1;                // search list length (int)
+  static constexpr int S_M = S_IW + N1;                 // nodal -> modal map [k][a]
+  static constexpr int S_NK = S_M + N1 * N1;            // Legendre norms
+  static constexpr int S_LN = S_NK + N1;                // search list length (int)
   static constexpr int LDS = S_LN + 1;
   static_assert(LDS * 8 <= 160 * 1024, "tile does not fit in LDS");
 };
@@ -410,16 +412,99 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
   if (bad && bad_flag) atomicOr(bad_flag, 1u);
 }
 
-// copy the per-degree tables into LDS
+// copy the per-degree tables into LDS (sm, snk: the modal map and norms,
+// or NULL)
 template <int P>
-__device__ inline void load_tables(double* sw, double* sq, double* siw, const Tables& T,
-                                   int nthreads) {
+__device__ inline void load_tables(double* sw, double* sq, double* siw, double* sm, double* snk,
+                                   const Tables& T, int nthreads) {
   constexpr int N1 = P + 1;
   for (int t = threadIdx.x; t < N1; t += nthreads) {
     sw[t] = T.w[t];
     siw[t] = T.iw[t];
+    if (snk) snk[t] = T.nk[t];
   }
   for (int t = threadIdx.x; t < P * N1; t += nthreads) sq[t] = T.Q[t];
+  if (sm)
+    for (int t = threadIdx.x; t < N1 * N1; t += nthreads) sm[t] = T.M[t];
+}
+
+// Subcell-resolution smoothness factor of every element of the tile
+// (Sec. 4.4) from the limited component in LDS (own slots): modal
+// coefficients c = M u (tensor product in 2-D), the energy fraction of the
+// modes of degree p in any variable, s_K = log10 of it and eps_K on the
+// ramp 1/2 + 1/2 sin(pi (s_K - s0)/2) between s0 - 1 (0) and s0 + 1 (1).
+// An element whose polynomial is zero is smooth (0).  Uses scr (2-D:
+// 2 EPB (p+1) + EPB doubles, 1-D: EPB) as scratch; returns the factor of the
+// calling thread's element (own nodes), 1 for the others.  Sums run in a
+// fixed order, so the result does not depend on the launch.
+template <int DIM, int P, int EPB, int NS, int BS>
+__device__ inline double smoothness_tile(const double* u0, const double* M, const double* nk, double s0,
+                                         int nel, double* scr) {
+  // no multiply-add contraction: the result must not depend on how the
+  // kernel that inlines this is compiled (plain and batched agree bitwise)
+#pragma clang fp contract(off)
+  constexpr int N1 = P + 1, NP = DIM == 2 ? N1 * N1 : N1;
+  const int tid = threadIdx.x;
+  double* tot_h = scr;                                  // [2][EPB*N1] row sums (2-D)
+  double* eps_e = scr + (DIM == 2 ? 2 * EPB * N1 : 0);  // [EPB]
+  if constexpr (DIM == 2) {
+    // thread (element, x-mode k): the k-th x-modes of every row, then their
+    // y-transforms, squared and weighted
+    if (tid < nel * N1) {
+      const int le = tid / N1, k = tid - le * N1;
+      const double* ue = u0 + le * NS;
+      double t[N1];
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < N1; ++a) acc += M[k * N1 + a] * ue[b * N1 + a];
+        t[b] = acc;
+      }
+      double tot = 0.0, hi = 0.0;
+#pragma unroll
+      for (int l = 0; l < N1; ++l) {
+        double c = 0.0;
+#pragma unroll
+        for (int b = 0; b < N1; ++b) c += M[l * N1 + b] * t[b];
+        const double e = c * c * nk[k] * nk[l];
+        tot += e;
+        if (k == P || l == P) hi += e;
+      }
+      tot_h[tid] = tot;
+      tot_h[EPB * N1 + tid] = hi;
+    }
+    __syncthreads();
+  }
+  if (tid < nel) {
+    double tot = 0.0, hi = 0.0;
+    if constexpr (DIM == 2) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        tot += tot_h[tid * N1 + k];
+        hi += tot_h[EPB * N1 + tid * N1 + k];
+      }
+    } else {
+      const double* ue = u0 + tid * NS;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        double c = 0.0;
+#pragma unroll
+        for (int a = 0; a < N1; ++a) c += M[k * N1 + a] * ue[a];
+        const double e = c * c * nk[k];
+        tot += e;
+        if (k == P) hi += e;
+      }
+    }
+    double eps = 0.0;
+    if (tot > 0.0) {
+      const double sk = log10(hi / tot);
+      eps = sk < s0 - 1.0 ? 0.0 : (sk > s0 + 1.0 ? 1.0 : 0.5 + 0.5 * sin(M_PI * 0.5 * (sk - s0)));
+    }
+    eps_e[tid] = eps;
+  }
+  __syncthreads();
+  return tid < nel * NP ? eps_e[tid / NP] : 1.0;
 }
 
 // ----------------------------------------------------------------------
@@ -444,7 +529,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   double dt = S.dt_dev ? S.dt_scale * S.dt_dev[0] : S.dt;
   if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
 
-  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, T, C::BS);
+  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, lds + C::S_M, lds + C::S_NK, T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
   load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
@@ -455,6 +540,16 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     for (int c = 0; c < NC; ++c) Un[c] = S.u_n[c * nn + (long long)e0 * NP + tid];
   }
   __syncthreads();
+
+  // smoothness factor of the node's element (SUBCELL_SI; p = 1 keeps the
+  // strict bounds); the nodal-alpha array is free scratch until phase 4
+  double eps = 1.0;
+  if constexpr (P > 1) {
+    static_assert(DIM == 1 || 2 * EPB * N1 + EPB <= EPB * NP, "scratch for the smoothness factor");
+    if (A.limiter == LIM_SUBCELL_SI)
+      eps = smoothness_tile<DIM, P, EPB, NS, C::BS>(lds + C::A_U, lds + C::S_M, lds + C::S_NK, T.s0, nel,
+                                                   lds + C::S_AL);
+  }
 
   // ---- phase 3: subcell faces ----
   // K_min over the node and its 2d face neighbours (Euler)
@@ -597,6 +692,11 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     }
     const double tol = 1e-12 * fmax(fabs(umin), fabs(umax));
     lov = uL[0] > umax + tol || uL[0] < umin - tol;
+    if (A.limiter == LIM_SUBCELL_SI) {  // eq. relaxed-bounds
+#pragma clang fp contract(off)
+      umin = eps * umin + (1.0 - eps) * A.gmin;
+      umax = eps * umax + (1.0 - eps) * A.gmax;
+    }
     if (A.limiter == LIM_TARGET) {
       alpha = 1.0;
     } else if (A.limiter == LIM_LOW) {
@@ -902,6 +1002,8 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel
   A.limiter = pa->limiter;
   A.diag = pa->diag;
   A.trace = pa->trace;
+  A.gmin = pa->gmin;
+  A.gmax = pa->gmax;
   stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it]);
 }
 

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libidp_dg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "idp_dg.h")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET_ONLY, LOW_ONLY = 0, 1, 2
+SUBCELL, TARGET_ONLY, LOW_ONLY, SUBCELL_SI = 0, 1, 2, 3
 EINVAL, ENOMEM, EHIP = -1, -2, -3
 
 
@@ -25,7 +25,7 @@ class Desc(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("p", ctypes.c_int), ("eq", ctypes.c_int),
                 ("velocity", ctypes.c_double * 2), ("gamma", ctypes.c_double),
-                ("limiter", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("gmin", ctypes.c_double), ("gmax", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
@@ -107,6 +107,8 @@ def make_desc(prob):
     d.velocity[0], d.velocity[1] = float(v[0]), float(v[1])
     d.gamma = float(prob.gamma)
     d.limiter = int(prob.limiter)
+    d.gmin = float(getattr(prob, "gmin", 0.0))
+    d.gmax = float(getattr(prob, "gmax", 0.0))
     return d
 
 

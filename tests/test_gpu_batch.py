@@ -156,3 +156,22 @@ def test_batch_membership_changes_while_graphs_run():
     batch.close()
     for sv in solvers:
         sv.close()
+
+
+def test_batch_smoothness_indicator_bitwise_equals_plain():
+    idp_dg = _lib()
+    cases = []
+    for (prob, u) in mix(count=5, seed=13):
+        cases.append((prob.replace(limiter=W.SUBCELL_SI, gmin=float(u[0].min()), gmax=float(u[0].max())), u))
+    solvers = [idp_dg.Solver(p) for p, _ in cases]
+    ub = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    up = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    batch = idp_dg.Batch(solvers)
+    for _ in range(3):
+        batch.step_cfl(ub, 0.5)
+        for sv, u in zip(solvers, up):
+            sv.step_cfl(u, 0.5)
+    torch.cuda.synchronize()
+    for a, b in zip(ub, up):
+        assert torch.equal(a, b)
+    batch.close()

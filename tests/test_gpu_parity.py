@@ -6,9 +6,10 @@ max |u_gpu - u_ref| / max |u_ref| <= 1e-12 for one stage and <= 1e-9 after
 100 SSP-RK3 steps.  Both sides compute in binary64; they differ by the
 order of rounding (the GPU contracts multiply-adds, forms the high-order
 subcell flux directly instead of by prefix sums, and finds the entropy
-root by Newton from the infeasible side with a step back to the nearest
-admissible point instead of bisection; both land within rounding of the
-supremum).
+root by a bracketed Newton search instead of bisection; both land within
+rounding of the supremum).  The smoothness-indicator mode (SUBCELL_SI) is
+checked the same way, with the global bounds set to the range of the
+initial limited component, as in the paper's examples.
 """
 import numpy as np
 import pytest
@@ -272,3 +273,77 @@ def test_stage_parity_other_gamma(gamma, dim, p):
         prob = W.Problem(dim=2, nx=6, ny=5, p=p, eq=W.EULER, gamma=gamma)
     u = W.euler_quadrants(prob, rng)
     stage_parity(prob, u, 0.5 * oracle.max_dt(prob, u))
+
+
+def si(prob, u):
+    """The problem in SUBCELL_SI mode with the global bounds of the limited
+    component taken from u."""
+    return prob.replace(limiter=W.SUBCELL_SI, gmin=float(u[0].min()), gmax=float(u[0].max()))
+
+
+@pytest.mark.parametrize("name,wl", SMALL, ids=[s[0] for s in SMALL])
+def test_stage_parity_smoothness_indicator(name, wl):
+    prob = si(wl.prob, wl.u0)
+    dt = wl.cfl * oracle.max_dt(prob, wl.u0)
+    stage_parity(prob, wl.u0, dt)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("eq", ["burgers", "euler"])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_smoothness_indicator_every_degree(p, eq, dim):
+    """Smooth data with a jump, so that the tile holds smooth, partly rough
+    and rough elements."""
+    if dim == 1:
+        prob = W.Problem(dim=1, nx=9, ny=1, p=p, eq=W.EQ_NAMES[eq], vel=(0.9, 0.0))
+    else:
+        prob = W.Problem(dim=2, nx=6, ny=5, p=p, eq=W.EQ_NAMES[eq], vel=(0.6, 1.1))
+    x, y, _ = W.node_coords(prob)
+    smooth = 1.0 + 0.3 * np.sin(2 * np.pi * x) * (np.cos(2 * np.pi * y) if dim == 2 else 1.0)
+    f = smooth + 2.0 * (x > 0.55)
+    if prob.eq == W.EULER:
+        nc = prob.nc
+        u = np.zeros((nc, prob.num_nodes))
+        u[0] = f
+        u[1] = 0.2 * f
+        if dim == 2:
+            u[2] = -0.1 * f
+        vel2 = (u[1] ** 2 + (u[2] ** 2 if dim == 2 else 0.0)) / f ** 2
+        u[nc - 1] = 1.0 / (prob.gamma - 1.0) + 0.5 * f * vel2
+    else:
+        u = f[None, :]
+    prob = si(prob, u)
+    eps = oracle.smoothness(prob, u)
+    if p > 1:
+        assert (eps == 0).any() and (eps > 0).any()
+    dt = 0.5 * oracle.max_dt(prob, u)
+    stage_parity(prob, u, dt)
+
+
+@pytest.mark.parametrize("wl", [W.euler_2d(n=16, p=4), W.burgers_2d(n=16, p=3), W.advection_1d()],
+                         ids=["euler2d", "burgers2d", "adv1d"])
+def test_smoothness_indicator_relaxed_bounds_match_oracle(wl):
+    idp_dg = _gpu()
+    prob = si(wl.prob, wl.u0)
+    dt = wl.cfl * oracle.max_dt(prob, wl.u0)
+    ref, tr = oracle.fe(prob, wl.u0, dt, trace=True)
+    sv = idp_dg.Solver(prob)
+    out = sv.empty()
+    g = sv.stage_trace(None, to_dev(wl.u0), out, dt, 0).cpu().numpy()
+    sc = np.abs(wl.u0[0]).max()
+    np.testing.assert_allclose(g[0], tr["umin"], rtol=0, atol=1e-14 * sc)
+    np.testing.assert_allclose(g[1], tr["umax"], rtol=0, atol=1e-14 * sc)
+    np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
+    # the relaxation changed the bounds somewhere (elements that are not
+    # rough): they are not the strict local ones
+    _, trs = oracle.fe(wl.prob, wl.u0, dt, trace=True)
+    assert (np.abs(tr["umax"] - trs["umax"]) > 1e-6 * sc).any()
+    assert rel_err(out.cpu().numpy(), ref) <= 1e-12
+    sv.close()
+
+
+def test_smoothness_indicator_rejects_bad_bounds():
+    idp_dg = _gpu()
+    prob = W.Problem(dim=1, nx=4, ny=1, p=3, eq=W.BURGERS, limiter=W.SUBCELL_SI, gmin=1.0, gmax=0.0)
+    with pytest.raises(idp_dg.IdpError):
+        idp_dg.Solver(prob)
