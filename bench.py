@@ -126,6 +126,40 @@ def batched_leg(steps, count=64):
     }
 
 
+def mode_leg(wl, prob, steps):
+    """The same device-timestepped step in another limiter mode: stage
+    latency from HIP events around each stage, and the limited fractions."""
+    import torch
+    from paper_2004_08503_amd import idp_dg
+    sv = idp_dg.Solver(prob)
+    u = torch.from_numpy(wl.u0.copy()).to("cuda")
+    b1, b2 = sv.empty(), sv.empty()
+    dtd = torch.empty(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps + 5):
+        e = ev[k - 5] if k >= 5 else None
+        if k == 5:
+            torch.cuda.synchronize()
+            sv.diagnostics()
+        sv.max_dt_async(u, dtd)
+        for st, (a, b, c) in enumerate(((None, u, b1), (u, b1, b2), (u, b2, u))):
+            if e is not None:
+                e[st].record(stream)
+            sv.stage_dt(a, b, c, dtd, wl.cfl, st)
+        if e is not None:
+            e[3].record(stream)
+    torch.cuda.synchronize()
+    d = sv.diagnostics()
+    ms = np.array([[x[j].elapsed_time(x[j + 1]) for j in range(3)] for x in ev]).reshape(-1)
+    nn = prob.num_nodes
+    sv.close()
+    return {"stage_ms_p50": float(np.percentile(ms, 50)), "stage_ms_p99": float(np.percentile(ms, 99)),
+            "stage_dof_updates_per_s": float(nn / (ms.mean() * 1e-3)),
+            "limited_node_fraction": d["limited_nodes"] / (3.0 * nn * steps),
+            "entropy_node_fraction": d["entropy_nodes"] / (3.0 * nn * steps), "steps": steps}
+
+
 def serving_leg(count, load, budget_gb=64.0):
     """The served workload: a seeded Poisson stream of `count` requests (half
     Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps).  The
@@ -155,6 +189,7 @@ def main():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-solve leg")
+    ap.add_argument("--no-modes", action="store_true", help="skip the other limiter modes")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests in the served stream (0 skips the serving leg)")
@@ -265,6 +300,15 @@ def main():
     }
     sv.close()
     del u, b1, b2
+    # the other limiter modes on the same workload (the smoothness-indicator
+    # mode with the initial density range as global bounds)
+    rho0 = wl.u0[0]
+    out["modes"] = {} if args.no_modes else {
+        "subcell_si": mode_leg(wl, prob.replace(limiter=W.SUBCELL_SI, gmin=float(rho0.min()),
+                                                gmax=float(rho0.max())), 50),
+        "target_only": mode_leg(wl, prob.replace(limiter=W.TARGET), 50),
+        "low_only": mode_leg(wl, prob.replace(limiter=W.LOW), 50),
+    }
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_steps)
     if args.serve_requests > 0:

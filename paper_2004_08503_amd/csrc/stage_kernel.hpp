@@ -832,7 +832,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   if (own) {
     alpha = lds[C::S_AL + tid];
     limited = alpha < 1.0;
-    ent = is_euler(EQ) && A.limiter == LIM_SUBCELL && alpha < az_dbg;
+    ent = is_euler(EQ) && (A.limiter == LIM_SUBCELL || A.limiter == LIM_SUBCELL_SI) && alpha < az_dbg;
     if (A.trace) {
       const long long g = (long long)e0 * NP + tid;
       A.trace[g] = umin;
