@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "idp_ref.c")
 _LIB_PATH = os.path.join(_HERE, "libidp_ref.so")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET, LOW, SUBCELL_SI = 0, 1, 2, 3
+SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 
 
 def build():

@@ -55,7 +55,7 @@ int idp_ref_check(const idp_ref_desc* d) {
   if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) return -1;
   if (d->p < 1 || d->p > MAXP) return -1;
   if (d->eq < IDP_REF_ADVECTION || d->eq > IDP_REF_EULER) return -1;
-  if (d->limiter < IDP_REF_SUBCELL || d->limiter > IDP_REF_SUBCELL_SI) return -1;
+  if (d->limiter < IDP_REF_SUBCELL || d->limiter > IDP_REF_ELEMENTWISE) return -1;
   if (d->limiter == IDP_REF_SUBCELL_SI && !(d->gmin <= d->gmax && isfinite(d->gmin) && isfinite(d->gmax)))
     return -1;
   /* the two-rarefaction wave-speed bound holds for 1 < gamma <= 5/3 */
@@ -758,8 +758,50 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
     free(eps);
   }
 
+  /* O8e/O9e: elementwise limiting (Sec. 4.1.2, eq. convex-provisional-
+   * elementwise).  Every node limits its whole correction u^H_i - u^L_i =
+   * dt/m_i (r^H_i - r^L_i): Zalesak with that single contribution on the
+   * limited component, then for Euler the largest t in [0, alpha_z] with
+   * u^L_i + t (u^H_i - u^L_i) admissible; the element applies the minimum
+   * over its nodes, u = u^L + alpha_K (u^H - u^L). */
+  if (R->d.limiter == IDP_REF_ELEMENTWISE) {
+    const long np = nn / R->ne;
+    for (long i = 0; i < nn; ++i) {
+      double m = node_mass(R, i);
+      double ul = uL[(long)lim * nn + i];
+      double f = m / dt * (uH[(long)lim * nn + i] - ul);
+      double Qp = m / dt * (umax[i] - ul);
+      double Qm = m / dt * (umin[i] - ul);
+      if (Qp < 0.0) Qp = 0.0;
+      if (Qm > 0.0) Qm = 0.0;
+      double a = 1.0;
+      if (f > 0.0) a = fmin(1.0, Qp / f);
+      if (f < 0.0) a = fmin(1.0, Qm / f);
+      az[i] = a;
+      if (euler) {
+        double uli[MAXC], P[MAXC];
+        for (int c = 0; c < nc; ++c) {
+          uli[c] = uL[(long)c * nn + i];
+          P[c] = uH[(long)c * nn + i] - uli[c];
+        }
+        a = entropy_search(R, uli, P, a, kmin[i]);
+      }
+      al[i] = a;
+    }
+    for (long e = 0; e < R->ne; ++e) {
+      double aK = 1.0;
+      for (long q = 0; q < np; ++q) aK = fmin(aK, al[e * np + q]);
+      for (long q = 0; q < np; ++q) al[e * np + q] = aK;
+    }
+    for (long i = 0; i < nn; ++i)
+      for (int c = 0; c < nc; ++c) {
+        long ic = (long)c * nn + i;
+        out[ic] = uL[ic] + al[i] * (uH[ic] - uL[ic]);
+      }
+  }
+
   /* O8: nodal Zalesak coefficients on the limited component */
-  for (long i = 0; i < nn; ++i) {
+  for (long i = 0; i < nn && R->d.limiter != IDP_REF_ELEMENTWISE; ++i) {
     double m = node_mass(R, i);
     double Pp = 0.0, Pm = 0.0;
     for (int k = 0; k < dim; ++k) {
@@ -790,7 +832,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
    * convex-provisional with gamma = 2d): every partial state
    * uL + t 2d dt/m (+-rbar) must stay admissible, t <= alpha_z.  Reading:
    * the search runs on [0, alpha_z] and also keeps rho > 0. */
-  if (euler) {
+  if (euler && R->d.limiter != IDP_REF_ELEMENTWISE) {
     for (long i = 0; i < nn; ++i) {
       double m = node_mass(R, i);
       double uli[MAXC];
@@ -829,7 +871,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
    * nodal coefficients and the flux-corrected update (eq. subcell-fct /
    * convex-fct).  Limiter modes TARGET and LOW return the unlimited
    * high-order and the low-order updates. */
-  for (long i = 0; i < nn; ++i) {
+  for (long i = 0; i < nn && R->d.limiter != IDP_REF_ELEMENTWISE; ++i) {
     if (R->d.limiter == IDP_REF_TARGET) {
       for (int c = 0; c < nc; ++c) out[(long)c * nn + i] = uH[(long)c * nn + i];
       continue;

@@ -33,8 +33,12 @@ enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2 };
  * LOW returns the low-order IDP update (eq. lo-update / idp-fe); SUBCELL_SI
  * is SUBCELL with the local bounds of the limited component relaxed towards
  * the global bounds [gmin, gmax] by the subcell-resolution smoothness
- * indicator (Sec. 4.4, eq. relaxed-bounds). */
-enum { IDP_REF_SUBCELL = 0, IDP_REF_TARGET = 1, IDP_REF_LOW = 2, IDP_REF_SUBCELL_SI = 3 };
+ * indicator (Sec. 4.4, eq. relaxed-bounds); ELEMENTWISE limits every node's
+ * whole correction u^H_i - u^L_i (Zalesak, then for Euler the entropy line
+ * search of eq. convex-provisional-elementwise) and applies the minimum over
+ * the element (Sec. 4.1.2 and 4.2.1). */
+enum { IDP_REF_SUBCELL = 0, IDP_REF_TARGET = 1, IDP_REF_LOW = 2, IDP_REF_SUBCELL_SI = 3,
+       IDP_REF_ELEMENTWISE = 4 };
 
 typedef struct {
   int dim;          /* 1 or 2 */
@@ -44,7 +48,7 @@ typedef struct {
   int eq;           /* IDP_REF_ADVECTION / _BURGERS / _EULER */
   double vel[2];    /* advection velocity, or Burgers direction vector v */
   double gamma;     /* ratio of specific heats (Euler) */
-  int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW / _SUBCELL_SI */
+  int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW / _SUBCELL_SI / _ELEMENTWISE */
   double gmin, gmax; /* global bounds of the limited component (SUBCELL_SI) */
 } idp_ref_desc;
 

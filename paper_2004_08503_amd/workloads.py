@@ -28,9 +28,10 @@ from typing import List, Tuple
 import numpy as np
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET, LOW, SUBCELL_SI = 0, 1, 2, 3
+SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
-LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW, "subcell_si": SUBCELL_SI}
+LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW, "subcell_si": SUBCELL_SI,
+                 "elementwise": ELEMENTWISE}
 
 
 @dataclass
