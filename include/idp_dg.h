@@ -59,7 +59,7 @@ enum {
   IDP_DG_SUBCELL = 0,     /* subcell convex limiting (Sec. 4.1.3, 4.2.2) */
   IDP_DG_TARGET_ONLY = 1, /* alpha = 1: the unlimited high-order update */
   IDP_DG_LOW_ONLY = 2,    /* alpha = 0: the low-order IDP update */
-  IDP_DG_SUBCELL_SI = 3   /* SUBCELL with the local bounds of the limited
+  IDP_DG_SUBCELL_SI = 3,  /* SUBCELL with the local bounds of the limited
                              component (u, or rho for Euler) relaxed by the
                              subcell-resolution smoothness indicator towards
                              the global bounds [gmin, gmax] (Sec. 4.4,
@@ -69,6 +69,13 @@ enum {
                              1/2 + 1/2 sin(pi (s_K - s0)/2) from 0 at
                              s0 - 1 to 1 at s0 + 1, s0 = log10(p^-4); p = 1
                              keeps the strict bounds */
+  IDP_DG_ELEMENTWISE = 4  /* elementwise limiting (Sec. 4.1.2 and the convex
+                             counterpart, eq. convex-provisional-elementwise):
+                             every node limits its whole correction
+                             u^H_i - u^L_i (Zalesak, then the Euler entropy
+                             line search), and each element applies the
+                             minimum over its nodes, u = u^L + alpha_K
+                             (u^H - u^L) */
 };
 
 /* Problem description.  Periodic box [0,lx) x [0,ly) of nx x ny elements

@@ -10,7 +10,7 @@ namespace idp {
 enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2, EQ_EULER53 = 3, EQ_EULER75 = 4 };
 constexpr bool is_euler(int eq) { return eq >= EQ_EULER; }
 constexpr int gn_of(int eq) { return eq == EQ_EULER53 ? 3 : eq == EQ_EULER75 ? 5 : 0; }
-enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2, LIM_SUBCELL_SI = 3 };
+enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2, LIM_SUBCELL_SI = 3, LIM_ELEMENTWISE = 4 };
 constexpr int MAXP = 8;
 
 // Per-degree constants, passed by value in the kernel arguments.

@@ -133,7 +133,7 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) { *why = "lx, ly must be > 0"; return false; }
   if (d->p < 1 || d->p > MAXP) { *why = "p must be in [1, 8]"; return false; }
   if (d->eq < IDP_DG_ADVECTION || d->eq > IDP_DG_EULER) { *why = "unknown equation"; return false; }
-  if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_SUBCELL_SI) { *why = "unknown limiter"; return false; }
+  if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_ELEMENTWISE) { *why = "unknown limiter"; return false; }
   if (d->limiter == IDP_DG_SUBCELL_SI && !(std::isfinite(d->gmin) && std::isfinite(d->gmax) && d->gmin <= d->gmax)) {
     *why = "gmin, gmax must be finite with gmin <= gmax";
     return false;

@@ -701,6 +701,48 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       alpha = 1.0;
     } else if (A.limiter == LIM_LOW) {
       alpha = 0.0;
+    } else if (A.limiter == LIM_ELEMENTWISE) {
+      if (dt > 0.0) {
+        // elementwise limiting (Sec. 4.1.2, eq. convex-provisional-
+        // elementwise): the node's whole correction d = u^H - u^L, the sum
+        // of its subcell-face antidiffusive fluxes; Zalesak with that single
+        // contribution, then the entropy line search along d; the element
+        // minimum is taken in phase 5
+        double d[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          double acc = 0.0;
+          const int pos[2] = {a, b};
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            if (pos[k] < P) acc += lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]];
+            if (pos[k] > 0) acc -= lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
+          }
+          d[c] = dtm * acc;
+        }
+        const double mdt = m * idt;
+        const double f = mdt * d[0];
+        const double Qp = fmax(0.0, mdt * (umax - uL[0]));
+        const double Qm = fmin(0.0, mdt * (umin - uL[0]));
+        alpha = f > 0.0 ? fmin(1.0, Qp / f) : (f < 0.0 ? fmin(1.0, Qm / f) : 1.0);
+        az_dbg = alpha;
+        if constexpr (is_euler(EQ)) {
+          kmin_dbg = kmin;
+          const PhiVal ea = phi_at<DIM, gn_of(EQ)>(alpha, uL, d, kmin, ph_of(A));
+          if (!admissible(ea)) {
+            const double zero[NC] = {};
+            const PhiVal e0 = phi_at<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ph_of(A));
+            if (!admissible(e0)) {
+              alpha = 0.0;
+            } else {
+              double tn = ea.rho > 0.0 && ea.dphi < 0.0 ? alpha - ea.phi / ea.dphi : alpha;
+              tn = fmin(fmax(tn, 0.0), alpha);
+              alpha = entropy_root<DIM, gn_of(EQ)>(uL, d, tn, true, kmin, ph_of(A));
+            }
+          }
+        }
+        alpha = alpha > 0.0 ? alpha : 0.0;
+      }
     } else if (dt > 0.0) {
       double Pp = 0.0, Pm = 0.0;
 #pragma unroll
@@ -831,6 +873,11 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   bool limited = false, ent = false;
   if (own) {
     alpha = lds[C::S_AL + tid];
+    const bool elementwise = A.limiter == LIM_ELEMENTWISE;
+    if (elementwise) {  // one coefficient per element: the minimum over its nodes
+      const double* ae = lds + C::S_AL + le * NP;
+      for (int q = 0; q < NP; ++q) alpha = fmin(alpha, ae[q]);
+    }
     limited = alpha < 1.0;
     ent = is_euler(EQ) && (A.limiter == LIM_SUBCELL || A.limiter == LIM_SUBCELL_SI) && alpha < az_dbg;
     if (A.trace) {
@@ -849,12 +896,12 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       if (pos[k] < P) {
-        const double ap = fmin(alpha, lds[C::S_AL + tid + stride[k]]);
+        const double ap = elementwise ? alpha : fmin(alpha, lds[C::S_AL + tid + stride[k]]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) corr[c] += ap * lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]];
       }
       if (pos[k] > 0) {
-        const double am = fmin(alpha, lds[C::S_AL + tid - stride[k]]);
+        const double am = elementwise ? alpha : fmin(alpha, lds[C::S_AL + tid - stride[k]]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) corr[c] -= am * lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
       }

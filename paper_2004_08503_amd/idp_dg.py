@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libidp_dg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "idp_dg.h")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-SUBCELL, TARGET_ONLY, LOW_ONLY, SUBCELL_SI = 0, 1, 2, 3
+SUBCELL, TARGET_ONLY, LOW_ONLY, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 EINVAL, ENOMEM, EHIP = -1, -2, -3
 
 

@@ -175,3 +175,20 @@ def test_batch_smoothness_indicator_bitwise_equals_plain():
     for a, b in zip(ub, up):
         assert torch.equal(a, b)
     batch.close()
+
+
+def test_batch_elementwise_bitwise_equals_plain():
+    idp_dg = _lib()
+    cases = [(prob.replace(limiter=W.ELEMENTWISE), u) for prob, u in mix(count=5, seed=17)]
+    solvers = [idp_dg.Solver(p) for p, _ in cases]
+    ub = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    up = [torch.from_numpy(u.copy()).cuda() for _, u in cases]
+    batch = idp_dg.Batch(solvers)
+    for _ in range(3):
+        batch.step_cfl(ub, 0.5)
+        for sv, u in zip(solvers, up):
+            sv.step_cfl(u, 0.5)
+    torch.cuda.synchronize()
+    for a, b in zip(ub, up):
+        assert torch.equal(a, b)
+    batch.close()

@@ -347,3 +347,44 @@ def test_smoothness_indicator_rejects_bad_bounds():
     prob = W.Problem(dim=1, nx=4, ny=1, p=3, eq=W.BURGERS, limiter=W.SUBCELL_SI, gmin=1.0, gmax=0.0)
     with pytest.raises(idp_dg.IdpError):
         idp_dg.Solver(prob)
+
+
+@pytest.mark.parametrize("name,wl", SMALL, ids=[s[0] for s in SMALL])
+def test_stage_parity_elementwise(name, wl):
+    prob = wl.prob.replace(limiter=W.ELEMENTWISE)
+    dt = wl.cfl * oracle.max_dt(prob, wl.u0)
+    stage_parity(prob, wl.u0, dt)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
+@pytest.mark.parametrize("eq", ["advection", "burgers", "euler"])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_elementwise_every_degree(p, eq, dim):
+    rng = np.random.default_rng(300 * p + dim)
+    if dim == 1:
+        prob = W.Problem(dim=1, nx=7, ny=1, p=p, eq=W.EQ_NAMES[eq], vel=(-0.7, 0.0), limiter=W.ELEMENTWISE)
+    else:
+        prob = W.Problem(dim=2, nx=5, ny=3, p=p, eq=W.EQ_NAMES[eq], vel=(0.6, 1.1), limiter=W.ELEMENTWISE)
+    if prob.eq == W.EULER:
+        u = W.euler_quadrants(prob, rng)
+    else:
+        u = rng.uniform(-1.0, 1.0, (1, prob.num_nodes))
+    dt = 0.5 * oracle.max_dt(prob, u)
+    stage_parity(prob, u, dt)
+
+
+def test_elementwise_intermediates_match_oracle():
+    idp_dg = _gpu()
+    wl = W.euler_2d(n=12, p=4)
+    prob = wl.prob.replace(limiter=W.ELEMENTWISE)
+    dt = wl.cfl * oracle.max_dt(prob, wl.u0)
+    ref, tr = oracle.fe(prob, wl.u0, dt, trace=True)
+    sv = idp_dg.Solver(prob)
+    out = sv.empty()
+    g = sv.stage_trace(None, to_dev(wl.u0), out, dt, 0).cpu().numpy()
+    np.testing.assert_allclose(g[3], tr["alpha_z"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
+    a = g[4].reshape(-1, 25)
+    assert np.all(a == a[:, :1]) and (a < 1).any()
+    assert rel_err(out.cpu().numpy(), ref) <= 1e-12
+    sv.close()
