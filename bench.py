@@ -306,6 +306,7 @@ def main():
     out["modes"] = {} if args.no_modes else {
         "subcell_si": mode_leg(wl, prob.replace(limiter=W.SUBCELL_SI, gmin=float(rho0.min()),
                                                 gmax=float(rho0.max())), 50),
+        "elementwise": mode_leg(wl, prob.replace(limiter=W.ELEMENTWISE), 50),
         "target_only": mode_leg(wl, prob.replace(limiter=W.TARGET), 50),
         "low_only": mode_leg(wl, prob.replace(limiter=W.LOW), 50),
     }
