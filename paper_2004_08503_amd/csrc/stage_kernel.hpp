@@ -873,13 +873,14 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   bool limited = false, ent = false;
   if (own) {
     alpha = lds[C::S_AL + tid];
+    // the node's own coefficient was lowered by the entropy search
+    ent = is_euler(EQ) && A.limiter != LIM_TARGET && A.limiter != LIM_LOW && alpha < az_dbg;
     const bool elementwise = A.limiter == LIM_ELEMENTWISE;
     if (elementwise) {  // one coefficient per element: the minimum over its nodes
       const double* ae = lds + C::S_AL + le * NP;
       for (int q = 0; q < NP; ++q) alpha = fmin(alpha, ae[q]);
     }
     limited = alpha < 1.0;
-    ent = is_euler(EQ) && (A.limiter == LIM_SUBCELL || A.limiter == LIM_SUBCELL_SI) && alpha < az_dbg;
     if (A.trace) {
       const long long g = (long long)e0 * NP + tid;
       A.trace[g] = umin;

@@ -388,3 +388,45 @@ def test_elementwise_intermediates_match_oracle():
     assert np.all(a == a[:, :1]) and (a < 1).any()
     assert rel_err(out.cpu().numpy(), ref) <= 1e-12
     sv.close()
+
+
+@pytest.mark.parametrize("limiter", [W.SUBCELL, W.SUBCELL_SI, W.ELEMENTWISE],
+                         ids=["subcell", "subcell_si", "elementwise"])
+def test_diagnostics_count_the_traced_coefficients(limiter):
+    """The limiter counters of one stage against the stage's own trace:
+    limited nodes are those with alpha < 1; entropy nodes are those whose
+    own coefficient the entropy search lowered below alpha_z (read from the
+    trace where it holds node coefficients; for elementwise limiting, where
+    it holds the element minimum, bracketed from the oracle's u^L, u^H and
+    K_min: at least the nodes whose state at alpha_z is clearly inadmissible,
+    at most those not clearly admissible.  The bracket is needed: with the
+    velocity and pressure uniform in a quadrant every flux is linear in the
+    density, the update keeps them uniform, K >= K_min is then the same
+    constraint as the density's upper bound, and where Zalesak clips the
+    density to that bound the state at alpha_z lies on Phi = 0 up to
+    rounding)."""
+    idp_dg = _gpu()
+    wl = W.euler_2d(n=12, p=4)
+    # 1 % noise on the energy too, so that the pressure is not uniform in a
+    # quadrant and the entropy bound binds clearly at some nodes
+    u = wl.u0.copy()
+    u[3] *= 1 + 0.01 * np.random.default_rng(7).uniform(-1, 1, u.shape[1])
+    prob = wl.prob.replace(limiter=limiter, gmin=float(u[0].min()), gmax=float(u[0].max()))
+    dt = wl.cfl * oracle.max_dt(prob, u)
+    sv = idp_dg.Solver(prob)
+    sv.diagnostics()   # reset
+    out = sv.empty()
+    g = sv.stage_trace(None, to_dev(u), out, dt, 0).cpu().numpy()
+    d = sv.diagnostics()
+    assert d["limited_nodes"] == int((g[4] < 1.0).sum()) > 0
+    if limiter != W.ELEMENTWISE:
+        assert d["entropy_nodes"] == int((g[4] < g[3]).sum()) > 0
+    else:
+        _, tr = oracle.fe(prob, u, dt, trace=True)
+        v = tr["uL"] + tr["alpha_z"] * (tr["uH"] - tr["uL"])
+        rhoe = v[3] - 0.5 * (v[1] ** 2 + v[2] ** 2) / v[0]
+        r = (rhoe - tr["kmin"] * v[0] ** prob.gamma / (prob.gamma - 1.0)) / np.abs(rhoe)
+        lo = int(((v[0] <= 0) | (r < -1e-12)).sum())
+        hi = int(((v[0] <= 0) | (r < 1e-12)).sum())
+        assert 0 < lo <= d["entropy_nodes"] <= hi, (lo, d["entropy_nodes"], hi)
+    sv.close()
