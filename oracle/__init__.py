@@ -10,7 +10,9 @@ path never does.
 Problem descriptions are duck-typed: any object with the attributes
 ``dim, nx, ny, lx, ly, p, eq, vel, gamma, limiter`` (``eq`` and ``limiter``
 as the integer codes below; ``gmin, gmax`` too for SUBCELL_SI) is accepted,
-e.g. the seeded workload objects.
+e.g. the seeded workload objects.  ADVECTION_FIELD takes the nodal
+velocity from ``beta`` (shape (2, Nn)) when the object has one, else from
+the per-row / per-column samples ``vrows``, ``vcols``.
 State arrays are float64 of shape ``(nc, Nn)`` in the layout ``u[c][e][b][a]``.
 """
 import ctypes
@@ -23,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "idp_ref.c")
 _LIB_PATH = os.path.join(_HERE, "libidp_ref.so")
 
-ADVECTION, BURGERS, EULER = 0, 1, 2
+ADVECTION, BURGERS, EULER, ADVECTION_FIELD = 0, 1, 2, 3
 SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 
 
@@ -42,7 +44,8 @@ class _Desc(ctypes.Structure):
                 ("p", ctypes.c_int), ("eq", ctypes.c_int),
                 ("vel", ctypes.c_double * 2), ("gamma", ctypes.c_double),
                 ("limiter", ctypes.c_int),
-                ("gmin", ctypes.c_double), ("gmax", ctypes.c_double)]
+                ("gmin", ctypes.c_double), ("gmax", ctypes.c_double),
+                ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Trace(ctypes.Structure):
@@ -99,7 +102,30 @@ def _desc(prob):
     d.limiter = int(prob.limiter)
     d.gmin = float(getattr(prob, "gmin", 0.0))
     d.gmax = float(getattr(prob, "gmax", 0.0))
+    if d.eq == ADVECTION_FIELD:
+        beta = nodal_velocity(prob)
+        d.beta = _ptr(beta)
+        d._keep = beta          # the array lives as long as the descriptor
     return d
+
+
+def nodal_velocity(prob):
+    """The velocity at every node, shape (2, Nn): ``prob.beta`` if given,
+    else beta_x from the node's row sample and beta_y from its column
+    sample (node i of element e = ey*nx + ex at local (a, b) sits on row
+    ey*(p+1) + b and column ex*(p+1) + a)."""
+    beta = getattr(prob, "beta", None)
+    if beta is not None:
+        return np.ascontiguousarray(beta, dtype=np.float64).reshape(2, -1)
+    n1 = prob.p + 1
+    vr = np.asarray(prob.vrows, dtype=np.float64)
+    vc = np.asarray(prob.vcols, dtype=np.float64)
+    if vr.size != prob.ny * n1 or vc.size != prob.nx * n1:
+        return np.full((2, prob.nx * prob.ny * n1 * n1), np.nan)
+    ey, ex, b, a = np.meshgrid(np.arange(prob.ny), np.arange(prob.nx), np.arange(n1),
+                               np.arange(n1), indexing="ij")
+    return np.ascontiguousarray(np.stack([vr[(ey * n1 + b).reshape(-1)],
+                                          vc[(ex * n1 + a).reshape(-1)]]))
 
 
 def _ptr(a):

@@ -6,7 +6,8 @@
  *
  *   O0 tables          Sec. 2.1-2.2 (Gauss-Lobatto basis, eq. P1/P2),
  *                      Sec. 3 (eq. didp)
- *   O1 pointwise flux  eq. cons-law, eq. euler-eos / euler-flux
+ *   O1 pointwise flux  eq. cons-law, eq. euler-eos / euler-flux; for a
+ *                      velocity field the nodal flux beta_i u_i (Sec. 3.3)
  *   O2 wave speeds     eq. riemann-problem, eq. lax-friedrichs
  *   O3/O4 residuals    eq. ho-update (strong form, eq. dg-strong) and
  *                      eq. lo-update (weak form with Dhat + graph viscosity,
@@ -14,7 +15,8 @@
  *   O5 low-order state eq. lo-update
  *   O6 subcell fluxes  Sec. 4.1.3 (rbar as sums of nodal antidiffusive
  *                      fluxes on one side of a subcell face)
- *   O7 bounds          eq. bar-states, Sec. 4.1.1, Sec. 4.3 (Euler)
+ *   O7 bounds          eq. bar-states, Sec. 4.1.1, Sec. 4.3 (Euler); the
+ *                      modified bar states of Sec. 3.3 for a velocity field
  *   O8 Zalesak         Sec. 4.1.2-4.1.3
  *   O9 entropy search  eq. convex-provisional, Sec. 4.3
  *   O10 update         eq. subcell-fct / convex-fct
@@ -47,6 +49,8 @@ typedef struct {
 /* argument checks                                                     */
 /* ------------------------------------------------------------------ */
 
+static int field_check(const idp_ref_desc* d);
+
 int idp_ref_check(const idp_ref_desc* d) {
   if (!d) return -1;
   if (d->dim != 1 && d->dim != 2) return -1;
@@ -54,13 +58,14 @@ int idp_ref_check(const idp_ref_desc* d) {
   if (d->dim == 1 && d->ny != 1) return -1;
   if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) return -1;
   if (d->p < 1 || d->p > MAXP) return -1;
-  if (d->eq < IDP_REF_ADVECTION || d->eq > IDP_REF_EULER) return -1;
+  if (d->eq < IDP_REF_ADVECTION || d->eq > IDP_REF_ADVECTION_FIELD) return -1;
   if (d->limiter < IDP_REF_SUBCELL || d->limiter > IDP_REF_ELEMENTWISE) return -1;
   if (d->limiter == IDP_REF_SUBCELL_SI && !(d->gmin <= d->gmax && isfinite(d->gmin) && isfinite(d->gmax)))
     return -1;
   /* the two-rarefaction wave-speed bound holds for 1 < gamma <= 5/3 */
   if (d->eq == IDP_REF_EULER && !(d->gamma > 1.0 && d->gamma <= 5.0 / 3.0))
     return -1;
+  if (d->eq == IDP_REF_ADVECTION_FIELD && field_check(d)) return -1;
   return 0;
 }
 
@@ -269,7 +274,7 @@ static double lambda(const ref_t* R, const double* uL, const double* uR,
 
 int idp_ref_flux(const idp_ref_desc* d, const double* u, double* F) {
   ref_t R;
-  if (setup(&R, d)) return -1;
+  if (setup(&R, d) || d->eq == IDP_REF_ADVECTION_FIELD) return -1;
   flux(&R, u, F);
   return 0;
 }
@@ -277,19 +282,42 @@ int idp_ref_flux(const idp_ref_desc* d, const double* u, double* F) {
 double idp_ref_lambda(const idp_ref_desc* d, const double* uL,
                       const double* uR, const double* n) {
   ref_t R;
-  if (setup(&R, d)) return NAN;
+  if (setup(&R, d) || d->eq == IDP_REF_ADVECTION_FIELD) return NAN;
   return lambda(&R, uL, uR, n);
 }
 
-/* Lax-Friedrichs numerical flux (eq. lax-friedrichs) for one component
- * set: Fh = 1/2 (F(um) + F(up)) . n - lambda/2 (up - um). */
-static void lax_friedrichs(const ref_t* R, const double* um, const double* up,
-                           const double* n, double* Fh) {
+/* The flux at node i with state ui: F(ui), or beta_i ui for a velocity
+ * field (the collocated flux of Sec. 3.3). */
+static void flux_node(const ref_t* R, const double* ui, long i, double* F) {
+  if (R->d.eq == IDP_REF_ADVECTION_FIELD) {
+    for (int k = 0; k < R->d.dim; ++k) F[k] = R->d.beta[(long)k * R->nn + i] * ui[0];
+    return;
+  }
+  flux(R, ui, F);
+}
+
+/* Lax-Friedrichs numerical flux (eq. lax-friedrichs) between node im
+ * (state um) and node ip (state up) on an element face: Fh = 1/2 (F_m +
+ * F_p) . n - lambda/2 (up - um).  Reading for a velocity field: lambda =
+ * max(|beta_m . n|, |beta_p . n|); the two nodes sit at one point, where
+ * the field has one value. */
+static void lax_friedrichs(const ref_t* R, const double* um, long im, const double* up,
+                           long ip, const double* n, double* Fh) {
   double Fm[2 * MAXC], Fp[2 * MAXC];
   int nc = R->nc;
-  flux(R, um, Fm);
-  flux(R, up, Fp);
-  double lam = lambda(R, um, up, n);
+  flux_node(R, um, im, Fm);
+  flux_node(R, up, ip, Fp);
+  double lam;
+  if (R->d.eq == IDP_REF_ADVECTION_FIELD) {
+    double bm = 0.0, bp = 0.0;
+    for (int k = 0; k < R->d.dim; ++k) {
+      bm += R->d.beta[(long)k * R->nn + im] * n[k];
+      bp += R->d.beta[(long)k * R->nn + ip] * n[k];
+    }
+    lam = fmax(fabs(bm), fabs(bp));
+  } else {
+    lam = lambda(R, um, up, n);
+  }
   for (int c = 0; c < nc; ++c) {
     double fn = 0.0;
     for (int k = 0; k < R->d.dim; ++k)
@@ -384,13 +412,31 @@ static void graph_coeffs(const ref_t* R, const double* u, long i, int k, int s,
                          long* j_out, double* chat, double* dhat) {
   int across, t;
   long j = neighbour(R, i, k, s, &across);
-  double ui[MAXC], uj[MAXC];
-  get_state(R, u, i, ui);
-  get_state(R, u, j, uj);
   double scale = line_scale(R, k, (line_pos(R, i, k, &t), t));
   double e_ij[2] = {0.0, 0.0}, e_ji[2] = {0.0, 0.0};
   e_ij[k] = (double)s;
   e_ji[k] = (double)-s;
+  if (R->d.eq == IDP_REF_ADVECTION_FIELD) {
+    /* Sec. 3.3: dhat_ij = max(|chat_ij . beta_i|, |chat_ji . beta_j|) */
+    double bi = R->d.beta[(long)k * R->nn + i], bj = R->d.beta[(long)k * R->nn + j];
+    double cij, cji;
+    if (across) {
+      cij = -0.5 * scale * (double)s;
+      cji = 0.5 * scale * (double)s;
+    } else {
+      int ai = line_pos(R, i, k, &t);
+      cij = scale * R->Dh[(ai + s) * R->n1 + ai];
+      cji = scale * R->Dh[ai * R->n1 + ai + s];
+    }
+    double d1 = fabs(cij * bi), d2 = fabs(cji * bj);
+    *chat = cij;
+    *dhat = d1 > d2 ? d1 : d2;
+    *j_out = j;
+    return;
+  }
+  double ui[MAXC], uj[MAXC];
+  get_state(R, u, i, ui);
+  get_state(R, u, j, uj);
   if (across) {
     double wn = scale; /* |wn_ij|: face weight times face metric */
     *chat = -0.5 * wn * (double)s;
@@ -407,6 +453,48 @@ static void graph_coeffs(const ref_t* R, const double* u, long i, int k, int s,
     *dhat = d1 > d2 ? d1 : d2;
   }
   *j_out = j;
+}
+
+/* The discrete divergence-free identity of a velocity field (Sec. 3.3):
+ * per node and direction, sum_{j != i} chat_ij beta_{j,k} = 0 within 1e-12
+ * of sum |chat_ij beta_{j,k}|.  Reading: the paper requires this identity
+ * for the low-order update to be conservative and the bar states to be
+ * the update's convex decomposition, and says that the conservative
+ * correction must be adapted to enforce it without giving the adaptation;
+ * fields that miss it are rejected rather than corrected.  Fields with
+ * beta_x depending on y only and beta_y on x only meet it on Cartesian
+ * meshes (beta_{j,k} is constant along a k-line and the chat_ij of a line
+ * sum to zero). */
+static int field_check(const idp_ref_desc* d) {
+  if (d->dim != 2 || !d->beta) return -1;
+  ref_t Rs, *R = &Rs;
+  memset(R, 0, sizeof(*R));
+  R->d = *d;
+  R->nc = 1;
+  R->n1 = d->p + 1;
+  R->np = R->n1 * R->n1;
+  R->ne = (long)d->nx * d->ny;
+  R->nn = R->ne * R->np;
+  R->hx = d->lx / d->nx;
+  R->hy = d->ly / d->ny;
+  if (idp_ref_gl(d->p, R->xi, R->w) || idp_ref_dhat(d->p, R->Dh)) return -1;
+  for (long q = 0; q < 2 * R->nn; ++q)
+    if (!isfinite(d->beta[q])) return -1;
+  for (long i = 0; i < R->nn; ++i) {
+    for (int k = 0; k < 2; ++k) {
+      double sum = 0.0, mag = 0.0;
+      for (int sd = -1; sd <= 1; sd += 2) {
+        long j;
+        double chat, dhat;
+        graph_coeffs(R, NULL, i, k, sd, &j, &chat, &dhat);
+        double t = chat * d->beta[(long)k * R->nn + j];
+        sum += t;
+        mag += fabs(t);
+      }
+      if (fabs(sum) > 1e-12 * mag) return -1;
+    }
+  }
+  return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -565,6 +653,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   const long nn = R->nn;
   const int lim = 0; /* limited component: u (scalar) or rho (Euler) */
   const int euler = R->d.eq == IDP_REF_EULER;
+  const int field = R->d.eq == IDP_REF_ADVECTION_FIELD;
 
   if (dt == 0.0) { /* a zero step leaves the state unchanged */
     memcpy(out, u, sizeof(double) * nc * nn);
@@ -594,7 +683,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   for (long i = 0; i < nn; ++i) {
     double ui[MAXC], Fi[2 * MAXC];
     get_state(R, u, i, ui);
-    flux(R, ui, Fi);
+    flux_node(R, ui, i, Fi);
     for (int k = 0; k < dim; ++k)
       for (int c = 0; c < nc; ++c) F[IDX3(k, c, i)] = Fi[k * nc + c];
   }
@@ -623,8 +712,8 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
           get_state(R, u, jr, ujr);
           /* numerical fluxes on the two element faces of this line, with
            * the outward unit normal of this element */
-          lax_friedrichs(R, u0, ujl, nm, FhL);
-          lax_friedrichs(R, up, ujr, np_, FhR);
+          lax_friedrichs(R, u0, line[0], ujl, jl, nm, FhL);
+          lax_friedrichs(R, up, line[p], ujr, jr, np_, FhR);
 
           for (int a = 0; a <= p; ++a) {
             long i = line[a];
@@ -648,6 +737,25 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
               if (a == 0) rl -= s * FhL[c];
               if (a == p) rl -= s * FhR[c];
               rL[IDX3(k, c, i)] = rl;
+            }
+            if (field) {
+              /* Sec. 3.3: the low-order update as the convex combination
+               * of the modified bar states, sum_j 2 dhat_ij (ubar_ij - u_i)
+               * = sum_j (dhat_ij + chat_ij . beta_j) (u_j - u_i), over
+               * the two neighbours of i on this line (inside the element
+               * or across its face) */
+              double ui[MAXC];
+              get_state(R, u, i, ui);
+              double rl = 0.0;
+              for (int sd = -1; sd <= 1; sd += 2) {
+                long j;
+                double chat, dhat, uj[MAXC];
+                graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat);
+                get_state(R, u, j, uj);
+                rl += (dhat + chat * R->d.beta[(long)k * nn + j]) * (uj[0] - ui[0]);
+              }
+              rL[IDX3(k, 0, i)] = rl;
+              continue;
             }
             /* graph viscosity d_ij (eq. dij) between i and its neighbours
              * on the same line inside the element */
@@ -709,7 +817,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   for (long i = 0; i < nn; ++i) {
     double ui[MAXC], Fi[2 * MAXC];
     get_state(R, u, i, ui);
-    flux(R, ui, Fi);
+    flux_node(R, ui, i, Fi);
     double lo = ui[lim], hi = ui[lim];
     double km = 0.0;
     if (euler) km = euler_pressure(R, ui) * pow(ui[0], -R->d.gamma);
@@ -720,12 +828,15 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
         graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat);
         double uj[MAXC], Fj[2 * MAXC];
         get_state(R, u, j, uj);
-        flux(R, uj, Fj);
+        flux_node(R, uj, j, Fj);
         double bar = 0.5 * (ui[lim] + uj[lim]);
-        /* reading: with dhat_ij = 0 the flux term is 0/0 (F_j = F_i); the
-         * bar state is then the plain average */
-        if (dhat > 0.0)
-          bar += chat * (Fj[k * nc + lim] - Fi[k * nc + lim]) / (2.0 * dhat);
+        /* eq. bar-states; for a velocity field the modified bar state of
+         * Sec. 3.3, with chat_ij . beta_j (u_j - u_i) in place of
+         * chat_ij . (F_j - F_i).  Reading: with dhat_ij = 0 the flux term
+         * is 0/0; the bar state is then the plain average */
+        double dF = field ? R->d.beta[(long)k * nn + j] * (uj[lim] - ui[lim])
+                          : Fj[k * nc + lim] - Fi[k * nc + lim];
+        if (dhat > 0.0) bar += chat * dF / (2.0 * dhat);
         if (bar < lo) lo = bar;
         if (bar > hi) hi = bar;
         if (euler) {

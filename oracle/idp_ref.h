@@ -26,7 +26,11 @@
 extern "C" {
 #endif
 
-enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2 };
+/* ADVECTION_FIELD is u_t + div(beta(x) u) = 0 with a prescribed,
+ * divergence-free velocity field given by its nodal values (Sec. 3.3; 2-D
+ * only: a divergence-free field in 1-D is constant). */
+enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2,
+       IDP_REF_ADVECTION_FIELD = 3 };
 
 /* Limiter modes: SUBCELL is the subcell convex limiter (Sec. 4.1.3 and
  * 4.2.2); TARGET returns the unlimited high-order update (eq. ho-update);
@@ -50,6 +54,12 @@ typedef struct {
   double gamma;     /* ratio of specific heats (Euler) */
   int limiter;      /* IDP_REF_SUBCELL / _TARGET / _LOW / _SUBCELL_SI / _ELEMENTWISE */
   double gmin, gmax; /* global bounds of the limited component (SUBCELL_SI) */
+  const double* beta; /* ADVECTION_FIELD: nodal velocity beta[k*Nn + i],
+                         k < dim (host, read during each call); the field
+                         must satisfy the discrete divergence-free identity
+                         sum_j chat_ij . beta_j = 0 at every node (checked,
+                         1e-12 relative), which fields with beta_x = beta_x(y)
+                         and beta_y = beta_y(x) meet on Cartesian meshes */
 } idp_ref_desc;
 
 /* Optional per-node outputs of one forward-Euler sub-step.  Any pointer may
@@ -78,7 +88,8 @@ int idp_ref_dmat(int p, double* D);
 int idp_ref_dhat(int p, double* Dh);
 
 /* Pointwise physics: F[k*nc + c] for k < dim; lambda for the 1-D Riemann
- * problem with left state uL, right state uR along the unit vector n. */
+ * problem with left state uL, right state uR along the unit vector n.
+ * Both need a state-only flux: -1 / NaN for ADVECTION_FIELD. */
 int idp_ref_flux(const idp_ref_desc* d, const double* u, double* F);
 double idp_ref_lambda(const idp_ref_desc* d, const double* uL,
                       const double* uR, const double* n);

@@ -21,15 +21,20 @@ dataset):
     per quadrant, node density times (1 + 0.01 U(-1,1)).
   * ``batch_mix``     -- many Euler solves of uneven n in [32, 256] and p in
     {2..6}, each with its own quadrant data.
+  * ``solid_body``    -- u_t + div(beta u) = 0 on [0,1]^2 with the rotation
+    field beta = 2 pi (1/2 - y, x - 1/2), 64^2, p = 3: a smooth bump, a cone
+    and a slotted cylinder of radius 0.15 (the paper's Sec. 5 test); one
+    revolution takes t = 1.
 """
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
 import numpy as np
 
-ADVECTION, BURGERS, EULER = 0, 1, 2
+ADVECTION, BURGERS, EULER, ADVECTION_FIELD = 0, 1, 2, 3
 SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
-EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER}
+EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER,
+            "advection_field": ADVECTION_FIELD}
 LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW, "subcell_si": SUBCELL_SI,
                  "elementwise": ELEMENTWISE}
 
@@ -48,6 +53,11 @@ class Problem:
     limiter: int = SUBCELL
     gmin: float = 0.0     # global bounds of the limited component (SUBCELL_SI)
     gmax: float = 0.0
+    # ADVECTION_FIELD: the velocity beta = (beta_x(y), beta_y(x)) sampled on
+    # the node rows (beta_x at y = (ey + xi_b) hy, index ey*(p+1) + b) and
+    # the node columns (beta_y at x = (ex + xi_a) hx, index ex*(p+1) + a)
+    vrows: Tuple[float, ...] = ()
+    vcols: Tuple[float, ...] = ()
 
     @property
     def nc(self) -> int:
@@ -195,6 +205,41 @@ def batch_mix(count: int = 64, n_range=(32, 256), p_choices=(2, 3, 4, 5, 6),
         out.append(Workload("euler_2d_batch", prob, u, cfl=0.5, steps=50,
                             seed=seed, meta={"index": s}))
     return out
+
+
+def rotation_lines(prob: Problem, omega: float = 2.0 * np.pi, centre=(0.5, 0.5)):
+    """The solid-body rotation field beta = omega (c_y - y, x - c_x) on the
+    node rows and columns of prob (see Problem.vrows / vcols)."""
+    xi = gl_points(prob.p)
+    hx, hy = prob.lx / prob.nx, prob.ly / prob.ny
+    y = ((np.arange(prob.ny)[:, None] + xi[None, :]) * hy).reshape(-1)
+    x = ((np.arange(prob.nx)[:, None] + xi[None, :]) * hx).reshape(-1)
+    return tuple(omega * (centre[1] - y)), tuple(omega * (x - centre[0]))
+
+
+def solid_body_state(x, y):
+    """The three bodies at points (x, y): bump at (0.25, 0.5), cone at
+    (0.5, 0.25), slotted cylinder at (0.5, 0.75), radius 0.15, zero
+    elsewhere."""
+    r0 = 0.15
+    u = np.zeros_like(x)
+    r = np.hypot(x - 0.25, y - 0.5) / r0
+    u = np.where(r <= 1.0, 0.25 * (1.0 + np.cos(np.pi * r)), u)
+    r = np.hypot(x - 0.5, y - 0.25) / r0
+    u = np.where(r <= 1.0, 1.0 - r, u)
+    r = np.hypot(x - 0.5, y - 0.75) / r0
+    cyl = (np.abs(x - 0.5) >= 0.025) | (y >= 0.85)
+    u = np.where(r <= 1.0, cyl.astype(np.float64), u)
+    return u
+
+
+def solid_body(n: int = 64, p: int = 3, limiter: int = SUBCELL) -> Workload:
+    prob = Problem(dim=2, nx=n, ny=n, p=p, eq=ADVECTION_FIELD, limiter=limiter)
+    vr, vc = rotation_lines(prob)
+    prob = prob.replace(vrows=vr, vcols=vc)
+    x, y, _ = node_coords(prob)
+    return Workload("solid_body", prob, solid_body_state(x, y)[None, :].copy(), cfl=0.5,
+                    steps=0, meta={"t_end": 1.0})
 
 
 def small_cases():
