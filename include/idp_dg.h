@@ -51,7 +51,17 @@ extern "C" {
 enum {
   IDP_DG_ADVECTION = 0, /* u_t + div(v u) = 0, constant v = velocity */
   IDP_DG_BURGERS = 1,   /* u_t + div(u^2/2 v) = 0, constant direction v */
-  IDP_DG_EULER = 2      /* compressible Euler, ideal gas with gamma */
+  IDP_DG_EULER = 2,     /* compressible Euler, ideal gas with gamma */
+  IDP_DG_ADVECTION_FIELD = 3 /* u_t + div(beta(x) u) = 0 with a prescribed
+                             velocity field (Sec. 3.3: modified bar states
+                             and graph viscosity dhat_ij = max(|chat_ij .
+                             beta_i|, |chat_ji . beta_j|)); dim = 2, and the
+                             field has the form beta = (beta_x(y), beta_y(x))
+                             (desc.vel_rows, desc.vel_cols), which satisfies
+                             the discrete divergence-free identity sum_j
+                             chat_ij . beta_j = 0 the method needs on
+                             Cartesian meshes; the solid-body rotation
+                             field is of this form */
 };
 
 /* limiter modes */
@@ -81,7 +91,13 @@ enum {
 /* Problem description.  Periodic box [0,lx) x [0,ly) of nx x ny elements
  * (ny = 1 and ly ignored when dim = 1); p in [1, 8]; velocity is the
  * advection velocity or the Burgers direction vector; gamma in (1, 5/3]
- * for Euler (the range where the wave-speed bound used is proven). */
+ * for Euler (the range where the wave-speed bound used is proven).
+ * For IDP_DG_ADVECTION_FIELD, vel_rows and vel_cols are host arrays read
+ * (and copied to the device) during idp_dg_create / idp_dg_create_in only:
+ * vel_rows[ey*(p+1) + b] = beta_x on the node row y = (ey + xi_b) hy and
+ * vel_cols[ex*(p+1) + a] = beta_y on the node column x = (ex + xi_a) hx,
+ * xi the Gauss-Lobatto points on [0,1]; ny*(p+1) and nx*(p+1) finite
+ * doubles.  Other equations ignore them (NULL is fine). */
 typedef struct {
   int dim;
   int nx, ny;
@@ -93,6 +109,8 @@ typedef struct {
   int limiter;
   double gmin, gmax;  /* global bounds of the limited component, used by
                          IDP_DG_SUBCELL_SI (finite, gmin <= gmax) */
+  const double* vel_rows; /* IDP_DG_ADVECTION_FIELD: beta_x per node row */
+  const double* vel_cols; /* IDP_DG_ADVECTION_FIELD: beta_y per node column */
 } idp_dg_desc;
 
 typedef struct idp_dg idp_dg;

@@ -7,8 +7,10 @@ namespace idp {
 // Equation codes of the kernels.  Euler comes in three instantiations:
 // generic gamma, and gamma = 1 + 2/n with n = 3 (5/3) or n = 5 (7/5), where
 // the fractional powers become integer powers of one inverse root.
-enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2, EQ_EULER53 = 3, EQ_EULER75 = 4 };
-constexpr bool is_euler(int eq) { return eq >= EQ_EULER; }
+// EQ_ADVV is advection by a velocity field beta = (beta_x(y), beta_y(x))
+// given per node row and column (2-D only).
+enum { EQ_ADV = 0, EQ_BURG = 1, EQ_EULER = 2, EQ_EULER53 = 3, EQ_EULER75 = 4, EQ_ADVV = 5 };
+constexpr bool is_euler(int eq) { return eq >= EQ_EULER && eq <= EQ_EULER75; }
 constexpr int gn_of(int eq) { return eq == EQ_EULER53 ? 3 : eq == EQ_EULER75 ? 5 : 0; }
 enum { LIM_SUBCELL = 0, LIM_TARGET = 1, LIM_LOW = 2, LIM_SUBCELL_SI = 3, LIM_ELEMENTWISE = 4 };
 constexpr int MAXP = 8;
@@ -26,6 +28,8 @@ struct Tables {
 // Physics constants of one problem.
 struct Phys {
   double vel0, vel1;   // advection velocity / Burgers direction
+  const double* vrow;  // EQ_ADVV: beta_x of every node row (ny*(p+1), device)
+  const double* vcol;  // EQ_ADVV: beta_y of every node column (nx*(p+1), device)
   double gamma;        // Euler
   double ex;           // (gamma-1)/(2 gamma)
   double inv_ex;       // 2 gamma/(gamma-1)
@@ -133,6 +137,7 @@ IDP_DECLARE_LAUNCHERS(euler53_1)
 IDP_DECLARE_LAUNCHERS(euler53_2)
 IDP_DECLARE_LAUNCHERS(euler75_1)
 IDP_DECLARE_LAUNCHERS(euler75_2)
+IDP_DECLARE_LAUNCHERS(advv2)
 
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);

@@ -29,6 +29,7 @@ struct idp_dg {
   Diag* diag = nullptr;
   double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
   double* partial = nullptr;   // per-workgroup minima of the time-step kernel
+  double* vel = nullptr;       // IDP_DG_ADVECTION_FIELD: row then column velocities
   // cached graph of one device-timestepped step
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;

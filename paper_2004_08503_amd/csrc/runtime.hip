@@ -132,7 +132,7 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   if (d->dim == 1 && d->ny != 1) { *why = "ny must be 1 when dim = 1"; return false; }
   if (!(d->lx > 0.0) || (d->dim == 2 && !(d->ly > 0.0))) { *why = "lx, ly must be > 0"; return false; }
   if (d->p < 1 || d->p > MAXP) { *why = "p must be in [1, 8]"; return false; }
-  if (d->eq < IDP_DG_ADVECTION || d->eq > IDP_DG_EULER) { *why = "unknown equation"; return false; }
+  if (d->eq < IDP_DG_ADVECTION || d->eq > IDP_DG_ADVECTION_FIELD) { *why = "unknown equation"; return false; }
   if (d->limiter < IDP_DG_SUBCELL || d->limiter > IDP_DG_ELEMENTWISE) { *why = "unknown limiter"; return false; }
   if (d->limiter == IDP_DG_SUBCELL_SI && !(std::isfinite(d->gmin) && std::isfinite(d->gmax) && d->gmin <= d->gmax)) {
     *why = "gmin, gmax must be finite with gmin <= gmax";
@@ -145,6 +145,14 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   const long long n1 = d->p + 1;
   const long long nn = (long long)d->nx * d->ny * (d->dim == 2 ? n1 * n1 : n1);
   if ((long long)d->nx * d->ny > 0x7fffffffLL || nn > (1LL << 40)) { *why = "mesh too large"; return false; }
+  if (d->eq == IDP_DG_ADVECTION_FIELD) {
+    if (d->dim != 2) { *why = "a velocity field needs dim = 2"; return false; }
+    if (!d->vel_rows || !d->vel_cols) { *why = "vel_rows and vel_cols must be non-NULL"; return false; }
+    for (long long i = 0; i < d->ny * n1; ++i)
+      if (!std::isfinite(d->vel_rows[i])) { *why = "vel_rows must be finite"; return false; }
+    for (long long i = 0; i < d->nx * n1; ++i)
+      if (!std::isfinite(d->vel_cols[i])) { *why = "vel_cols must be finite"; return false; }
+  }
   return true;
 }
 
@@ -164,6 +172,7 @@ hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
     case 7: return launch_stage_euler53_2(p, h->variant, a, s);
     case 8: return launch_stage_euler75_1(p, h->variant, a, s);
     case 9: return launch_stage_euler75_2(p, h->variant, a, s);
+    case 11: return launch_stage_advv2(p, h->variant, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -181,6 +190,7 @@ hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
     case 7: return launch_maxdt_euler53_2(p, a, s);
     case 8: return launch_maxdt_euler75_1(p, a, s);
     case 9: return launch_maxdt_euler75_2(p, a, s);
+    case 11: return launch_maxdt_advv2(p, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -198,6 +208,7 @@ int tile_elems(const idp_dg* h) {
     case 7: return tile_elems_euler53_2(p, h->variant);
     case 8: return tile_elems_euler75_1(p, h->variant);
     case 9: return tile_elems_euler75_2(p, h->variant);
+    case 11: return tile_elems_advv2(p, h->variant);
   }
   return 1;
 }
@@ -293,6 +304,7 @@ int batch_kernels(int fam, int p, BatchKernels* k) {
     case 7: return batch_kernels_euler53_2(p, k);
     case 8: return batch_kernels_euler75_1(p, k);
     case 9: return batch_kernels_euler75_2(p, k);
+    case 11: return batch_kernels_advv2(p, k);
   }
   return -1;
 }
@@ -370,7 +382,7 @@ long long ws_up(long long x) { return (x + kWsAlign - 1) / kWsAlign * kWsAlign; 
 
 // Offsets of the handle's device buffers in one workspace.
 struct WsLayout {
-  long long buf1, buf2, diag, dtdev, partial, total;
+  long long buf1, buf2, diag, dtdev, partial, vel, total;
 };
 
 WsLayout ws_layout(const idp_dg_desc* d) {
@@ -384,7 +396,8 @@ WsLayout ws_layout(const idp_dg_desc* d) {
   L.diag = ws_up(L.buf2 + 8 * nc * nn);
   L.dtdev = ws_up(L.diag + (long long)sizeof(Diag));
   L.partial = ws_up(L.dtdev + 64);
-  L.total = ws_up(L.partial + 8 * (ne + 64));
+  L.vel = ws_up(L.partial + 8 * (ne + 64));
+  L.total = ws_up(L.vel + (d->eq == IDP_DG_ADVECTION_FIELD ? 8 * n1 * (d->nx + d->ny) : 0));
   return L;
 }
 
@@ -414,6 +427,23 @@ int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream, void* workspace,
 }
 
 namespace {
+// Copy a velocity field's row and column samples to h->vel on the handle's
+// stream and wait for the copy (the caller's arrays are only borrowed for
+// the create call); point the physics constants at them.
+hipError_t upload_field(idp_dg* h, const idp_dg_desc* desc) {
+  h->d.vel_rows = nullptr;
+  h->d.vel_cols = nullptr;
+  if (desc->eq != IDP_DG_ADVECTION_FIELD) return hipSuccess;
+  const size_t nr = (size_t)desc->ny * (desc->p + 1), ncol = (size_t)desc->nx * (desc->p + 1);
+  hipError_t e = hipMemcpyAsync(h->vel, desc->vel_rows, sizeof(double) * nr, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->vel + nr, desc->vel_cols, sizeof(double) * ncol, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  h->ph.vrow = h->vel;
+  h->ph.vcol = h->vel + nr;
+  return e;
+}
+
 int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long ws_bytes, idp_dg** out) {
   (void)ws_bytes;
   if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
@@ -444,7 +474,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
   h->ph.inv_ex = 1.0 / h->ph.ex;
   const double r = std::nearbyint(h->ph.inv_ex);
   h->ph.inv_ex_int = (std::fabs(h->ph.inv_ex - r) < 1e-12 && r > 0 && r < 64) ? (int)r : 0;
-  h->kcode = desc->eq;
+  h->kcode = desc->eq == IDP_DG_ADVECTION_FIELD ? EQ_ADVV : desc->eq;
   if (desc->eq == IDP_DG_EULER) {
     const double gn = std::nearbyint(2.0 / (h->ph.gamma - 1.0));
     const bool exact = std::fabs(h->ph.gamma - (1.0 + 2.0 / gn)) <= 4e-16 * h->ph.gamma;
@@ -463,9 +493,11 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
     h->diag = reinterpret_cast<Diag*>(ws + L.diag);
     h->dtdev = reinterpret_cast<double*>(ws + L.dtdev);
     h->partial = reinterpret_cast<double*>(ws + L.partial);
+    if (desc->eq == IDP_DG_ADVECTION_FIELD) h->vel = reinterpret_cast<double*>(ws + L.vel);
     e = hipMemsetAsync(h->diag, 0, sizeof(Diag), h->stream);
+    if (e == hipSuccess) e = upload_field(h, desc);
     if (e != hipSuccess) {
-      fail(nullptr, IDP_DG_EHIP, std::string("workspace clear: ") + hipGetErrorString(e));
+      fail(nullptr, IDP_DG_EHIP, std::string("workspace set-up: ") + hipGetErrorString(e));
       delete h;
       return IDP_DG_EHIP;
     }
@@ -478,11 +510,15 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
   if (e == hipSuccess) e = hipMalloc(&h->diag, sizeof(Diag) + 64);
   if (e == hipSuccess) e = hipMalloc(&h->dtdev, 64);
   if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * (h->ne + 64));
+  if (e == hipSuccess && desc->eq == IDP_DG_ADVECTION_FIELD)
+    e = hipMalloc(&h->vel, sizeof(double) * n1 * (desc->nx + desc->ny));
   if (e == hipSuccess) e = hipMemset(h->diag, 0, sizeof(Diag));
+  if (e == hipSuccess) e = upload_field(h, desc);
   if (e != hipSuccess) {
     const int code = e == hipErrorOutOfMemory ? IDP_DG_ENOMEM : IDP_DG_EHIP;
     fail(nullptr, code, std::string("device allocation: ") + hipGetErrorString(e));
     hipFree(h->buf1); hipFree(h->buf2); hipFree(h->diag); hipFree(h->dtdev); hipFree(h->partial);
+    hipFree(h->vel);
     delete h;
     return code;
   }
@@ -502,6 +538,7 @@ void idp_dg_destroy(idp_dg* h) {
     hipFree(h->diag);
     hipFree(h->dtdev);
     hipFree(h->partial);
+    hipFree(h->vel);
   }
   delete h;
 }

@@ -38,7 +38,9 @@ struct Cfg {
   static constexpr int NT = 2 * DIM * TJ;               // trace nodes per element
   static constexpr int NS = NP + NT;                    // LDS slots per element
   static constexpr int NC = is_euler(EQ) ? DIM + 2 : 1;
-  static constexpr int NAUX = is_euler(EQ) ? 5 : 0;   // 1/rho, p, c, p^-ex, K
+  // per-slot auxiliaries: Euler 1/rho, p, c, p^-ex, K; EQ_ADVV beta_x, beta_y
+  static constexpr int NAUX = is_euler(EQ) ? 5 : EQ == EQ_ADVV ? 2 : 0;
+  static constexpr int NAUXF = is_euler(EQ) ? 4 : NAUX;   // those fluxes and speeds read
   static constexpr int NFL = P + 2;                     // subcell faces per line
   static constexpr int NL = DIM == 2 ? N1 : 1;          // lines per direction
   static constexpr int NF = NFL * NL;                   // faces per direction
@@ -181,6 +183,8 @@ template <int EQ, int DIM>
 __device__ inline void flux_k(int k, const double* U, const double* X, const Phys& ph, double* F) {
   if constexpr (EQ == EQ_ADV) {
     F[0] = (k == 0 ? ph.vel0 : ph.vel1) * U[0];
+  } else if constexpr (EQ == EQ_ADVV) {
+    F[0] = X[k] * U[0];
   } else if constexpr (EQ == EQ_BURG) {
     F[0] = 0.5 * U[0] * U[0] * (k == 0 ? ph.vel0 : ph.vel1);
   } else {
@@ -201,6 +205,9 @@ __device__ inline double lambda_k(int k, const double* UL, const double* XL, con
                                   const double* XR, const Phys& ph) {
   if constexpr (EQ == EQ_ADV) {
     return fabs(k == 0 ? ph.vel0 : ph.vel1);
+  } else if constexpr (EQ == EQ_ADVV) {
+    // Sec. 3.3: dhat_ij = max(|chat_ij . beta_i|, |chat_ji . beta_j|)
+    return fmax(fabs(XL[k]), fabs(XR[k]));
   } else if constexpr (EQ == EQ_BURG) {
     return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(k == 0 ? ph.vel0 : ph.vel1);
   } else {
@@ -395,7 +402,18 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
       euler_aux<DIM, gn_of(EQ), FLUX>(U, ph, X, b);
       bad |= b;
 #pragma unroll
-      for (int q = 0; q < (FLUX ? C::NAUX : C::NAUX - 1); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
+      for (int q = 0; q < (FLUX ? C::NAUX : C::NAUXF); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
+    } else if constexpr (EQ == EQ_ADVV) {
+      // the velocity of the slot's node: beta_x of its row, beta_y of its
+      // column (own slot or face trace)
+      const long long g = s < NP ? (long long)(e0 + le) * NP + s
+                                 : trace_node<DIM, P>(e0 + le, s - NP, nx, ny);
+      const int e = (int)(g / NP), sn = (int)(g - (long long)e * NP);
+      const int ey = e / nx, ex = e - ey * nx;
+      X[0] = ph.vrow[ey * C::N1 + sn / C::N1];
+      X[1] = ph.vcol[ex * C::N1 + sn % C::N1];
+      lds[C::A_X + t] = X[0];
+      lds[C::A_X + EPB * NS + t] = X[1];
     }
     if constexpr (FLUX) {
       if (s < NP) {
@@ -593,7 +611,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         UR[c] = lds[C::A_U + c * EPB * NS + sr];
       }
 #pragma unroll
-      for (int q = 0; q < C::NAUX - 1; ++q) {
+      for (int q = 0; q < C::NAUXF; ++q) {
         XL[q] = lds[C::A_X + q * EPB * NS + sl];
         XR[q] = lds[C::A_X + q * EPB * NS + sr];
       }
@@ -976,7 +994,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
       UR[c] = lds[C::A_U + c * EPB * NS + sr];
     }
 #pragma unroll
-    for (int q = 0; q < (C::NAUX > 0 ? C::NAUX - 1 : 0); ++q) {
+    for (int q = 0; q < C::NAUXF; ++q) {
       XL[q] = lds[C::A_X + q * EPB * NS + sl];
       XR[q] = lds[C::A_X + q * EPB * NS + sr];
     }

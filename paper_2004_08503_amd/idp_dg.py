@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libidp_dg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "idp_dg.h")
 
-ADVECTION, BURGERS, EULER = 0, 1, 2
+ADVECTION, BURGERS, EULER, ADVECTION_FIELD = 0, 1, 2, 3
 SUBCELL, TARGET_ONLY, LOW_ONLY, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 EINVAL, ENOMEM, EHIP = -1, -2, -3
 
@@ -25,7 +25,9 @@ class Desc(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("p", ctypes.c_int), ("eq", ctypes.c_int),
                 ("velocity", ctypes.c_double * 2), ("gamma", ctypes.c_double),
-                ("limiter", ctypes.c_int), ("gmin", ctypes.c_double), ("gmax", ctypes.c_double)]
+                ("limiter", ctypes.c_int), ("gmin", ctypes.c_double), ("gmax", ctypes.c_double),
+                ("vel_rows", ctypes.POINTER(ctypes.c_double)),
+                ("vel_cols", ctypes.POINTER(ctypes.c_double))]
 
 
 class Diag(ctypes.Structure):
@@ -109,6 +111,17 @@ def make_desc(prob):
     d.limiter = int(prob.limiter)
     d.gmin = float(getattr(prob, "gmin", 0.0))
     d.gmax = float(getattr(prob, "gmax", 0.0))
+    if d.eq == ADVECTION_FIELD:
+        import numpy as np
+        rows = np.ascontiguousarray(getattr(prob, "vrows", ()), dtype=np.float64)
+        cols = np.ascontiguousarray(getattr(prob, "vcols", ()), dtype=np.float64)
+        n1 = d.p + 1
+        if rows.size != d.ny * n1 or cols.size != d.nx * n1:
+            raise ValueError("vrows / vcols need ny*(p+1) / nx*(p+1) samples")
+        dp = ctypes.POINTER(ctypes.c_double)
+        d.vel_rows = rows.ctypes.data_as(dp)
+        d.vel_cols = cols.ctypes.data_as(dp)
+        d._keep = (rows, cols)   # alive as long as the descriptor
     return d
 
 

@@ -25,6 +25,7 @@ def test_exports_every_declared_symbol():
     dict(p=0), dict(p=9), dict(dim=3), dict(nx=0), dict(eq=5), dict(gamma=1.0),
     dict(gamma=1.8), dict(limiter=-1), dict(dim=1, ny=3), dict(lx=0.0), dict(lx=float("nan")),
     dict(limiter=3, gmin=1.0, gmax=0.0), dict(limiter=3, gmin=float("nan"), gmax=1.0), dict(limiter=5),
+    dict(eq=4),
 ])
 def test_create_rejects_bad_desc(bad):
     prob = Problem(dim=2, nx=4, ny=4, p=3, eq=EULER).replace(**bad)
@@ -73,3 +74,31 @@ def test_workspace_size_and_validation():
     assert not h.value
     assert lib.idp_dg_batch_update(None, None, 0) == idp_dg.EINVAL
     assert lib.idp_dg_batch_create(None, 0, None, ctypes.byref(h)) == idp_dg.EINVAL
+
+
+def test_velocity_field_desc_validation():
+    """IDP_DG_ADVECTION_FIELD: 2-D only, both sample arrays present and
+    finite; the workspace holds the samples."""
+    from paper_2004_08503_amd import workloads as W
+    lib = idp_dg.lib
+    prob = W.solid_body(n=6, p=3).prob
+    good = idp_dg.make_desc(prob)
+    n_field = lib.idp_dg_workspace_bytes(ctypes.byref(good))
+    plain = idp_dg.make_desc(prob.replace(eq=W.ADVECTION))
+    n_plain = lib.idp_dg_workspace_bytes(ctypes.byref(plain))
+    assert n_field >= n_plain + 8 * 4 * (6 + 6)
+    h = ctypes.c_void_p()
+    bad = idp_dg.make_desc(prob)
+    bad.vel_rows = None
+    assert lib.idp_dg_create(ctypes.byref(bad), None, ctypes.byref(h)) == idp_dg.EINVAL
+    assert b"vel_rows" in lib.idp_dg_last_error(None)
+    rows = list(prob.vrows)
+    rows[5] = float("nan")
+    bad = idp_dg.make_desc(prob.replace(vrows=tuple(rows)))
+    assert lib.idp_dg_create(ctypes.byref(bad), None, ctypes.byref(h)) == idp_dg.EINVAL
+    bad = idp_dg.make_desc(prob)
+    bad.dim, bad.ny = 1, 1
+    assert lib.idp_dg_create(ctypes.byref(bad), None, ctypes.byref(h)) == idp_dg.EINVAL
+    assert not h.value
+    with pytest.raises(ValueError):
+        idp_dg.make_desc(prob.replace(vrows=prob.vrows[:-1]))
