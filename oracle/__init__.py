@@ -12,7 +12,9 @@ Problem descriptions are duck-typed: any object with the attributes
 as the integer codes below; ``gmin, gmax`` too for SUBCELL_SI) is accepted,
 e.g. the seeded workload objects.  ADVECTION_FIELD takes the nodal
 velocity from ``beta`` (shape (2, Nn)) when the object has one, else from
-the per-row / per-column samples ``vrows``, ``vcols``.
+the per-row / per-column samples ``vrows``, ``vcols``.  Open directions
+(``bc``) take their per-node boundary conditions from ``bnd`` (a
+``workloads.Boundary``).
 State arrays are float64 of shape ``(nc, Nn)`` in the layout ``u[c][e][b][a]``.
 """
 import ctypes
@@ -45,7 +47,10 @@ class _Desc(ctypes.Structure):
                 ("vel", ctypes.c_double * 2), ("gamma", ctypes.c_double),
                 ("limiter", ctypes.c_int),
                 ("gmin", ctypes.c_double), ("gmax", ctypes.c_double),
-                ("beta", ctypes.POINTER(ctypes.c_double))]
+                ("beta", ctypes.POINTER(ctypes.c_double)),
+                ("bc", ctypes.c_int * 2),
+                ("bc_type", ctypes.c_void_p * 4),
+                ("bc_state", ctypes.c_void_p * 4)]
 
 
 class _Trace(ctypes.Structure):
@@ -102,10 +107,25 @@ def _desc(prob):
     d.limiter = int(prob.limiter)
     d.gmin = float(getattr(prob, "gmin", 0.0))
     d.gmax = float(getattr(prob, "gmax", 0.0))
+    keep = []
     if d.eq == ADVECTION_FIELD:
         beta = nodal_velocity(prob)
         d.beta = _ptr(beta)
-        d._keep = beta          # the array lives as long as the descriptor
+        keep.append(beta)
+    bc = tuple(getattr(prob, "bc", (0, 0)))
+    d.bc[0], d.bc[1] = int(bc[0]), int(bc[1])
+    bnd = getattr(prob, "bnd", None)
+    if bnd is not None:
+        for side in range(4):
+            if bnd.type[side] is not None:
+                t = np.ascontiguousarray(bnd.type[side], dtype=np.int8)
+                d.bc_type[side] = t.ctypes.data
+                keep.append(t)
+            if bnd.state[side] is not None:
+                st = np.ascontiguousarray(bnd.state[side], dtype=np.float64)
+                d.bc_state[side] = st.ctypes.data
+                keep.append(st)
+    d._keep = keep          # the arrays live as long as the descriptor
     return d
 
 

@@ -66,6 +66,11 @@ int idp_ref_check(const idp_ref_desc* d) {
   if (d->eq == IDP_REF_EULER && !(d->gamma > 1.0 && d->gamma <= 5.0 / 3.0))
     return -1;
   if (d->eq == IDP_REF_ADVECTION_FIELD && field_check(d)) return -1;
+  for (int k = 0; k < 2; ++k) {
+    if (d->bc[k] != 0 && d->bc[k] != 1) return -1;
+    if (d->bc[k] && (!d->bc_type[2 * k] || !d->bc_type[2 * k + 1])) return -1;
+  }
+  if (d->dim == 1 && d->bc[1]) return -1;
   return 0;
 }
 
@@ -397,6 +402,51 @@ static void get_state(const ref_t* R, const double* u, long i, double* ui) {
   for (int c = 0; c < R->nc; ++c) ui[c] = u[(long)c * R->nn + i];
 }
 
+/* The neighbour of node i in direction k on side s when the pair may cross
+ * the boundary of an open direction.  Returns the neighbour's index, or i
+ * itself for a boundary face of an open direction (*ghost set): the
+ * exterior state then stands in for the neighbour, at the same point as
+ * node i. */
+static long nbr(const ref_t* R, long i, int k, int s, int* across, int* ghost) {
+  long j = neighbour(R, i, k, s, across);
+  *ghost = 0;
+  if (*across && R->d.bc[k]) {
+    long ex, ey;
+    int a, b;
+    node_coords(R, i, &ex, &ey, &a, &b);
+    long e = k == 0 ? ex : ey, n = k == 0 ? R->d.nx : R->d.ny;
+    if ((s < 0 && e == 0) || (s > 0 && e == n - 1)) {
+      *ghost = 1;
+      return i;
+    }
+  }
+  return j;
+}
+
+/* The state of that neighbour: u_j, or the exterior state of the boundary
+ * node i (reading: the paper leaves the boundary treatment open; the
+ * exterior state enters the Lax-Friedrichs flux, the graph viscosity and
+ * the bar states like a neighbour, so the low-order update stays a convex
+ * combination of admissible bar states when the exterior state is
+ * admissible). */
+static void nbr_state(const ref_t* R, const double* u, long i, int k, int s, int ghost, long j,
+                      double* uj) {
+  get_state(R, u, j, uj);
+  if (!ghost) return;
+  long ex, ey;
+  int a, b;
+  node_coords(R, i, &ex, &ey, &a, &b);
+  int side = 2 * k + (s > 0);
+  long q = k == 0 ? ey * R->n1 + b : ex * R->n1 + a;
+  long n = (k == 0 ? R->d.ny : R->d.nx) * R->n1;
+  int type = R->d.bc_type[side][q];
+  if (type == IDP_REF_BC_STATE && R->d.bc_state[side]) {
+    for (int c = 0; c < R->nc; ++c) uj[c] = R->d.bc_state[side][(long)c * n + q];
+  } else if (type == IDP_REF_BC_SLIP && R->d.eq == IDP_REF_EULER) {
+    uj[1 + k] = -uj[1 + k];
+  }
+}
+
 /* Graph coefficients of the low-order scheme in the form eq. dg-idp for
  * the neighbour j of i in direction k on side s: chat_ij (the k-th
  * component; the others vanish on Cartesian elements) and dhat_ij.
@@ -409,9 +459,10 @@ static void get_state(const ref_t* R, const double* u, long i, double* ui) {
  * u_i on the left and u_j on the right along the unit vector pointing
  * from node i to node j. */
 static void graph_coeffs(const ref_t* R, const double* u, long i, int k, int s,
-                         long* j_out, double* chat, double* dhat) {
-  int across, t;
-  long j = neighbour(R, i, k, s, &across);
+                         long* j_out, double* chat, double* dhat, double* uj_out) {
+  int across, ghost, t;
+  long j = nbr(R, i, k, s, &across, &ghost);
+  if (u && uj_out) nbr_state(R, u, i, k, s, ghost, j, uj_out);
   double scale = line_scale(R, k, (line_pos(R, i, k, &t), t));
   double e_ij[2] = {0.0, 0.0}, e_ji[2] = {0.0, 0.0};
   e_ij[k] = (double)s;
@@ -436,7 +487,7 @@ static void graph_coeffs(const ref_t* R, const double* u, long i, int k, int s,
   }
   double ui[MAXC], uj[MAXC];
   get_state(R, u, i, ui);
-  get_state(R, u, j, uj);
+  nbr_state(R, u, i, k, s, ghost, j, uj);
   if (across) {
     double wn = scale; /* |wn_ij|: face weight times face metric */
     *chat = -0.5 * wn * (double)s;
@@ -486,7 +537,7 @@ static int field_check(const idp_ref_desc* d) {
       for (int sd = -1; sd <= 1; sd += 2) {
         long j;
         double chat, dhat;
-        graph_coeffs(R, NULL, i, k, sd, &j, &chat, &dhat);
+        graph_coeffs(R, NULL, i, k, sd, &j, &chat, &dhat, NULL);
         double t = chat * d->beta[(long)k * R->nn + j];
         sum += t;
         mag += fabs(t);
@@ -698,9 +749,9 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
             line[a] = k == 0 ? node_index(R, ex, ey, a, t)
                              : node_index(R, ex, ey, t, a);
           double s = line_scale(R, k, t);
-          int across;
-          long jl = neighbour(R, line[0], k, -1, &across);
-          long jr = neighbour(R, line[p], k, +1, &across);
+          int across, gl, gr;
+          long jl = nbr(R, line[0], k, -1, &across, &gl);
+          long jr = nbr(R, line[p], k, +1, &across, &gr);
           double u0[MAXC], up[MAXC], ujl[MAXC], ujr[MAXC];
           double FhL[MAXC], FhR[MAXC];
           double nm[2] = {0.0, 0.0}, np_[2] = {0.0, 0.0};
@@ -708,8 +759,8 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
           np_[k] = 1.0;
           get_state(R, u, line[0], u0);
           get_state(R, u, line[p], up);
-          get_state(R, u, jl, ujl);
-          get_state(R, u, jr, ujr);
+          nbr_state(R, u, line[0], k, -1, gl, jl, ujl);
+          nbr_state(R, u, line[p], k, +1, gr, jr, ujr);
           /* numerical fluxes on the two element faces of this line, with
            * the outward unit normal of this element */
           lax_friedrichs(R, u0, line[0], ujl, jl, nm, FhL);
@@ -750,8 +801,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
               for (int sd = -1; sd <= 1; sd += 2) {
                 long j;
                 double chat, dhat, uj[MAXC];
-                graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat);
-                get_state(R, u, j, uj);
+                graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, uj);
                 rl += (dhat + chat * R->d.beta[(long)k * nn + j]) * (uj[0] - ui[0]);
               }
               rL[IDX3(k, 0, i)] = rl;
@@ -825,9 +875,8 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
       for (int sd = -1; sd <= 1; sd += 2) {
         long j;
         double chat, dhat;
-        graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat);
         double uj[MAXC], Fj[2 * MAXC];
-        get_state(R, u, j, uj);
+        graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, uj);
         flux_node(R, uj, j, Fj);
         double bar = 0.5 * (ui[lim] + uj[lim]);
         /* eq. bar-states; for a velocity field the modified bar state of
@@ -1085,7 +1134,7 @@ int idp_ref_max_dt(const idp_ref_desc* dsc, const double* u, double* dt) {
       for (int sd = -1; sd <= 1; sd += 2) {
         long j;
         double chat, dhat;
-        graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat);
+        graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, NULL);
         sum += dhat;
       }
     }

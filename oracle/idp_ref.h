@@ -12,8 +12,8 @@
  * Every routine is single-threaded, allocates with malloc, works on host
  * pointers and is compiled with -ffp-contract=off (no fused multiply-add).
  *
- * Mesh: periodic Cartesian box [0,lx) x [0,ly) split into nx x ny elements
- * (ny = 1 in 1-D).  Each element carries the (p+1)^d tensor Gauss-Lobatto
+ * Mesh: Cartesian box [0,lx) x [0,ly) split into nx x ny elements (ny = 1
+ * in 1-D), periodic in each direction unless that direction is open.  Each element carries the (p+1)^d tensor Gauss-Lobatto
  * nodes.  State layout: u[c][e][b][a], i.e. component c outermost, element
  * e = ey*nx + ex, then the y node index b, then the x node index a fastest.
  * The number of nodes is Nn = nx*ny*(p+1)^d and an array holds nc*Nn
@@ -31,6 +31,13 @@ extern "C" {
  * only: a divergence-free field in 1-D is constant). */
 enum { IDP_REF_ADVECTION = 0, IDP_REF_BURGERS = 1, IDP_REF_EULER = 2,
        IDP_REF_ADVECTION_FIELD = 3 };
+
+/* Conditions of a boundary node of an open direction: the state on the
+ * far side of the boundary face (the exterior, or "ghost", state) is a
+ * prescribed state (STATE), the node's own state (OUTFLOW), or its own state
+ * with the normal momentum reversed (SLIP: a reflecting wall for Euler; the
+ * same as OUTFLOW for the scalar laws).  Any other code acts as OUTFLOW. */
+enum { IDP_REF_BC_STATE = 1, IDP_REF_BC_OUTFLOW = 2, IDP_REF_BC_SLIP = 3 };
 
 /* Limiter modes: SUBCELL is the subcell convex limiter (Sec. 4.1.3 and
  * 4.2.2); TARGET returns the unlimited high-order update (eq. ho-update);
@@ -60,6 +67,15 @@ typedef struct {
                          sum_j chat_ij . beta_j = 0 at every node (checked,
                          1e-12 relative), which fields with beta_x = beta_x(y)
                          and beta_y = beta_y(x) meet on Cartesian meshes */
+  int bc[2];          /* per direction x, y: 0 periodic, 1 open (bc[1] = 0
+                         in 1-D) */
+  const signed char* bc_type[4]; /* open sides x = 0, x = lx, y = 0, y = ly:
+                         the condition of every boundary node, ny*(p+1)
+                         (x-sides, node row ey*(p+1) + b) or nx*(p+1)
+                         (y-sides, node column ex*(p+1) + a) entries */
+  const double* bc_state[4];     /* the prescribed states of STATE nodes,
+                         [c*n + q] for n boundary nodes (NULL: STATE acts
+                         as OUTFLOW) */
 } idp_ref_desc;
 
 /* Optional per-node outputs of one forward-Euler sub-step.  Any pointer may

@@ -33,6 +33,7 @@ import numpy as np
 
 ADVECTION, BURGERS, EULER, ADVECTION_FIELD = 0, 1, 2, 3
 SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
+BC_STATE, BC_OUTFLOW, BC_SLIP = 1, 2, 3      # per-node conditions of an open side
 EQ_NAMES = {"advection": ADVECTION, "burgers": BURGERS, "euler": EULER,
             "advection_field": ADVECTION_FIELD}
 LIMITER_NAMES = {"subcell": SUBCELL, "target": TARGET, "low": LOW, "subcell_si": SUBCELL_SI,
@@ -58,6 +59,10 @@ class Problem:
     # the node columns (beta_y at x = (ex + xi_a) hx, index ex*(p+1) + a)
     vrows: Tuple[float, ...] = ()
     vcols: Tuple[float, ...] = ()
+    # per direction (x, y): 0 periodic, 1 open; the open sides' per-node
+    # conditions in bnd (a Boundary)
+    bc: Tuple[int, int] = (0, 0)
+    bnd: object = None
 
     @property
     def nc(self) -> int:
@@ -75,6 +80,37 @@ class Problem:
         d = dict(self.__dict__)
         d.update(kw)
         return Problem(**d)
+
+
+@dataclass
+class Boundary:
+    """Per-node conditions of the open sides of a problem, sides ordered
+    x = 0, x = lx, y = 0, y = ly.  type[side] is an int8 array with one code
+    (BC_STATE, BC_OUTFLOW, BC_SLIP) per boundary node, in node-row order
+    ey*(p+1) + b on x-sides and node-column order ex*(p+1) + a on y-sides;
+    state[side] is None or a float64 array (nc, n) of prescribed states.
+    Periodic sides hold None."""
+    type: list
+    state: list
+
+
+def side_nodes(prob: Problem, side: int) -> int:
+    return (prob.ny if side < 2 else prob.nx) * (prob.p + 1)
+
+
+def uniform_boundary(prob: Problem, codes, states=None) -> Boundary:
+    """One condition per open side: codes[side] (None for periodic sides),
+    states[side] a length-nc vector for BC_STATE sides."""
+    types, sts = [None] * 4, [None] * 4
+    for side in range(4):
+        if codes[side] is None:
+            continue
+        n = side_nodes(prob, side)
+        types[side] = np.full(n, codes[side], dtype=np.int8)
+        if states is not None and states[side] is not None:
+            v = np.asarray(states[side], dtype=np.float64).reshape(-1, 1)
+            sts[side] = np.ascontiguousarray(np.repeat(v, n, axis=1))
+    return Boundary(types, sts)
 
 
 @dataclass
