@@ -5,8 +5,9 @@
  * Pazner, "Sparse invariant domain preserving discontinuous Galerkin
  * methods with subcell convex limiting" (arXiv 2004.08503).
  *
- * One stage computes, for every node i of a periodic Cartesian mesh of
- * tensor-product Gauss-Lobatto elements:
+ * One stage computes, for every node i of a Cartesian mesh of tensor-product
+ * Gauss-Lobatto elements (periodic, or with open sides, see
+ * idp_dg_set_boundary):
  *   - the high-order target residual r^H: the strong-form DG spectral
  *     element operator with the local Lax-Friedrichs flux (Sec. 2,
  *     eq. dg-strong, eq. ho-update);
@@ -88,7 +89,23 @@ enum {
                              (u^H - u^L) */
 };
 
-/* Problem description.  Periodic box [0,lx) x [0,ly) of nx x ny elements
+/* Boundaries, per direction (desc.bc): periodic, or open with per-node
+ * conditions on its two sides given by idp_dg_set_boundary. */
+enum { IDP_DG_BC_PERIODIC = 0, IDP_DG_BC_OPEN = 1 };
+
+/* Condition of a boundary node on an open side: the state on the far side
+ * of the boundary face (the exterior state, which enters the
+ * Lax-Friedrichs flux, the graph viscosity, the bar states and the local
+ * bounds like a neighbour's) is a prescribed state (STATE), the node's own
+ * state (OUTFLOW), or its own state with the normal momentum reversed
+ * (SLIP, a reflecting wall; for the scalar laws the same as OUTFLOW).  Any
+ * other code, and STATE on a side given no state array, act as OUTFLOW.
+ * The paper leaves the boundary treatment open; the low-order update stays
+ * a convex combination of admissible bar states when the exterior states
+ * are admissible. */
+enum { IDP_DG_BC_STATE = 1, IDP_DG_BC_OUTFLOW = 2, IDP_DG_BC_SLIP = 3 };
+
+/* Problem description.  Box [0,lx) x [0,ly) of nx x ny elements
  * (ny = 1 and ly ignored when dim = 1); p in [1, 8]; velocity is the
  * advection velocity or the Burgers direction vector; gamma in (1, 5/3]
  * for Euler (the range where the wave-speed bound used is proven).
@@ -111,6 +128,8 @@ typedef struct {
                          IDP_DG_SUBCELL_SI (finite, gmin <= gmax) */
   const double* vel_rows; /* IDP_DG_ADVECTION_FIELD: beta_x per node row */
   const double* vel_cols; /* IDP_DG_ADVECTION_FIELD: beta_y per node column */
+  int bc[2];              /* x, y: IDP_DG_BC_PERIODIC or IDP_DG_BC_OPEN
+                             (bc[1] periodic when dim = 1) */
 } idp_dg_desc;
 
 typedef struct idp_dg idp_dg;
@@ -144,6 +163,21 @@ long long idp_dg_workspace_bytes(const idp_dg_desc* desc);
  * asynchronous memset on hip_stream. */
 int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream,
                      void* workspace, long long bytes, idp_dg** out);
+
+/* Conditions of one side of an open direction: side 0 (x = 0), 1 (x = lx),
+ * 2 (y = 0), 3 (y = ly).  type holds one IDP_DG_BC_* code per boundary node
+ * and state (NULL allowed) the prescribed states [c][node] of STATE nodes;
+ * boundary nodes are ordered by node row ey*(p+1) + b on x-sides (ny*(p+1)
+ * of them) and by node column ex*(p+1) + a on y-sides (nx*(p+1)); one node
+ * per side in 1-D.  Both are device arrays, borrowed: every later launch
+ * on the handle reads them, so the caller may rewrite their contents
+ * between launches (time-dependent data) and keeps them alive while work
+ * that reads them is queued.  Every side of an open direction must be set
+ * before the handle steps (IDP_DG_EINVAL otherwise).  New pointers drop
+ * the handle's captured idp_dg_step_cfl graph; a batch holding the handle
+ * picks them up at its next step.  IDP_DG_EINVAL for a bad side, a
+ * periodic direction or a NULL type. */
+int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const double* state);
 
 /* Release the handle and the buffers it allocated.  NULL-safe. */
 void idp_dg_destroy(idp_dg* h);

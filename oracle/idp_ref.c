@@ -438,7 +438,7 @@ static void nbr_state(const ref_t* R, const double* u, long i, int k, int s, int
   node_coords(R, i, &ex, &ey, &a, &b);
   int side = 2 * k + (s > 0);
   long q = k == 0 ? ey * R->n1 + b : ex * R->n1 + a;
-  long n = (k == 0 ? R->d.ny : R->d.nx) * R->n1;
+  long n = R->d.dim == 1 ? 1 : (k == 0 ? R->d.ny : R->d.nx) * R->n1;
   int type = R->d.bc_type[side][q];
   if (type == IDP_REF_BC_STATE && R->d.bc_state[side]) {
     for (int c = 0; c < R->nc; ++c) uj[c] = R->d.bc_state[side][(long)c * n + q];

@@ -72,7 +72,8 @@ typedef struct {
   const signed char* bc_type[4]; /* open sides x = 0, x = lx, y = 0, y = ly:
                          the condition of every boundary node, ny*(p+1)
                          (x-sides, node row ey*(p+1) + b) or nx*(p+1)
-                         (y-sides, node column ex*(p+1) + a) entries */
+                         (y-sides, node column ex*(p+1) + a) entries; one
+                         entry per side in 1-D */
   const double* bc_state[4];     /* the prescribed states of STATE nodes,
                          [c*n + q] for n boundary nodes (NULL: STATE acts
                          as OUTFLOW) */

@@ -65,6 +65,7 @@ struct idp_dg_batch {
   int ring_next = 0;
   // what the device blob currently describes
   std::vector<double*> cur_u;
+  std::vector<unsigned> cur_bv;    // the solves' boundary versions
   double cur_scale = -1.0;
   int cur_mode = -1;               // 0: host time steps, 1: device bounds
   // reuse of the previous configuration's step as a graph
@@ -205,6 +206,8 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
   if (e == hipSuccess) e = hipEventRecord(b->ring_ev[r], b->stream);
   if (e != hipSuccess) return bhip(b, e, "batch upload");
   b->cur_u.assign(u, u + b->n);
+  b->cur_bv.resize(b->n);
+  for (int i = 0; i < b->n; ++i) b->cur_bv[i] = b->s[i]->bnd_version;
   b->cur_mode = mode;
   b->cur_scale = scale;
   b->dirty = false;
@@ -215,7 +218,7 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
 
 int prepare(idp_dg_batch* b, double* const* u, int mode, double scale) {
   bool same = !b->dirty && b->cur_mode == mode && b->cur_scale == scale;
-  for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i];
+  for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i] && b->cur_bv[i] == b->s[i]->bnd_version;
   if (same) {
     ++b->repeats;
     return 0;
@@ -332,6 +335,7 @@ int check_states(idp_dg_batch* b, double* const* u) {
     idp_dg* h = b->s[i];
     const long long ni = (long long)h->nc * h->nn;
     if (!u[i]) return bfail(b, IDP_DG_EINVAL, "u[i] is NULL");
+    if (!bnd_ready(h)) return bfail(b, IDP_DG_EINVAL, "a solve has an open side without boundary conditions");
     for (idp_dg* o : b->s) {
       const long long no = (long long)o->nc * o->nn;
       if (overlap(u[i], ni, o->buf1, no) || overlap(u[i], ni, o->buf2, no))

@@ -36,6 +36,21 @@ struct Phys {
   int inv_ex_int;      // inv_ex when it is an integer (7 for gamma = 1.4), else 0
 };
 
+// Open boundaries.  Per side (x = 0, x = lx, y = 0, y = ly) the condition
+// of every boundary node (node-row order on x-sides, node-column order on
+// y-sides, one node per side in 1-D) and the prescribed states [c][node]
+// (device arrays, caller-owned).  A face trace on an open side holds the
+// exterior state: the prescribed state, the node's own state (outflow), or
+// the own state with the normal momentum reversed (slip; outflow for the
+// scalar laws).  Other codes, and STATE without a state array, act as
+// outflow.
+enum { BC_STATE = 1, BC_OUTFLOW = 2, BC_SLIP = 3 };
+struct Bnd {
+  const signed char* type[4];
+  const double* state[4];
+  int open;   // bit k set: direction k is open (not periodic)
+};
+
 // Diagnostics words in device memory.  Counters are spread over slots
 // (indexed by workgroup) so that concurrent workgroups rarely meet on one
 // address; the host sums them.
@@ -72,6 +87,7 @@ struct StageArgs {
   Diag* diag;
   double* trace;   // optional per-node [umin, umax, kmin, alpha_z, alpha] x Nn
   double gmin, gmax;   // global bounds (LIM_SUBCELL_SI)
+  Bnd bnd;
 };
 
 struct MaxDtArgs {
@@ -83,6 +99,7 @@ struct MaxDtArgs {
   double hx, hy;
   Phys ph;
   Tables T;
+  Bnd bnd;
 };
 
 // Batched execution: per degree, a work list of (solve, tile) items over

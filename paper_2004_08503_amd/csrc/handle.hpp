@@ -30,6 +30,8 @@ struct idp_dg {
   double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
   double* partial = nullptr;   // per-workgroup minima of the time-step kernel
   double* vel = nullptr;       // IDP_DG_ADVECTION_FIELD: row then column velocities
+  idp::Bnd bnd{};              // open sides: per-node conditions (idp_dg_set_boundary)
+  unsigned bnd_version = 0;    // bumped by every idp_dg_set_boundary
   // cached graph of one device-timestepped step
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -50,6 +52,8 @@ idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double*
                                double dt, const double* dt_dev, double dt_scale, int stage);
 idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
+// Every side of an open direction has its conditions.
+bool bnd_ready(const idp_dg* h);
 int batch_kernels(int fam, int p, idp::BatchKernels* k);
 // Retire (graph, exec, event) and destroy retired graphs whose launches
 // have completed; with wait, block until all have completed.

@@ -145,6 +145,9 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
   const long long n1 = d->p + 1;
   const long long nn = (long long)d->nx * d->ny * (d->dim == 2 ? n1 * n1 : n1);
   if ((long long)d->nx * d->ny > 0x7fffffffLL || nn > (1LL << 40)) { *why = "mesh too large"; return false; }
+  for (int k = 0; k < 2; ++k)
+    if (d->bc[k] != IDP_DG_BC_PERIODIC && d->bc[k] != IDP_DG_BC_OPEN) { *why = "bc must be periodic or open"; return false; }
+  if (d->dim == 1 && d->bc[1] != IDP_DG_BC_PERIODIC) { *why = "bc[1] must be periodic when dim = 1"; return false; }
   if (d->eq == IDP_DG_ADVECTION_FIELD) {
     if (d->dim != 2) { *why = "a velocity field needs dim = 2"; return false; }
     if (!d->vel_rows || !d->vel_cols) { *why = "vel_rows and vel_cols must be non-NULL"; return false; }
@@ -153,6 +156,12 @@ bool desc_ok(const idp_dg_desc* d, std::string* why) {
     for (long long i = 0; i < d->nx * n1; ++i)
       if (!std::isfinite(d->vel_cols[i])) { *why = "vel_cols must be finite"; return false; }
   }
+  return true;
+}
+
+bool bnd_ready(const idp_dg* h) {
+  for (int k = 0; k < 2; ++k)
+    if (((h->bnd.open >> k) & 1) && (!h->bnd.type[2 * k] || !h->bnd.type[2 * k + 1])) return false;
   return true;
 }
 
@@ -244,6 +253,7 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.diag = h->diag;
   a.gmin = h->d.gmin;
   a.gmax = h->d.gmax;
+  a.bnd = h->bnd;
   return a;
 }
 
@@ -262,6 +272,7 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   a.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
   a.ph = h->ph;
   a.T = h->T;
+  a.bnd = h->bnd;
   return a;
 }
 
@@ -475,6 +486,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
   const double r = std::nearbyint(h->ph.inv_ex);
   h->ph.inv_ex_int = (std::fabs(h->ph.inv_ex - r) < 1e-12 && r > 0 && r < 64) ? (int)r : 0;
   h->kcode = desc->eq == IDP_DG_ADVECTION_FIELD ? EQ_ADVV : desc->eq;
+  h->bnd.open = (desc->bc[0] == IDP_DG_BC_OPEN ? 1 : 0) | (desc->bc[1] == IDP_DG_BC_OPEN ? 2 : 0);
   if (desc->eq == IDP_DG_EULER) {
     const double gn = std::nearbyint(2.0 / (h->ph.gamma - 1.0));
     const bool exact = std::fabs(h->ph.gamma - (1.0 + 2.0 / gn)) <= 4e-16 * h->ph.gamma;
@@ -549,6 +561,7 @@ int idp_dg_num_comp(const idp_dg* h) { return h ? h->nc : -1; }
 int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s, double* u_out, double dt,
                  int stage) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
   if (!u_s || !u_out || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(h, IDP_DG_EINVAL, "dt must be finite and >= 0");
@@ -564,6 +577,7 @@ int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
 int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
                        double dt, int stage, double* trace) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!trace) return fail(h, IDP_DG_EINVAL, "NULL trace pointer");
   if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
   if (!u_s || !u_out || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
@@ -593,6 +607,7 @@ int idp_dg_step(idp_dg* h, double* u, double dt) {
 
 int idp_dg_step_cfl(idp_dg* h, double* u, double cfl) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, IDP_DG_EINVAL, "cfl must be finite and > 0");
   const long long n = (long long)h->nc * h->nn;
@@ -640,6 +655,7 @@ int idp_dg_last_dt(idp_dg* h, double* dt) {
 
 int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u || !dt) return fail(h, IDP_DG_EINVAL, "NULL pointer");
   double* slot = h->dtdev + 1;   // keep the step's dt slot intact
   hipError_t e = enqueue_max_dt(h, u, slot, h->stream);
@@ -653,6 +669,7 @@ int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
 
 int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u || !dt_dev) return fail(h, IDP_DG_EINVAL, "NULL pointer");
   if (reinterpret_cast<uintptr_t>(dt_dev) % 8) return fail(h, IDP_DG_EINVAL, "dt_dev not 8-byte aligned");
   hipError_t e = enqueue_max_dt(h, u, dt_dev, h->stream);
@@ -663,6 +680,7 @@ int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev) {
 int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
                     const double* dt_dev, double cfl, int stage) {
   if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
   if (!u_s || !u_out || !dt_dev || (stage > 0 && !u_n)) return fail(h, IDP_DG_EINVAL, "NULL pointer");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, IDP_DG_EINVAL, "cfl must be finite and > 0");
@@ -672,6 +690,18 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s, double* u_o
     return fail(h, IDP_DG_EINVAL, "u_out partially overlaps u_n");
   hipError_t e = launch_stage(h, make_stage_args(h, u_n, u_s, u_out, 0.0, dt_dev, cfl, stage), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+  return 0;
+}
+
+int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const double* state) {
+  if (!h) return IDP_DG_EINVAL;
+  if (side < 0 || side >= 2 * h->d.dim) return fail(h, IDP_DG_EINVAL, "side must be in [0, 2 dim)");
+  if (!((h->bnd.open >> (side >> 1)) & 1)) return fail(h, IDP_DG_EINVAL, "the side's direction is periodic");
+  if (!type) return fail(h, IDP_DG_EINVAL, "type is NULL");
+  h->bnd.type[side] = type;
+  h->bnd.state[side] = state;
+  ++h->bnd_version;
+  drop_graph(h);   // a captured step holds the previous pointers
   return 0;
 }
 

@@ -108,6 +108,31 @@ __device__ inline long long trace_node(int e, int t, int nx, int ny) {
   }
 }
 
+// Whether trace t of element e lies on an open side of the box; if so the
+// side, the boundary node's index along that side and the global index of
+// the element's own node at that point.
+template <int DIM, int P>
+__device__ inline bool boundary_trace(int e, int t, int nx, int ny, int open, int* side, int* q,
+                                      long long* own) {
+  constexpr int N1 = P + 1;
+  const int face = DIM == 2 ? t / N1 : t, j = DIM == 2 ? t - face * N1 : 0;
+  const int k = face >> 1;
+  if (!((open >> k) & 1)) return false;
+  const int ex = e % nx, ey = e / nx;
+  const bool edge = k == 0 ? ((face & 1) ? ex == nx - 1 : ex == 0)
+                           : ((face & 1) ? ey == ny - 1 : ey == 0);
+  if (!edge) return false;
+  *side = face;
+  *q = DIM == 1 ? 0 : (k == 0 ? ey * N1 + j : ex * N1 + j);
+  if constexpr (DIM == 1) {
+    *own = (long long)e * N1 + ((face & 1) ? P : 0);
+  } else {
+    const int loc = face == 0 ? j * N1 : face == 1 ? j * N1 + P : face == 2 ? j : P * N1 + j;
+    *own = (long long)e * (N1 * N1) + loc;
+  }
+  return true;
+}
+
 __device__ inline double ipow(double x, int n) {
   double r = 1.0;
   while (n) {
@@ -366,7 +391,7 @@ __device__ inline int own_slot(int k, int l, int pos) {
 // ----------------------------------------------------------------------
 template <int EQ, int DIM, int P, int EPB, bool FLUX>
 __device__ inline void load_tile(double* lds, const double* __restrict__ u, long long nn, int e0,
-                                 int ne, int nx, int ny, const Phys& ph, double* Uown,
+                                 int ne, int nx, int ny, const Phys& ph, const Bnd& bnd, double* Uown,
                                  unsigned int* bad_flag) {
   using C = Cfg<EQ, DIM, P, EPB>;
   constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NT = C::NT;
@@ -383,12 +408,31 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
       lds[C::A_U + c * EPB * NS + le * NS + s] = Uown[c];
     }
   }
-  // face traces of the neighbouring elements
+  // face traces of the neighbouring elements, or exterior states on the
+  // open sides of the box
   for (int t = tid; t < nel * NT; t += C::BS) {
     const int le = t / NT, j = t - le * NT;
-    const long long g = trace_node<DIM, P>(e0 + le, j, nx, ny);
+    int side, q;
+    long long own;
+    if (bnd.open && boundary_trace<DIM, P>(e0 + le, j, nx, ny, bnd.open, &side, &q, &own)) {
+      double v[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = u[c * nn + g];
+      for (int c = 0; c < NC; ++c) v[c] = u[c * nn + own];
+      const int ty = bnd.type[side][q];
+      if (ty == BC_STATE && bnd.state[side]) {
+        const int n = DIM == 1 ? 1 : (side < 2 ? ny : nx) * (P + 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = bnd.state[side][c * n + q];
+      } else if (ty == BC_SLIP && is_euler(EQ)) {
+        v[1 + (side >> 1)] = -v[1 + (side >> 1)];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = v[c];
+    } else {
+      const long long g = trace_node<DIM, P>(e0 + le, j, nx, ny);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = u[c * nn + g];
+    }
   }
   __syncthreads();
   // pointwise physics on every slot
@@ -405,9 +449,14 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
       for (int q = 0; q < (FLUX ? C::NAUX : C::NAUXF); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
     } else if constexpr (EQ == EQ_ADVV) {
       // the velocity of the slot's node: beta_x of its row, beta_y of its
-      // column (own slot or face trace)
-      const long long g = s < NP ? (long long)(e0 + le) * NP + s
-                                 : trace_node<DIM, P>(e0 + le, s - NP, nx, ny);
+      // column (own slot or face trace; an exterior state sits at the
+      // element's own face node)
+      int side, q;
+      long long g;
+      if (s < NP)
+        g = (long long)(e0 + le) * NP + s;
+      else if (!(bnd.open && boundary_trace<DIM, P>(e0 + le, s - NP, nx, ny, bnd.open, &side, &q, &g)))
+        g = trace_node<DIM, P>(e0 + le, s - NP, nx, ny);
       const int e = (int)(g / NP), sn = (int)(g - (long long)e * NP);
       const int ey = e / nx, ex = e - ey * nx;
       X[0] = ph.vrow[ey * C::N1 + sn / C::N1];
@@ -550,7 +599,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, lds + C::S_M, lds + C::S_NK, T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
-  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, U,
+  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, A.bnd, U,
                                    A.diag ? &A.diag->bad_input : nullptr);
   const bool own = tid < nel * NP;
   if (A.use_un && own) {
@@ -975,7 +1024,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   const int nel = min(EPB, A.ne - e0);
   for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = T.w[t];
   double U[NC];
-  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, U, nullptr);
+  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, A.bnd, U, nullptr);
   __syncthreads();
   for (int w = tid; w < nel * DIM * NF; w += C::BS) {
     const int le = w / (DIM * NF);
@@ -1070,6 +1119,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel
   A.trace = pa->trace;
   A.gmin = pa->gmin;
   A.gmax = pa->gmax;
+  A.bnd = pa->bnd;
   stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it]);
 }
 
@@ -1091,6 +1141,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel
   A.hx = pa->hx;
   A.hy = pa->hy;
   A.ph = pa->ph;
+  A.bnd = pa->bnd;
   maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it], B.partial + it);
 }
 

@@ -27,7 +27,8 @@ class Desc(ctypes.Structure):
                 ("velocity", ctypes.c_double * 2), ("gamma", ctypes.c_double),
                 ("limiter", ctypes.c_int), ("gmin", ctypes.c_double), ("gmax", ctypes.c_double),
                 ("vel_rows", ctypes.POINTER(ctypes.c_double)),
-                ("vel_cols", ctypes.POINTER(ctypes.c_double))]
+                ("vel_cols", ctypes.POINTER(ctypes.c_double)),
+                ("bc", ctypes.c_int * 2)]
 
 
 class Diag(ctypes.Structure):
@@ -58,6 +59,7 @@ def _declare(lib):
         "idp_dg_max_dt_async": (ctypes.c_int, [H, _VP, _VP]),
         "idp_dg_stage_dt": (ctypes.c_int, [H, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
+        "idp_dg_set_boundary": (ctypes.c_int, [H, ctypes.c_int, _VP, _VP]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
         "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
         "idp_dg_batch_destroy": (None, [H]),
@@ -122,6 +124,8 @@ def make_desc(prob):
         d.vel_rows = rows.ctypes.data_as(dp)
         d.vel_cols = cols.ctypes.data_as(dp)
         d._keep = (rows, cols)   # alive as long as the descriptor
+    bc = tuple(getattr(prob, "bc", (0, 0)))
+    d.bc[0], d.bc[1] = int(bc[0]), int(bc[1])
     return d
 
 
@@ -170,6 +174,15 @@ class Solver:
             raise IdpError(rc, lib.idp_dg_last_error(None).decode())
         self.nc = lib.idp_dg_num_comp(self._h)
         self.nn = lib.idp_dg_num_nodes(self._h)
+        self._bnd = {}
+        bnd = getattr(prob, "bnd", None)
+        if bnd is not None:   # the problem's own boundary data, copied to the device
+            for side in range(4):
+                if bnd.type[side] is not None:
+                    t = torch.as_tensor(bnd.type[side], dtype=torch.int8).to("cuda")
+                    st = None if bnd.state[side] is None else \
+                        torch.as_tensor(bnd.state[side], dtype=torch.float64).to("cuda").contiguous()
+                    self.set_boundary(side, t, st)
 
     @property
     def handle(self):
@@ -200,6 +213,24 @@ class Solver:
             raise ValueError("%s must be a contiguous float64 CUDA tensor of %d values"
                              % (name, self.nc * self.nn))
         return ctypes.c_void_p(t.data_ptr())
+
+    def set_boundary(self, side, type_t, state_t=None):
+        """idp_dg_set_boundary: int8 CUDA tensor of per-node codes and an
+        optional float64 CUDA tensor (nc, n) of prescribed states.  The
+        tensors are kept referenced until replaced; their contents may be
+        rewritten between launches."""
+        torch = _torch()
+        if not (isinstance(type_t, torch.Tensor) and type_t.is_cuda and type_t.dtype == torch.int8
+                and type_t.is_contiguous()):
+            raise ValueError("type must be a contiguous int8 CUDA tensor")
+        sp = None
+        if state_t is not None:
+            if not (isinstance(state_t, torch.Tensor) and state_t.is_cuda
+                    and state_t.dtype == torch.float64 and state_t.is_contiguous()):
+                raise ValueError("state must be a contiguous float64 CUDA tensor")
+            sp = ctypes.c_void_p(state_t.data_ptr())
+        self._check(lib.idp_dg_set_boundary(self._h, int(side), ctypes.c_void_p(type_t.data_ptr()), sp))
+        self._bnd[side] = (type_t, state_t)
 
     def empty(self):
         torch = _torch()

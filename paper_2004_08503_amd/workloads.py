@@ -87,7 +87,8 @@ class Boundary:
     """Per-node conditions of the open sides of a problem, sides ordered
     x = 0, x = lx, y = 0, y = ly.  type[side] is an int8 array with one code
     (BC_STATE, BC_OUTFLOW, BC_SLIP) per boundary node, in node-row order
-    ey*(p+1) + b on x-sides and node-column order ex*(p+1) + a on y-sides;
+    ey*(p+1) + b on x-sides and node-column order ex*(p+1) + a on y-sides
+    (one node per side in 1-D);
     state[side] is None or a float64 array (nc, n) of prescribed states.
     Periodic sides hold None."""
     type: list
@@ -95,6 +96,9 @@ class Boundary:
 
 
 def side_nodes(prob: Problem, side: int) -> int:
+    """Boundary nodes of one side: one in 1-D."""
+    if prob.dim == 1:
+        return 1
     return (prob.ny if side < 2 else prob.nx) * (prob.p + 1)
 
 

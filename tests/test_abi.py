@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     dict(p=0), dict(p=9), dict(dim=3), dict(nx=0), dict(eq=5), dict(gamma=1.0),
     dict(gamma=1.8), dict(limiter=-1), dict(dim=1, ny=3), dict(lx=0.0), dict(lx=float("nan")),
     dict(limiter=3, gmin=1.0, gmax=0.0), dict(limiter=3, gmin=float("nan"), gmax=1.0), dict(limiter=5),
-    dict(eq=4),
+    dict(eq=4), dict(bc=(2, 0)), dict(bc=(0, -1)), dict(dim=1, ny=1, bc=(0, 1)),
 ])
 def test_create_rejects_bad_desc(bad):
     prob = Problem(dim=2, nx=4, ny=4, p=3, eq=EULER).replace(**bad)
