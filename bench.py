@@ -126,13 +126,17 @@ def batched_leg(steps, count=64):
     }
 
 
-def mode_leg(wl, prob, steps):
-    """The same device-timestepped step in another limiter mode: stage
-    latency from HIP events around each stage, and the limited fractions."""
+def mode_leg(wl, prob, steps, u0=None):
+    """Device-timestepped steps of prob (the benchmark workload in another
+    limiter mode, or another workload with its own initial state u0):
+    stage latency from HIP events around each stage, the limited fractions,
+    and the bandwidth the stage's algorithmic bytes reach (read the stage
+    input, and u^n on stages 2-3, write the output: nc * 8 * 8/3 bytes per
+    node and stage)."""
     import torch
     from paper_2004_08503_amd import idp_dg
     sv = idp_dg.Solver(prob)
-    u = torch.from_numpy(wl.u0.copy()).to("cuda")
+    u = torch.from_numpy((wl.u0 if u0 is None else u0).copy()).to("cuda")
     b1, b2 = sv.empty(), sv.empty()
     dtd = torch.empty(1, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -156,8 +160,52 @@ def mode_leg(wl, prob, steps):
     sv.close()
     return {"stage_ms_p50": float(np.percentile(ms, 50)), "stage_ms_p99": float(np.percentile(ms, 99)),
             "stage_dof_updates_per_s": float(nn / (ms.mean() * 1e-3)),
+            "algorithmic_gb_per_s": float(prob.nc * 8.0 * 8.0 / 3.0 * nn / (ms.mean() * 1e-3) / 1e9),
             "limited_node_fraction": d["limited_nodes"] / (3.0 * nn * steps),
             "entropy_node_fraction": d["entropy_nodes"] / (3.0 * nn * steps), "steps": steps}
+
+
+def double_mach_state(nx=2400, ny=600, p=3):
+    """The double Mach reflection set-up on [0, 4] x [0, 1] (Mach 10 shock at
+    60 degrees, rho = 1.4 and p = 1 ahead): the problem with its open sides
+    (post-shock inflow at x = 0 and on the bottom for x < 1/6, slip wall on
+    the rest of the bottom, outflow at x = 4, the initial shock position on
+    the top, held fixed for timing) and its initial state."""
+    from paper_2004_08503_amd import workloads as W
+    g = 1.4
+    post = np.array([8.0, 8.0 * 8.25 * np.cos(np.pi / 6), -8.0 * 8.25 * np.sin(np.pi / 6), 0.0])
+    post[3] = 116.5 / (g - 1) + 0.5 * (post[1] ** 2 + post[2] ** 2) / post[0]
+    pre = np.array([1.4, 0.0, 0.0, 1.0 / (g - 1)])
+    prob = W.Problem(dim=2, nx=nx, ny=ny, p=p, eq=W.EULER, lx=4.0, ly=1.0, bc=(1, 1))
+    xc, yc = W._element_centres(prob)
+    behind = xc < 1.0 / 6.0 + yc / np.sqrt(3.0)
+    u0 = np.where(behind[None, :], post[:, None], pre[:, None])
+    xs = ((np.arange(nx)[:, None] + W.gl_points(p)[None, :]) * (4.0 / nx)).reshape(-1)
+    n = [W.side_nodes(prob, s) for s in range(4)]
+    types = [np.full(n[0], W.BC_STATE, np.int8), np.full(n[1], W.BC_OUTFLOW, np.int8),
+             np.where(xs < 1.0 / 6.0, W.BC_STATE, W.BC_SLIP).astype(np.int8),
+             np.full(n[3], W.BC_STATE, np.int8)]
+    top = np.where((xs < 1.0 / 6.0 + 1.0 / np.sqrt(3.0))[None, :], post[:, None], pre[:, None])
+    states = [np.repeat(post[:, None], n[0], axis=1), None, np.repeat(post[:, None], n[2], axis=1), top]
+    return prob.replace(bnd=W.Boundary(types, states)), u0
+
+
+def workload_legs(wl):
+    """The widened paths measured like the benchmark: the paper's
+    solid-body rotation (velocity field, 64^2 and 512^2, p = 3), its double
+    Mach reflection set-up at the paper's own resolution (open boundaries,
+    2400 x 600, p = 3, 23 M nodes) and a large 1-D Euler problem (2^20
+    elements, p = 3, the Sod path)."""
+    from paper_2004_08503_amd import workloads as W
+    out = {}
+    for n in (64, 512):
+        sb = W.solid_body(n=n, p=3)
+        out["solid_body_%dx%d_p3" % (n, n)] = mode_leg(sb, sb.prob, 30)
+    prob, u0 = double_mach_state()
+    out["double_mach_2400x600_p3"] = mode_leg(wl, prob, 10, u0=u0)
+    e1 = W.euler_1d(n=1 << 20, p=3)
+    out["euler_1d_1048576_p3"] = mode_leg(e1, e1.prob, 30)
+    return out
 
 
 def serving_leg(count, load, budget_gb=64.0):
@@ -190,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-solve leg")
     ap.add_argument("--no-modes", action="store_true", help="skip the other limiter modes")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the solid-body, double Mach and 1-D Euler legs")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests in the served stream (0 skips the serving leg)")
@@ -310,6 +360,8 @@ def main():
         "target_only": mode_leg(wl, prob.replace(limiter=W.TARGET), 50),
         "low_only": mode_leg(wl, prob.replace(limiter=W.LOW), 50),
     }
+    if not args.no_workloads:
+        out["workloads"] = workload_legs(wl)
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_steps)
     if args.serve_requests > 0:
