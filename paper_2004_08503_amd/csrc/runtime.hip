@@ -359,12 +359,30 @@ hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
 }  // namespace
 
 namespace idp {
+// min over partial[b..e) by one thread at stride BS: eight independent loads
+// in flight per wait (a single chain waits on every load; large meshes have
+// hundreds of thousands of partial minima)
+template <int BS>
+__device__ inline double strided_min(const double* __restrict__ partial, int b, int e) {
+  double v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = INFINITY;
+  int i = b + (int)threadIdx.x;
+  for (; i + 7 * BS < e; i += 8 * BS) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = fmin(v[j], partial[i + j * BS]);
+  }
+  for (; i < e; i += BS) v[0] = fmin(v[0], partial[i]);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[0] = fmin(v[0], v[j]);
+  return v[0];
+}
+
 __global__ __launch_bounds__(256) void segmented_min_kernel(const double* partial, const int* range,
                                                              double* out) {
   __shared__ double red[4];
   const int s = blockIdx.x;
-  double v = INFINITY;
-  for (int i = range[2 * s] + threadIdx.x; i < range[2 * s + 1]; i += 256) v = fmin(v, partial[i]);
+  double v = strided_min<256>(partial, range[2 * s], range[2 * s + 1]);
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -373,8 +391,7 @@ __global__ __launch_bounds__(256) void segmented_min_kernel(const double* partia
 
 __global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial, int n, double* out) {
   __shared__ double red[16];
-  double v = INFINITY;
-  for (int i = threadIdx.x; i < n; i += 1024) v = fmin(v, partial[i]);
+  double v = strided_min<1024>(partial, 0, n);
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();

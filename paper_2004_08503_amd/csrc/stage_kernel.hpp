@@ -582,7 +582,8 @@ __device__ inline double smoothness_tile(const double* u0, const double* M, cons
 // the plain kernel (the tiles of one solve) and the batched work-list
 // kernel (the tiles of every solve of one degree).
 template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, const Tables& T, int tile) {
+__device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, const Tables& T, const Bnd& bnd,
+                                           int tile) {
   using C = Cfg<EQ, DIM, P, EPB>;
   constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
   constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
@@ -599,7 +600,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, lds + C::S_M, lds + C::S_NK, T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
-  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, A.bnd, U,
+  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, bnd, U,
                                    A.diag ? &A.diag->bad_input : nullptr);
   const bool own = tid < nel * NP;
   if (A.use_un && own) {
@@ -995,7 +996,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(StageArgs A) {
   __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
-  stage_tile<EQ, DIM, P, EPB>(lds, A, A.T, xcd_tile(blockIdx.x, gridDim.x));
+  stage_tile<EQ, DIM, P, EPB>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------
@@ -1012,7 +1013,7 @@ struct DtCfg {
 
 // the minimum of one tile into *out
 template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, int tile,
+__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, const Bnd& bnd, int tile,
                                            double* out) {
   using C = Cfg<EQ, DIM, P, EPB>;
   using D = DtCfg<EQ, DIM, P, EPB>;
@@ -1024,7 +1025,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   const int nel = min(EPB, A.ne - e0);
   for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = T.w[t];
   double U[NC];
-  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, A.bnd, U, nullptr);
+  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, bnd, U, nullptr);
   __syncthreads();
   for (int w = tid; w < nel * DIM * NF; w += C::BS) {
     const int le = w / (DIM * NF);
@@ -1079,7 +1080,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
 template <int EQ, int DIM, int P, int EPB>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDtArgs A) {
   __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
-  maxdt_tile<EQ, DIM, P, EPB>(lds, A, A.T, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
+  maxdt_tile<EQ, DIM, P, EPB>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
 }
 
 // ----------------------------------------------------------------------
@@ -1119,8 +1120,9 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel
   A.trace = pa->trace;
   A.gmin = pa->gmin;
   A.gmax = pa->gmax;
-  A.bnd = pa->bnd;
-  stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it]);
+  // the boundary arrays are indexed at run time: read them where they are
+  // (a copy in this local struct would move it to scratch memory)
+  stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, pa->bnd, B.item_tile[it]);
 }
 
 template <int EQ, int DIM, int P, int EPB>
@@ -1141,8 +1143,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel
   A.hx = pa->hx;
   A.hy = pa->hy;
   A.ph = pa->ph;
-  A.bnd = pa->bnd;
-  maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, B.item_tile[it], B.partial + it);
+  maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
 }
 
 template <int EQ, int DIM, int P>
