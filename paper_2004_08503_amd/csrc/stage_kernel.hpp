@@ -386,6 +386,34 @@ __device__ inline int own_slot(int k, int l, int pos) {
   return k == 0 ? l * (P + 1) + pos : pos * (P + 1) + l;
 }
 
+// Work item w of a tile's face pass -> element le, direction k, line l and
+// position f along it.  Every element face (f = 0 or p + 1) of the tile
+// comes first, then every interior face, so that most waves take one path:
+// the trace-side flux on element faces, the high-order contraction on
+// interior faces.
+template <int DIM, int P>
+__device__ inline void face_item(int w, int nel, int* le, int* k, int* l, int* f) {
+  constexpr int NL = DIM == 2 ? P + 1 : 1;
+  constexpr int PE = DIM * NL * 2;   // element-face items per element
+  constexpr int PI = DIM * NL * P;   // interior items per element
+  if (w < nel * PE) {
+    *le = w / PE;
+    int r = w - *le * PE;
+    *k = DIM == 2 ? r / (2 * NL) : 0;
+    r -= *k * (2 * NL);
+    *l = r >> 1;
+    *f = (r & 1) ? P + 1 : 0;
+  } else {
+    w -= nel * PE;
+    *le = w / PI;
+    int r = w - *le * PI;
+    *k = DIM == 2 ? r / (P * NL) : 0;
+    r -= *k * (P * NL);
+    *l = r / P;
+    *f = 1 + (r - *l * P);
+  }
+}
+
 // ----------------------------------------------------------------------
 // phases 1-2 shared by the stage and the time-step kernels
 // ----------------------------------------------------------------------
@@ -645,12 +673,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 #pragma unroll
     for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
     if (w < nel * DIM * NF) {
-      const int le = w / (DIM * NF);
-      const int r = w - le * (DIM * NF);
-      const int k = DIM == 2 ? r / NF : 0;
-      const int fi = r - k * NF;
-      const int l = fi / NFL;
-      const int f = fi - l * NFL;
+      int le, k, l, f;
+      face_item<DIM, P>(w, nel, &le, &k, &l, &f);
       const int base = le * NS;
       const int sl = base + (f == 0 ? NP + (2 * k) * C::TJ + l : own_slot<DIM, P>(k, l, f - 1));
       const int sr = base + (f == P + 1 ? NP + (2 * k + 1) * C::TJ + l : own_slot<DIM, P>(k, l, f));
@@ -702,11 +726,9 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   for (int it = 0; it < C::NITEM; ++it) {
     const int w = tid + it * C::BS;
     if (w < nel * DIM * NF) {
-      const int le = w / (DIM * NF);
-      const int r = w - le * (DIM * NF);
-      const int k = DIM == 2 ? r / NF : 0;
-      const int fi = r - k * NF;
-      const int o = le * NF + fi;
+      int le, k, l, f;
+      face_item<DIM, P>(w, nel, &le, &k, &l, &f);
+      const int o = le * NF + l * NFL + f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         lds[C::B_FL + (k * NC + c) * EPB * NF + o] = rFL[it][c];
