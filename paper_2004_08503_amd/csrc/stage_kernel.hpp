@@ -463,9 +463,19 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
     }
   }
   __syncthreads();
-  // pointwise physics on every slot
-  for (int t = tid; t < nel * NS; t += C::BS) {
-    const int le = t / NS, s = t - le * NS;
+  // pointwise physics on every slot: the tile's own slots first, then its
+  // face traces, so that most waves agree on forming their slot's fluxes
+  for (int i = tid; i < nel * NS; i += C::BS) {
+    int le, s;
+    if (i < nel * NP) {
+      le = i / NP;
+      s = i - le * NP;
+    } else {
+      const int j = i - nel * NP;
+      le = j / NT;
+      s = NP + (j - le * NT);
+    }
+    const int t = le * NS + s;
     double U[NC], X[C::NAUX > 0 ? C::NAUX : 1];
 #pragma unroll
     for (int c = 0; c < NC; ++c) U[c] = lds[C::A_U + c * EPB * NS + t];
