@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 DOF-updates/s per limited RK stage (p=4 Euler); batched vs plain; p99"
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_euler2d_p4_256x256_pmc.md")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_euler2d_p4_256x256_sq.md")
+SIMDS, CLOCK_GHZ = 1024, 2.4     # 256 CUs x 4 SIMDs, peak engine clock
 KERNEL_SOURCES = ["paper_2004_08503_amd/csrc/stage_kernel.hpp",
                   "paper_2004_08503_amd/csrc/common.hpp",
                   "paper_2004_08503_amd/csrc/kernels_euler75_2.hip"]
@@ -51,6 +53,19 @@ def measured_traffic():
     if not m or not t or m.group(1) != kernel_hash():
         return None
     return float(t.group(1))
+
+
+def measured_valu():
+    """VALU wave-instructions per stage launch from the committed SQ counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(SQ_SUMMARY):
+        return None
+    text = open(SQ_SUMMARY).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    v = re.search(r"valu_wave_instructions_per_stage_launch:\s*([0-9.eE+]+)", text)
+    if not m or not v or m.group(1) != kernel_hash():
+        return None
+    return float(v.group(1))
 
 
 def cpu_baseline(wl, dt):
@@ -314,6 +329,7 @@ def main():
     bytes_stage = np.array([64.0, 96.0, 96.0]) * nn
     achieved = bytes_stage.sum() / (ms[:, 1:].mean(axis=0).sum() * 1e-3) / 1e9   # GB/s
     traffic = measured_traffic()
+    valu = measured_valu()
     value = 3 * nn * args.steps / elapsed
 
     assert np.isfinite(u.cpu().numpy()).all()
@@ -346,7 +362,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "stage_kernel<EULER75,2,4,5>",
-                     "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn)},
+                     "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn),
+                     # the kernel is bound by VALU issue, not HBM: at least 4 cycles
+                     # per counted wave64 instruction over the SIMDs' cycles in
+                     # this run's mean stage time
+                     "valu_issue_busy": (None if valu is None else
+                                         valu * 4.0 / (SIMDS * stage_ms.mean() * 1e6 * CLOCK_GHZ))},
     }
     sv.close()
     del u, b1, b2
