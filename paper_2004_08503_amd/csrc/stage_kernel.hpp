@@ -133,6 +133,15 @@ __device__ inline bool boundary_trace(int e, int t, int nx, int ny, int open, in
   return true;
 }
 
+// The advection velocity / Burgers direction component k, selected between
+// two values already loaded (a select between two fields of the argument
+// struct could otherwise become a load from a run-time address, which moves
+// a local copy of the struct to scratch memory).
+__device__ inline double vel_k(int k, const Phys& ph) {
+  const unsigned long long v0 = __double_as_longlong(ph.vel0), v1 = __double_as_longlong(ph.vel1);
+  return __longlong_as_double(k == 0 ? v0 : v1);
+}
+
 __device__ inline double ipow(double x, int n) {
   double r = 1.0;
   while (n) {
@@ -207,11 +216,11 @@ __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, boo
 template <int EQ, int DIM>
 __device__ inline void flux_k(int k, const double* U, const double* X, const Phys& ph, double* F) {
   if constexpr (EQ == EQ_ADV) {
-    F[0] = (k == 0 ? ph.vel0 : ph.vel1) * U[0];
+    F[0] = (vel_k(k, ph)) * U[0];
   } else if constexpr (EQ == EQ_ADVV) {
     F[0] = X[k] * U[0];
   } else if constexpr (EQ == EQ_BURG) {
-    F[0] = 0.5 * U[0] * U[0] * (k == 0 ? ph.vel0 : ph.vel1);
+    F[0] = 0.5 * U[0] * U[0] * (vel_k(k, ph));
   } else {
     const double vk = U[1 + k] * X[0];
     const double p = X[1];
@@ -229,12 +238,12 @@ template <int EQ, int DIM>
 __device__ inline double lambda_k(int k, const double* UL, const double* XL, const double* UR,
                                   const double* XR, const Phys& ph) {
   if constexpr (EQ == EQ_ADV) {
-    return fabs(k == 0 ? ph.vel0 : ph.vel1);
+    return fabs(vel_k(k, ph));
   } else if constexpr (EQ == EQ_ADVV) {
     // Sec. 3.3: dhat_ij = max(|chat_ij . beta_i|, |chat_ji . beta_j|)
     return fmax(fabs(XL[k]), fabs(XR[k]));
   } else if constexpr (EQ == EQ_BURG) {
-    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(k == 0 ? ph.vel0 : ph.vel1);
+    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(vel_k(k, ph));
   } else {
     const double g = ph.gamma;
     const double vl = UL[1 + k] * XL[0], vr = UR[1 + k] * XR[0];
