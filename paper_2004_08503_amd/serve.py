@@ -1,9 +1,13 @@
 """Serving loop with continuous batching.
 
 Requests (a problem, an initial state and a number of SSP-RK3 steps at
-CFL 1/2) arrive over time.  The server admits a waiting request as soon as
-its HBM footprint (state + the handle's two stage buffers) fits in the
-budget, keeps every admitted state on the device, and on every tick
+CFL 1/2) arrive over time.  The server admits waiting requests in arrival
+order as soon as their HBM footprint (state + the handle's two stage
+buffers) fits in the budget and, by default, while the admitted requests
+hold at most about one GPU-filling solve of nodes (2^21; a larger request
+is admitted alone).  Small requests thus batch together, and large ones
+are not stretched by sharing every tick with others.  It keeps every
+admitted state on the device, and on every tick
 advances all admitted requests by one step: the requests of one equation
 family form a batch (one HIP graph per step with a work-list launch per
 degree and stage), the families' graphs are enqueued back to back on one
@@ -47,9 +51,14 @@ def footprint_bytes(req: Request) -> int:
 
 
 class Server:
-    def __init__(self, hbm_budget: int, cfl: float = 0.5, keep_results: bool = False):
+    def __init__(self, hbm_budget: int, cfl: float = 0.5, keep_results: bool = False,
+                 max_active: int = 0, max_active_nodes: int = 1 << 21):
         import torch
         self.torch = torch
+        self.max_active = int(max_active)   # 0: no cap on concurrently served requests
+        # 0: no cap; else a request is admitted only while the admitted
+        # requests' nodes stay within it (or nothing else is admitted)
+        self.max_active_nodes = int(max_active_nodes)
         self.budget = int(hbm_budget)
         self.cfl = cfl
         self.keep = keep_results
@@ -73,7 +82,11 @@ class Server:
         while pending or active:
             now = time.perf_counter() - t0
             # admission: FIFO, as long as the footprint fits
-            while pending and pending[0].arrival <= now and used + footprint_bytes(pending[0]) <= self.budget:
+            while (pending and pending[0].arrival <= now and used + footprint_bytes(pending[0]) <= self.budget
+                   and (self.max_active <= 0 or len(active) < self.max_active)
+                   and (self.max_active_nodes <= 0 or not active
+                        or sum(a["req"].problem().num_nodes for a in active.values())
+                        + pending[0].problem().num_nodes <= self.max_active_nodes)):
                 req = pending.pop(0)
                 sv = idp_dg.Solver(req.problem(), stream=self.stream, workspace=True)
                 u = initial_state_device(req)

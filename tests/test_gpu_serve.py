@@ -41,6 +41,20 @@ def test_served_results_equal_alone(budget_mb):
     assert s["tts_s_p99"] >= s["tts_s_p50"] > 0
 
 
+@pytest.mark.parametrize("caps", [dict(max_active_nodes=700), dict(max_active=1), dict(max_active_nodes=0)],
+                         ids=["node-cap", "one-active", "no-cap"])
+def test_admission_caps_keep_results(caps):
+    """Admission by node count or request count only changes when requests
+    run, not what they compute."""
+    idp_dg, serve = _mods()
+    reqs = W.request_stream(8, rate=800.0, n_range=(4, 12), p_range=(2, 4),
+                            steps_range=(3, 7), seed=19)
+    done = serve.Server(hbm_budget=4096 * 2 ** 20, keep_results=True, **caps).run(reqs)
+    assert [d.rid for d in done] == [r.rid for r in reqs]
+    for d, r in zip(done, reqs):
+        assert torch.equal(d.result, alone(idp_dg, r)), r
+
+
 def test_fifo_plain_matches():
     idp_dg, serve = _mods()
     reqs = W.request_stream(4, rate=1000.0, n_range=(4, 8), p_range=(2, 3),
