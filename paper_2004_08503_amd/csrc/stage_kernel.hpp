@@ -185,11 +185,12 @@ __device__ inline double inv_root(double x) {
 // K = p rho^-gamma) (K only when WITHK).  For gamma = 1 + 2/n (GN = n = 5:
 // 7/5, n = 3: 5/3) every fractional power is an integer power of
 // z = rho^(-1/n) or of p^(-1/(n+2)): 1/rho = z^n, K = p z^(n+2); otherwise
-// pow and a division are used.
+// pow and a division are used.  Without K (the time-step pass) 1/rho is a
+// plain division, cheaper than the root.
 template <int DIM, int GN, bool WITHK = true>
 __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, bool& bad) {
   double rinv, z = 0.0;
-  if constexpr (GN > 0) {
+  if constexpr (GN > 0 && WITHK) {   // z = rho^(-1/n) also gives K below
     z = inv_root<GN>(U[0]);
     rinv = ipow_c<GN>(z);
   } else {
@@ -1046,7 +1047,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(Stage
 template <int EQ, int DIM, int P, int EPB>
 struct DtCfg {
   using C = Cfg<EQ, DIM, P, EPB>;
-  static constexpr int L = C::A_F;                          // [DIM][EPB*NF] wave speeds
+  static constexpr int L = C::A_X + C::NAUXF * EPB * C::NS;  // [DIM][EPB*NF] wave speeds
   static constexpr int W = L + DIM * EPB * C::NF;
   static constexpr int R = W + C::N1;
   static constexpr int LDS = R + C::BS / 64;
