@@ -286,3 +286,18 @@ def test_double_mach_reflection_stays_admissible():
     assert not d["bad_input"] and not d["low_order_violation"]
     assert rho.max() < 40.0    # no runaway (the start-up at the wedge tip peaks near 28)
     sv.close()
+
+
+def test_boundary_in_caller_workspace_equals_allocating_handle():
+    idp_dg = _gpu()
+    _, prob, u0 = CASES[1]
+    outs = []
+    for ws in (False, True):
+        sv = idp_dg.Solver(prob, workspace=ws)
+        u = to_dev(u0)
+        for _ in range(5):
+            sv.step_cfl(u, 0.5)
+        torch.cuda.synchronize()
+        outs.append(u.cpu())
+        sv.close()
+    assert torch.equal(outs[0], outs[1])

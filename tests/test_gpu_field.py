@@ -162,3 +162,20 @@ def test_solid_body_revolution_matches_paper(limiter):
         assert abs(g.max() - hi) < 0.01
     assert abs(l1 - e) < 0.05 * e, (l1, e)
     sv.close()
+
+
+def test_field_in_caller_workspace_equals_allocating_handle():
+    """idp_dg_create_in places the velocity samples in the caller's
+    workspace: the same steps, bitwise."""
+    idp_dg = _gpu()
+    prob, u0 = field_problem(10, 8, 3)
+    outs = []
+    for ws in (False, True):
+        sv = idp_dg.Solver(prob, workspace=ws)
+        u = to_dev(u0)
+        for _ in range(5):
+            sv.step_cfl(u, 0.5)
+        torch.cuda.synchronize()
+        outs.append(u.cpu())
+        sv.close()
+    assert torch.equal(outs[0], outs[1])
