@@ -301,3 +301,29 @@ def test_boundary_in_caller_workspace_equals_allocating_handle():
         outs.append(u.cpu())
         sv.close()
     assert torch.equal(outs[0], outs[1])
+
+
+def test_batch_one_dimensional_mixed_boundaries():
+    """1-D Euler solves of several degrees, some with open sides, batched:
+    bitwise equal to the plain path."""
+    idp_dg = _gpu()
+    probs = []
+    for i, (nx, p, bc) in enumerate(((40, 2, 1), (33, 3, 0), (57, 5, 1), (20, 7, 1))):
+        pr = W.Problem(dim=1, nx=nx, ny=1, p=p, eq=W.EULER, bc=(bc, 0))
+        u = W.euler_quadrants(pr, np.random.default_rng(60 + i))
+        probs.append((mixed_boundary(pr, u, 70 + i) if bc else pr, u))
+    solvers = [idp_dg.Solver(pr) for pr, _ in probs]
+    plain = [idp_dg.Solver(pr) for pr, _ in probs]
+    ub = [to_dev(u) for _, u in probs]
+    up = [to_dev(u) for _, u in probs]
+    batch = idp_dg.Batch(solvers)
+    for _ in range(4):
+        batch.step_cfl(ub, 0.5)
+        for sv, u in zip(plain, up):
+            sv.step_cfl(u, 0.5)
+    torch.cuda.synchronize()
+    for a, b in zip(ub, up):
+        assert torch.equal(a, b)
+    batch.close()
+    for sv in solvers + plain:
+        sv.close()
