@@ -63,6 +63,10 @@ def cases():
     p4 = W.Problem(dim=2, nx=10, ny=5, p=2, eq=W.BURGERS, vel=(1.0, -0.6), bc=(1, 1))
     u = np.random.default_rng(7).uniform(-1, 1, (1, p4.num_nodes))
     out.append(("burgers2d", mixed_boundary(p4, u, 8), u))
+    for g, name in ((1.3, "euler2d-g1.3"), (5.0 / 3.0, "euler2d-g5/3")):   # the other kernel families
+        pg = W.Problem(dim=2, nx=6, ny=5, p=3, eq=W.EULER, gamma=g, bc=(1, 1))
+        u = W.euler_quadrants(pg, np.random.default_rng(11))
+        out.append((name, mixed_boundary(pg, u, 12), u))
     wl = W.solid_body(n=9, p=3)
     p5 = wl.prob.replace(bc=(1, 1))
     u = wl.u0 + 0.1 * np.random.default_rng(9).uniform(0, 1, wl.u0.shape)
