@@ -333,19 +333,25 @@ __device__ inline bool admissible(const PhiVal& e) { return e.rho > 0.0 && e.phi
 //    next points are probes under hi at half the tolerance, doubling the
 //    distance after each inadmissible probe;
 //  - the search stops once the bracket is narrower than 1e-15 or than
-//    1e-14 max|uL| / max|P| (the admissible end it returns then moves the
-//    state by less than 1e-14 of its size from any point of the bracket,
-//    the supremum included), and returns the admissible end.
-template <int DIM, int GN>
+//    RTOL max|uL| / max|P| (the admissible end it returns then moves the
+//    state by less than RTOL of its largest component from any point of
+//    the bracket, the supremum included), and returns the admissible end.
+// RTOL: 1e-14 for a subcell face, whose t moves only that face's flux; 1e-16
+// for elementwise limiting, where one node's t is applied to every node of
+// the element, so that nodes of other scales (the small momentum of a gas
+// near rest next to a node of large energy) still land within rounding.
+template <int DIM, int GN, int RTOL_EXP>
 __device__ double entropy_root(const double* uL, const double* P, double U, bool tang, double kmin,
                                const Phys& ph) {
+  constexpr double RTOL = RTOL_EXP == 16 ? 1e-16 : 1e-14;
+  static_assert(RTOL_EXP == 14 || RTOL_EXP == 16, "search tolerance 1e-14 or 1e-16");
   double us = 0.0, ps = 0.0;
 #pragma unroll
   for (int c = 0; c < DIM + 2; ++c) {
     us = fmax(us, fabs(uL[c]));
     ps = fmax(ps, fabs(P[c]));
   }
-  const double tol = fmax(1e-15, 1e-14 * us / ps);
+  const double tol = fmax(1e-15, RTOL * us / ps);
   double lo = 0.0, hi = U, fhi = -INFINITY, dhi = 0.0, rhi = 0.0;
   double t = U, prev = INFINITY, probe = 0.5 * tol;
   int slow = 0;
@@ -847,7 +853,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
             } else {
               double tn = ea.rho > 0.0 && ea.dphi < 0.0 ? alpha - ea.phi / ea.dphi : alpha;
               tn = fmin(fmax(tn, 0.0), alpha);
-              alpha = entropy_root<DIM, gn_of(EQ)>(uL, d, tn, true, kmin, ph_of(A));
+              alpha = entropy_root<DIM, gn_of(EQ), 16>(uL, d, tn, true, kmin, ph_of(A));
             }
           }
         }
@@ -971,8 +977,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         ul[c] = lds[C::C_UL + c * EPB * NP + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
       }
-      const double t = entropy_root<DIM, gn_of(EQ)>(ul, Pv, lds[C::C_AZ + node], (item & 1) != 0,
-                                                    lds[C::C_KM + node], ph_of(A));
+      const double t = entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], (item & 1) != 0,
+                                                        lds[C::C_KM + node], ph_of(A));
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
     }
