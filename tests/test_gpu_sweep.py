@@ -1,0 +1,103 @@
+"""Seeded random configurations against the oracle: each case draws its
+dimension, equation (advection with a constant velocity or a rotation
+field, Burgers, Euler with one of four gammas), degree 1..8, a mesh of
+1..12 x 1..9 elements with random side lengths, a limiter mode,
+periodic or open directions with per-node boundary codes (prescribed
+state, outflow, slip), with or without prescribed states, and a time step
+between 0.1 and 1 of the oracle's CFL bound.  The time-step bound must
+agree to 1e-13 and three SSP-RK3 stages, each fed the oracle's previous
+stage, to 1e-12 per component (max |u_gpu - u_ref| / max |u_ref|)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08503_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = 120
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08503_amd import idp_dg
+    return idp_dg
+
+
+def rel_err(a, b):
+    a = np.asarray(a).reshape(b.shape)
+    return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).max()
+
+
+def random_case(rng):
+    dim = int(rng.integers(1, 3))
+    eqs = [W.ADVECTION, W.BURGERS, W.EULER] + ([W.ADVECTION_FIELD] if dim == 2 else [])
+    eq = int(rng.choice(eqs))
+    p = int(rng.integers(1, 9))
+    nx = int(rng.integers(1, 13))
+    ny = int(rng.integers(1, 10)) if dim == 2 else 1
+    lx = float(rng.uniform(0.5, 2.0))
+    ly = float(rng.uniform(0.5, 2.0)) if dim == 2 else 1.0
+    lim = int(rng.integers(0, 5))
+    gam = float(rng.choice([1.4, 5.0 / 3.0, 1.3, 1.2]))
+    bc = (int(rng.integers(0, 2)), int(rng.integers(0, 2)) if dim == 2 else 0)
+    vel = tuple(float(v) for v in rng.uniform(-1.5, 1.5, 2))
+    prob = W.Problem(dim=dim, nx=nx, ny=ny, p=p, eq=eq, lx=lx, ly=ly, gamma=gam,
+                     limiter=lim, vel=vel, bc=bc)
+    if eq == W.ADVECTION_FIELD:
+        vr, vc = W.rotation_lines(prob, omega=float(rng.uniform(-7, 7)),
+                                  centre=(float(rng.uniform(0, lx)), float(rng.uniform(0, ly))))
+        prob = prob.replace(vrows=vr, vcols=vc)
+    if eq == W.EULER:
+        u = W.euler_quadrants(prob, rng)
+    else:
+        u = rng.uniform(-1.0, 1.0, (1, prob.num_nodes))
+    if any(bc):
+        types, states = [None] * 4, [None] * 4
+        codes = np.array([W.BC_STATE, W.BC_OUTFLOW, W.BC_SLIP], dtype=np.int8)
+        for side in range(4):
+            if not bc[side // 2]:
+                continue
+            n = W.side_nodes(prob, side)
+            types[side] = rng.choice(codes, n)
+            if rng.random() < 0.8:   # else a state side falls back to its own trace
+                states[side] = np.ascontiguousarray(u[:, rng.integers(0, u.shape[1], n)])
+        prob = prob.replace(bnd=W.Boundary(types, states))
+    lo, hi = float(u[0].min()), float(u[0].max())
+    prob = prob.replace(gmin=lo - 0.1 * abs(lo), gmax=hi + 0.1 * abs(hi))
+    return prob, u
+
+
+@pytest.mark.parametrize("seed", range(CASES))
+def test_random_configuration(seed):
+    idp_dg = _gpu()
+    rng = np.random.default_rng(5000 + seed)
+    prob, u = random_case(rng)
+    name = "seed %d: dim %d eq %d p %d mesh %dx%d limiter %d gamma %.3f bc %s" % (
+        seed, prob.dim, prob.eq, prob.p, prob.nx, prob.ny, prob.limiter, prob.gamma, prob.bc)
+    print(name, flush=True)
+    assert oracle.check(prob) == 0, name
+    sv = idp_dg.Solver(prob)
+    try:
+        un = torch.from_numpy(u.copy()).cuda()
+        mdt = oracle.max_dt(prob, u)
+        got = sv.max_dt(un)
+        if np.isfinite(mdt):
+            assert got == pytest.approx(mdt, rel=1e-13), name
+        else:
+            assert not np.isfinite(got), name
+            mdt = 1e-2
+        dt = float(rng.uniform(0.1, 1.0)) * mdt
+        cur_ref, cur = u, un
+        for s in range(3):
+            ref = oracle.stage(prob, None if s == 0 else u, cur_ref, dt, s)
+            out = sv.empty()
+            sv.stage(None if s == 0 else un, cur, out, dt, s)
+            torch.cuda.synchronize()
+            err = rel_err(out.cpu().numpy(), ref)
+            assert err <= 1e-12, "%s stage %d: %.3e" % (name, s, err)
+            cur_ref, cur = ref, torch.from_numpy(ref.copy()).cuda()
+    finally:
+        sv.close()
