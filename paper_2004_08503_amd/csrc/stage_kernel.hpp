@@ -315,14 +315,45 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
 
 __device__ inline bool admissible(const PhiVal& e) { return e.rho > 0.0 && e.phi >= 0.0; }
 
-// The smallest root over the faces of one node.  The node's search data
-// (from the checks at t = alpha): U, the smallest tangent bound over its
-// failing faces (every root lies below its own face's tangent bound, so the
-// node's answer is at most U).  A face searches
-// sup { t in [0, U] : uL + t P admissible }:
-//  - the first point is U itself: for the face that set U it is a Newton
-//    step from alpha (tangent), for the others a probe, and an admissible
-//    probe means the face cannot lower the node's answer below U;
+// Whether V = uL + t P is admissible beyond doubt, from integer powers
+// only; false means "not certain" and leaves the decision to phi_at.  For
+// gamma = 1 + 2/n and rho > 0, with W = rho (rho e) = E rho - |m|^2 / 2 and
+// w = W (gamma - 1) / K_min:  Phi >= 0  <=>  w^n >= rho^(2n+2).  W is
+// lowered by 32 ulps of the terms it is formed from (twice a bound on its
+// own rounding, and on that of a direct evaluation of rho e), the powers
+// carry a relative margin of 1e-12, and densities or w outside the ranges
+// where the powers neither overflow nor underflow are never certain.  For
+// other gamma the test is the direct evaluation itself.
+template <int DIM, int GN>
+__device__ inline bool surely_admissible(double t, const double* uL, const double* P, double kmin,
+                                         double ikg, const Phys& ph) {
+  if constexpr (GN == 5 || GN == 3) {
+    const double rho = fma(t, P[0], uL[0]);
+    double mm = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double m = fma(t, P[1 + k], uL[1 + k]);
+      mm = fma(m, m, mm);
+    }
+    const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
+    const double W = fma(E, rho, -0.5 * mm);
+    const double err = 0x1p-48 * fma(fabs(E), rho, 0.5 * mm);
+    const double w = (W - err) * ikg;
+    const double r2 = rho * rho, r4 = r2 * r2;
+    const double rhs = GN == 5 ? r4 * r4 * r4 : r4 * r4;   // rho^12 or rho^8
+    const double lhs = ipow_c<GN>(w);
+    return rho >= 1e-20 && rho <= 1e20 && w >= 1e-50 && w <= 1e50 && lhs >= rhs * (1.0 + 1e-12);
+  } else {
+    return admissible(phi_at<DIM, GN>(t, uL, P, kmin, ph));
+  }
+}
+
+// sup { t in [0, U] : uL + t P admissible }, for uL admissible.  U is the
+// node's alpha for a subcell face, and for elementwise limiting the
+// tangent bound from alpha (tang = true).
+//  - the first point is U itself: an admissible U is the answer; otherwise
+//    it is the first infeasible end (for a subcell face, the exact value
+//    at alpha that the screen could not certify);
 //  - then Newton steps from the infeasible end hi (Phi is concave wherever
 //    rho > 0, so the tangent at hi cuts zero at or above the root), each a
 //    single evaluation; a tangent step that lands admissible is within
@@ -779,7 +810,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   }
   bool lov = false;
   double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
-  int search = 0, tangent = 0;   // faces of this node for the search list
+  int search = 0, check0 = 0;   // faces of this node for the search list; check u^L first
   double ubound = 0.0;
   const double idt = dt > 0.0 ? 1.0 / dt : 0.0;
   double dtm = 0.0;
@@ -878,68 +909,46 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       az_dbg = alpha;
       if constexpr (is_euler(EQ)) {
         // every partial state uL + t 2d dt/m (+-rbar) must stay admissible
-        // for t <= alpha (eq. convex-provisional).  Each face whose partial
-        // state fails at t = alpha brackets its own root: the tangent at
-        // alpha cuts zero above it, the chord from t = 0 below it (Phi is
-        // concave).  The node needs only the smallest root, which lies in
-        // [min of the lower bounds, U = min of the upper bounds]; faces whose
-        // lower bound is at least U cannot hold it, the others go to the
-        // workgroup's search list with the node's bracket.
+        // for t <= alpha (eq. convex-provisional).  A face whose partial
+        // state at t = alpha is not admissible beyond doubt goes to the
+        // workgroup's search list, which finds its root on [0, alpha]
+        // starting from the exact value at alpha; most faces pass here
+        // with integer powers only.  If u^L itself is not certain, the
+        // search first checks it exactly (u^L off the set by rounding
+        // leaves the node at alpha = 0).  A face whose whole partial-state
+        // correction is below the search tolerance (max|P| <= 1e-14 max|u^L|)
+        // needs no search: any t in [0, alpha] moves the state by less than
+        // that, which is as close as a search would get (in a uniform
+        // region the antidiffusive fluxes are of rounding size and Phi at
+        // alpha is zero to rounding, which no test could settle).
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dtm;
+        const double ikg = (ph_of(A).gamma - 1.0) / kmin;
+        double us = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) us = fmax(us, fabs(uL[c]));
         int act = 0;
-        PhiVal ef[2 * DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
 #pragma unroll
           for (int sd = 0; sd < 2; ++sd) {
             const int fidx = sd ? fr[k] : fl[k];
             const double sg = sd ? 1.0 : -1.0;
-            double Pv[NC];
-            bool nz = false;
+            double Pv[NC], ps = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-              const double cf = sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
-              nz |= cf != 0.0;
-              Pv[c] = g2 * cf;
+              Pv[c] = g2 * (sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx]);
+              ps = fmax(ps, fabs(Pv[c]));
             }
-            ef[2 * k + sd] = phi_at<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ph_of(A));
-            if (nz && !admissible(ef[2 * k + sd])) act |= 1 << (2 * k + sd);
+            if (ps > 1e-14 * us && !surely_admissible<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ikg, ph_of(A)))
+              act |= 1 << (2 * k + sd);
           }
         }
         if (act) {
           const double zero[NC] = {};
-          const PhiVal e0 = phi_at<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ph_of(A));
-          if (!admissible(e0)) {  // u^L itself off the set by rounding
-            alpha = 0.0;
-            act = 0;
-          } else {
-            double tup[2 * DIM], tlo[2 * DIM], ub = alpha;
-#pragma unroll
-            for (int f = 0; f < 2 * DIM; ++f) {
-              const PhiVal& e = ef[f];
-              double tn = e.rho > 0.0 && e.dphi < 0.0 ? alpha - e.phi / e.dphi : alpha;
-              tn = fmin(fmax(tn, 0.0), alpha);
-              double tl = e.rho > 0.0 ? alpha * (e0.phi / (e0.phi - e.phi)) : 0.0;
-              tl = fmin(fmax(tl, 0.0), tn);
-              tup[f] = tn;
-              tlo[f] = tl;
-              if (act & (1 << f)) ub = fmin(ub, tn);
-            }
-            int keep = 0;
-#pragma unroll
-            for (int f = 0; f < 2 * DIM; ++f)
-              if ((act & (1 << f)) && tlo[f] < ub) keep |= 1 << f;
-            if (!keep) {  // the bounds meet: the smallest root is ub
-              alpha = ub;
-            } else {
-              search = keep;
-              ubound = ub;
-#pragma unroll
-              for (int f = 0; f < 2 * DIM; ++f)
-                if (tup[f] <= ub) tangent |= 1 << f;
-            }
-          }
+          search = act;
+          ubound = alpha;
+          check0 = !surely_admissible<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ikg, ph_of(A));
         }
       }
     }
@@ -956,7 +965,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       int* count = reinterpret_cast<int*>(lds + C::S_LN);
 #pragma unroll
       for (int f = 0; f < 2 * DIM; ++f)
-        if (search & (1 << f)) list[atomicAdd(count, 1)] = tid * 8 + f * 2 + ((tangent >> f) & 1);
+        if (search & (1 << f)) list[atomicAdd(count, 1)] = tid * 8 + f * 2 + check0;
     }
     __syncthreads();
     // ---- phase 4b: entropy line searches, spread over the workgroup ----
@@ -977,8 +986,14 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         ul[c] = lds[C::C_UL + c * EPB * NP + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
       }
-      const double t = entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], (item & 1) != 0,
-                                                        lds[C::C_KM + node], ph_of(A));
+      const double km = lds[C::C_KM + node];
+      bool feasible = true;
+      if (item & 1) {
+        const double zero[NC] = {};
+        feasible = admissible(phi_at<DIM, gn_of(EQ)>(0.0, ul, zero, km, ph_of(A)));
+      }
+      const double t = feasible ? entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], false, km, ph_of(A))
+                                : 0.0;
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
     }
