@@ -45,7 +45,17 @@ struct Cfg {
   static constexpr int NL = DIM == 2 ? N1 : 1;          // lines per direction
   static constexpr int NF = NFL * NL;                   // faces per direction
   static constexpr int BS = ((EPB * NP + 63) / 64) * 64;
-  static constexpr int NITEM = (EPB * DIM * NF + BS - 1) / BS;
+  // phase 3 work: per direction, the element faces (f = 0 or p + 1) and the
+  // interior faces form two groups, each cut into chunks of 64 items; a wave
+  // takes whole chunks, so each of its passes runs one body specialised for
+  // a direction and a face kind
+  static constexpr int NW = BS / 64;                   // waves per workgroup
+  static constexpr int GE = EPB * 2 * NL;              // element-face items per direction
+  static constexpr int GI = EPB * P * NL;              // interior items per direction
+  static constexpr int CE = (GE + 63) / 64;            // chunks per group
+  static constexpr int CI = (GI + 63) / 64;
+  static constexpr int NCHUNK = DIM * (CE + CI);
+  static constexpr int NITEM = (NCHUNK + NW - 1) / NW;  // chunks per wave
   // region A: phase 1-2 results, read in phase 3 (fluxes of own nodes only:
   // the face-trace fluxes are formed where a face needs them)
   static constexpr int A_U = 0;
@@ -232,6 +242,34 @@ __device__ inline void flux_k(int k, const double* U, const double* X, const Phy
   }
 }
 
+// The two-rarefaction bound of the Euler wave speeds (Guermond and Popov,
+// J. Comput. Phys. 2016, valid for 1 < gamma <= 5/3) from the normal
+// velocities, pressures, sound speeds and p^-(gamma-1)/(2 gamma) of the
+// left and right states.
+template <int GN>
+__device__ inline double euler_lambda(double vl, double vr, double pl, double pr, double cl, double cr,
+                                      double xl3, double xr3, const Phys& ph) {
+  const double g = ph.gamma;
+  double num = cl + cr - 0.5 * (g - 1.0) * (vr - vl);
+  num = num < 0.0 ? 0.0 : num;
+  const double den = cl * xl3 + cr * xr3;
+  const double base = num / den;
+  double pstar, ipl, ipr;
+  if constexpr (GN > 0) {  // 2 gamma/(gamma-1) = n + 2; 1/p = (p^-1/(n+2))^(n+2)
+    pstar = ipow_c<GN + 2>(base);
+    ipl = ipow_c<GN + 2>(xl3);
+    ipr = ipow_c<GN + 2>(xr3);
+  } else {
+    pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
+    ipl = 1.0 / pl;
+    ipr = 1.0 / pr;
+  }
+  const double fac = (g + 1.0) / (2.0 * g);
+  const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) * ipl);
+  const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) * ipr);
+  return fmax(fmax(-lam_l, 0.0), fmax(lam_r, 0.0));
+}
+
 // Upper bound of the maximum wave speed of the Riemann problem (UL | UR)
 // along +e_k.  Euler: the two-rarefaction pressure bound (Guermond and
 // Popov, J. Comput. Phys. 2016), valid for 1 < gamma <= 5/3.
@@ -246,28 +284,33 @@ __device__ inline double lambda_k(int k, const double* UL, const double* XL, con
   } else if constexpr (EQ == EQ_BURG) {
     return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(vel_k(k, ph));
   } else {
-    const double g = ph.gamma;
     const double vl = UL[1 + k] * XL[0], vr = UR[1 + k] * XR[0];
-    const double pl = XL[1], pr = XR[1], cl = XL[2], cr = XR[2];
-    double num = cl + cr - 0.5 * (g - 1.0) * (vr - vl);
-    num = num < 0.0 ? 0.0 : num;
-    const double den = cl * XL[3] + cr * XR[3];
-    const double base = num / den;
-    constexpr int GN = gn_of(EQ);
-    double pstar, ipl, ipr;
-    if constexpr (GN > 0) {  // 2 gamma/(gamma-1) = n + 2; 1/p = (p^-1/(n+2))^(n+2)
-      pstar = ipow_c<GN + 2>(base);
-      ipl = ipow_c<GN + 2>(XL[3]);
-      ipr = ipow_c<GN + 2>(XR[3]);
-    } else {
-      pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
-      ipl = 1.0 / pl;
-      ipr = 1.0 / pr;
+    return euler_lambda<gn_of(EQ)>(vl, vr, XL[1], XR[1], XL[2], XR[2], XL[3], XR[3], ph);
+  }
+}
+
+// lambda_k of an element face from its own-side state O and its trace T:
+// side 1 is the element's right face (O on the left), side 0 its left face
+// (T on the left).  The Euler bound selects the values it reads into
+// left/right order and then forms the same expressions as lambda_k (so the
+// result is identical to the bound of the pair in that order).
+template <int EQ, int DIM>
+__device__ inline double lambda_face(int k, const double* UO, const double* XO, const double* UT,
+                                     const double* XT, int side, const Phys& ph) {
+  if constexpr (is_euler(EQ)) {
+    const bool r = side != 0;
+    double ul[DIM + 2] = {}, ur[DIM + 2] = {}, xl[4], xr[4];
+    ul[1 + k] = r ? UO[1 + k] : UT[1 + k];
+    ur[1 + k] = r ? UT[1 + k] : UO[1 + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xl[q] = r ? XO[q] : XT[q];
+      xr[q] = r ? XT[q] : XO[q];
     }
-    const double fac = (g + 1.0) / (2.0 * g);
-    const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) * ipl);
-    const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) * ipr);
-    return fmax(fmax(-lam_l, 0.0), fmax(lam_r, 0.0));
+    return lambda_k<EQ, DIM>(k, ul, xl, ur, xr, ph);
+  } else {
+    // symmetric in the two states
+    return lambda_k<EQ, DIM>(k, UO, XO, UT, XT, ph);
   }
 }
 
@@ -433,32 +476,130 @@ __device__ inline int own_slot(int k, int l, int pos) {
   return k == 0 ? l * (P + 1) + pos : pos * (P + 1) + l;
 }
 
-// Work item w of a tile's face pass -> element le, direction k, line l and
-// position f along it.  Every element face (f = 0 or p + 1) of the tile
-// comes first, then every interior face, so that most waves take one path:
-// the trace-side flux on element faces, the high-order contraction on
-// interior faces.
-template <int DIM, int P>
-__device__ inline void face_item(int w, int nel, int* le, int* k, int* l, int* f) {
-  constexpr int NL = DIM == 2 ? P + 1 : 1;
-  constexpr int PE = DIM * NL * 2;   // element-face items per element
-  constexpr int PI = DIM * NL * P;   // interior items per element
-  if (w < nel * PE) {
-    *le = w / PE;
-    int r = w - *le * PE;
-    *k = DIM == 2 ? r / (2 * NL) : 0;
-    r -= *k * (2 * NL);
-    *l = r >> 1;
-    *f = (r & 1) ? P + 1 : 0;
-  } else {
-    w -= nel * PE;
-    *le = w / PI;
-    int r = w - *le * PI;
-    *k = DIM == 2 ? r / (P * NL) : 0;
-    r -= *k * (P * NL);
-    *l = r / P;
-    *f = 1 + (r - *l * P);
+// One element face of a tile for phase 3: item -> element le, line l and
+// side (0: f = 0, the trace on the left; 1: f = p + 1, the trace on the
+// right).  Writes the low-order flux, the bar state of the limited
+// component and the face's index in the phase-3 arrays (o < 0: no face).
+template <int EQ, int DIM, int P, int EPB, int K>
+__device__ __forceinline__ void element_face(const double* lds, const Phys& ph, int item, int nel,
+                                             double* FLo, double& UBo, int& o) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NL = C::NL;
+  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  const int le = item / (2 * NL);
+  if (le >= nel) return;
+  const int r = item - le * (2 * NL);
+  const int l = r >> 1, side = r & 1;
+  const int base = le * NS;
+  const int st = base + NP + (2 * K + side) * C::TJ + l;             // trace slot
+  const int so = base + own_slot<DIM, P>(K, l, side ? P : 0);       // own slot
+  double UO[NC], UT[NC], XO[NX], XT[NX], FO[NC], FT[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    UO[c] = lds[C::A_U + c * EPB * NS + so];
+    UT[c] = lds[C::A_U + c * EPB * NS + st];
+    FO[c] = lds[C::A_F + (K * NC + c) * EPB * NP + le * NP + (so - base)];
   }
+#pragma unroll
+  for (int q = 0; q < C::NAUXF; ++q) {
+    XO[q] = lds[C::A_X + q * EPB * NS + so];
+    XT[q] = lds[C::A_X + q * EPB * NS + st];
+  }
+  flux_k<EQ, DIM>(K, UT, XT, ph, FT);
+  const double lam = lambda_face<EQ, DIM>(K, UO, XO, UT, XT, side, ph);
+  // (F_L + F_R) / 2 - lam (U_R - U_L) / 2 with U_R - U_L = sg (U_T - U_O),
+  // sg = +-1 (exact).  The trace flux enters its sums rounded, not fused
+  // into them, as an interior face's fluxes do.
+  const double sg = side ? 1.0 : -1.0;
+  double fs[NC], df0;
+  {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fs[c] = FO[c] + FT[c];
+    df0 = FT[0] - FO[0];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * fs[c] - 0.5 * lam * (sg * (UT[c] - UO[c]));
+  const double avg = 0.5 * (UO[0] + UT[0]);
+  UBo = lam > 0.0 ? avg - (sg * df0) / (2.0 * lam) : avg;
+  o = le * C::NF + l * C::NFL + (side ? P + 1 : 0);
+}
+
+// One interior subcell face (1 <= f <= p) of a tile for phase 3: also the
+// high-order subcell flux and the antidiffusive flux.
+template <int EQ, int DIM, int P, int EPB, int K>
+__device__ __forceinline__ void interior_face(const double* lds, const Phys& ph, const Solve& S, int item,
+                                              int nel, double* FLo, double* RBo, double& UBo, int& o) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NL = C::NL, N1 = C::N1;
+  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  const int le = item / (P * NL);
+  if (le >= nel) return;
+  const int r = item - le * (P * NL);
+  const int l = r / P;
+  const int f = 1 + (r - l * P);
+  const int base = le * NS;
+  const int sl = base + own_slot<DIM, P>(K, l, f - 1);
+  const int sr = base + own_slot<DIM, P>(K, l, f);
+  double UL[NC], UR[NC], FL[NC], FR[NC], XL[NX], XR[NX];
+  const double* Fo = lds + C::A_F + K * NC * EPB * NP + le * NP;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    UL[c] = lds[C::A_U + c * EPB * NS + sl];
+    UR[c] = lds[C::A_U + c * EPB * NS + sr];
+    FL[c] = Fo[c * EPB * NP + sl - base];
+    FR[c] = Fo[c * EPB * NP + sr - base];
+  }
+#pragma unroll
+  for (int q = 0; q < C::NAUXF; ++q) {
+    XL[q] = lds[C::A_X + q * EPB * NS + sl];
+    XR[q] = lds[C::A_X + q * EPB * NS + sr];
+  }
+  const double lam = lambda_k<EQ, DIM>(K, UL, XL, UR, XR, ph);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
+  const double avg = 0.5 * (UL[0] + UR[0]);
+  UBo = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
+  const double sc = DIM == 2 ? lds[C::S_W + l] * (K == 0 ? S.hy : S.hx) : 1.0;
+  const double* q = lds + C::S_Q + (f - 1) * N1;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double* Fl = Fo + c * EPB * NP;
+    double fh = Fl[own_slot<DIM, P>(K, l, 0)];
+#pragma unroll
+    for (int e = 0; e <= P; ++e) fh += q[e] * Fl[own_slot<DIM, P>(K, l, e)];
+    RBo[c] = sc * (FLo[c] - fh);
+  }
+  o = le * C::NF + l * C::NFL + f;
+}
+
+// Phase-3 chunk ch (wave-uniform) of a tile: chunks of the element-face
+// groups (direction 0, then 1) come first, then those of the interior
+// groups; lane picks the item within the chunk.
+template <int EQ, int DIM, int P, int EPB>
+__device__ __forceinline__ void face_chunk(const double* lds, const Phys& ph, const Solve& S, int ch, int lane,
+                                           int nel, double* FLo, double* RBo, double& UBo, int& o) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  if (ch < DIM * C::CE) {
+    const int k = ch / C::CE;
+    const int item = (ch - k * C::CE) * 64 + lane;
+    if (k == 0) element_face<EQ, DIM, P, EPB, 0>(lds, ph, item, nel, FLo, UBo, o);
+    else if constexpr (DIM == 2) element_face<EQ, DIM, P, EPB, 1>(lds, ph, item, nel, FLo, UBo, o);
+  } else if (ch < C::NCHUNK) {
+    const int c2 = ch - DIM * C::CE;
+    const int k = c2 / C::CI;
+    const int item = (c2 - k * C::CI) * 64 + lane;
+    if (k == 0) interior_face<EQ, DIM, P, EPB, 0>(lds, ph, S, item, nel, FLo, RBo, UBo, o);
+    else if constexpr (DIM == 2) interior_face<EQ, DIM, P, EPB, 1>(lds, ph, S, item, nel, FLo, RBo, UBo, o);
+  }
+}
+
+// direction of phase-3 chunk ch
+template <int EQ, int DIM, int P, int EPB>
+__device__ inline int chunk_dir(int ch) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  if constexpr (DIM == 1) return 0;
+  return ch < DIM * C::CE ? ch / C::CE : (ch - DIM * C::CE) / C::CI;
 }
 
 // ----------------------------------------------------------------------
@@ -722,70 +863,25 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       }
     }
   }
+  // one work item per subcell face of every line (element faces included,
+  // formed by both adjacent elements), in wave-uniform chunks
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM];
+  int rO[C::NITEM];
 #pragma unroll
   for (int it = 0; it < C::NITEM; ++it) {
-    const int w = tid + it * C::BS;
     rUB[it] = 0.0;
+    rO[it] = -1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
-    if (w < nel * DIM * NF) {
-      int le, k, l, f;
-      face_item<DIM, P>(w, nel, &le, &k, &l, &f);
-      const int base = le * NS;
-      const int sl = base + (f == 0 ? NP + (2 * k) * C::TJ + l : own_slot<DIM, P>(k, l, f - 1));
-      const int sr = base + (f == P + 1 ? NP + (2 * k + 1) * C::TJ + l : own_slot<DIM, P>(k, l, f));
-      double UL[NC], UR[NC], FL[NC], FR[NC], XL[NX], XR[NX];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        UL[c] = lds[C::A_U + c * EPB * NS + sl];
-        UR[c] = lds[C::A_U + c * EPB * NS + sr];
-      }
-#pragma unroll
-      for (int q = 0; q < C::NAUXF; ++q) {
-        XL[q] = lds[C::A_X + q * EPB * NS + sl];
-        XR[q] = lds[C::A_X + q * EPB * NS + sr];
-      }
-      const double* Fo = lds + C::A_F + k * NC * EPB * NP + le * NP;
-      if (f == 0) {
-        flux_k<EQ, DIM>(k, UL, XL, A.ph, FL);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) FL[c] = Fo[c * EPB * NP + sl - base];
-      }
-      if (f == P + 1) {
-        flux_k<EQ, DIM>(k, UR, XR, A.ph, FR);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) FR[c] = Fo[c * EPB * NP + sr - base];
-      }
-      const double lam = lambda_k<EQ, DIM>(k, UL, XL, UR, XR, A.ph);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) rFL[it][c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
-      const double avg = 0.5 * (UL[0] + UR[0]);
-      rUB[it] = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
-      if (f >= 1 && f <= P) {
-        const double sc = DIM == 2 ? lds[C::S_W + l] * (k == 0 ? S.hy : S.hx) : 1.0;
-        const double* q = lds + C::S_Q + (f - 1) * N1;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double* Fl = Fo + c * EPB * NP;
-          double fh = Fl[own_slot<DIM, P>(k, l, 0)];
-#pragma unroll
-          for (int e = 0; e <= P; ++e) fh += q[e] * Fl[own_slot<DIM, P>(k, l, e)];
-          rRB[it][c] = sc * (rFL[it][c] - fh);
-        }
-      }
-    }
+    face_chunk<EQ, DIM, P, EPB>(lds, A.ph, S, wv + it * C::NW, lane, nel, rFL[it], rRB[it], rUB[it], rO[it]);
   }
   __syncthreads();  // region A is dead from here on
 #pragma unroll
   for (int it = 0; it < C::NITEM; ++it) {
-    const int w = tid + it * C::BS;
-    if (w < nel * DIM * NF) {
-      int le, k, l, f;
-      face_item<DIM, P>(w, nel, &le, &k, &l, &f);
-      const int o = le * NF + l * NFL + f;
+    const int k = chunk_dir<EQ, DIM, P, EPB>(wv + it * C::NW);
+    const int o = rO[it];
+    if (o >= 0) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         lds[C::B_FL + (k * NC + c) * EPB * NF + o] = rFL[it][c];
