@@ -1168,7 +1168,38 @@ struct DtCfg {
   static constexpr int W = L + DIM * EPB * C::NF;
   static constexpr int R = W + C::N1;
   static constexpr int LDS = R + C::BS / 64;
+  static constexpr int CH = (EPB * C::NF + 63) / 64;   // chunks of faces per direction
 };
+
+// Wave speed of face w (element le, line l, position f in 0..p+1) of
+// direction K of a tile, into the time-step kernel's array.
+template <int EQ, int DIM, int P, int EPB, int K>
+__device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int w, int nel) {
+  using C = Cfg<EQ, DIM, P, EPB>;
+  using D = DtCfg<EQ, DIM, P, EPB>;
+  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL;
+  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  const int le = w / NF;
+  if (le >= nel) return;
+  const int fi = w - le * NF;
+  const int l = fi / NFL;
+  const int f = fi - l * NFL;
+  const int base = le * NS;
+  const int sl = base + (f == 0 ? NP + (2 * K) * C::TJ + l : own_slot<DIM, P>(K, l, f - 1));
+  const int sr = base + (f == P + 1 ? NP + (2 * K + 1) * C::TJ + l : own_slot<DIM, P>(K, l, f));
+  double UL[NC], UR[NC], XL[NX], XR[NX];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    UL[c] = lds[C::A_U + c * EPB * NS + sl];
+    UR[c] = lds[C::A_U + c * EPB * NS + sr];
+  }
+#pragma unroll
+  for (int q = 0; q < C::NAUXF; ++q) {
+    XL[q] = lds[C::A_X + q * EPB * NS + sl];
+    XR[q] = lds[C::A_X + q * EPB * NS + sr];
+  }
+  lds[D::L + K * EPB * NF + le * NF + fi] = lambda_k<EQ, DIM>(K, UL, XL, UR, XR, ph);
+}
 
 // the minimum of one tile into *out
 template <int EQ, int DIM, int P, int EPB>
@@ -1186,28 +1217,13 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   double U[NC];
   load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, bnd, U, nullptr);
   __syncthreads();
-  for (int w = tid; w < nel * DIM * NF; w += C::BS) {
-    const int le = w / (DIM * NF);
-    const int r = w - le * (DIM * NF);
-    const int k = DIM == 2 ? r / NF : 0;
-    const int fi = r - k * NF;
-    const int l = fi / NFL;
-    const int f = fi - l * NFL;
-    const int base = le * NS;
-    const int sl = base + (f == 0 ? NP + (2 * k) * C::TJ + l : own_slot<DIM, P>(k, l, f - 1));
-    const int sr = base + (f == P + 1 ? NP + (2 * k + 1) * C::TJ + l : own_slot<DIM, P>(k, l, f));
-    double UL[NC], UR[NC], XL[NX], XR[NX];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      UL[c] = lds[C::A_U + c * EPB * NS + sl];
-      UR[c] = lds[C::A_U + c * EPB * NS + sr];
-    }
-#pragma unroll
-    for (int q = 0; q < C::NAUXF; ++q) {
-      XL[q] = lds[C::A_X + q * EPB * NS + sl];
-      XR[q] = lds[C::A_X + q * EPB * NS + sr];
-    }
-    lds[D::L + k * EPB * NF + le * NF + fi] = lambda_k<EQ, DIM>(k, UL, XL, UR, XR, A.ph);
+  // wave-uniform chunks of 64 faces of one direction (D::CH per direction)
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  for (int ch = wv; ch < DIM * D::CH; ch += C::NW) {
+    const int k = ch / D::CH;
+    const int w = (ch - k * D::CH) * 64 + lane;
+    if (k == 0) dt_face<EQ, DIM, P, EPB, 0>(lds, A.ph, w, nel);
+    else if constexpr (DIM == 2) dt_face<EQ, DIM, P, EPB, 1>(lds, A.ph, w, nel);
   }
   __syncthreads();
   double dti = INFINITY;
