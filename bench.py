@@ -223,16 +223,18 @@ def workload_legs(wl):
     return out
 
 
-def serving_leg(count, load, budget_gb=64.0):
+def serving_leg(count, load, budget_gb=64.0, busy=None):
     """The served workload: a seeded Poisson stream of `count` requests (half
     Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps).  The
     arrival rate is set for the given offered load of the plain path's own
     capacity on this stream, measured by running the same requests back to
-    back, one at a time.  The stream then runs once through the
-    continuous-batching server and once FIFO through the plain path."""
+    back, one at a time (or given as `busy`, seconds).  The stream then runs
+    once through the continuous-batching server and once FIFO through the
+    plain path."""
     from paper_2004_08503_amd import serve, workloads as W
-    back_to_back = W.request_stream(count, rate=1e9, seed=5)
-    busy = serve.summarize(serve.run_fifo_plain(back_to_back))["makespan_s"]
+    if busy is None:
+        back_to_back = W.request_stream(count, rate=1e9, seed=5)
+        busy = serve.summarize(serve.run_fifo_plain(back_to_back))["makespan_s"]
     rate = load * count / busy
     reqs = W.request_stream(count, rate=rate, seed=5)
     srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
@@ -259,6 +261,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests in the served stream (0 skips the serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-overload", type=float, default=1.3,
+                    help="offered load of a second served run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (4 times), the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -387,6 +391,9 @@ def main():
         out["batched"] = batched_leg(args.batch_steps)
     if args.serve_requests > 0:
         out["serving"] = serving_leg(args.serve_requests, args.serve_load)
+        if args.serve_overload > 0:   # the same stream arriving faster than the plain path serves it
+            out["serving_overload"] = serving_leg(args.serve_requests, args.serve_overload,
+                                                  busy=out["serving"]["plain_service_s"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, dt_last)
     print(json.dumps(out))

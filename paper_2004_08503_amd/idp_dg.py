@@ -347,6 +347,15 @@ class Batch:
     def step_cfl(self, us, cfl):
         self._check(lib.idp_dg_batch_step_cfl(self._b, self._ptrs(us), float(cfl)))
 
+    def prepare(self, us):
+        """The checked state-pointer array of `us`, for repeated
+        step_cfl_prepared calls while the members and their state tensors
+        stay the same (the tensors must stay alive)."""
+        return self._ptrs(us)
+
+    def step_cfl_prepared(self, ptrs, cfl):
+        self._check(lib.idp_dg_batch_step_cfl(self._b, ptrs, float(cfl)))
+
     def last_dt(self):
         d = (ctypes.c_double * self.n)()
         self._check(lib.idp_dg_batch_last_dt(self._b, d))

@@ -3,17 +3,24 @@
 Requests (a problem, an initial state and a number of SSP-RK3 steps at
 CFL 1/2) arrive over time.  The server admits waiting requests in arrival
 order as soon as their HBM footprint (state + the handle's two stage
-buffers) fits in the budget and, by default, while the admitted requests
-hold at most about one GPU-filling solve of nodes (2^21; a larger request
-is admitted alone).  Small requests thus batch together, and large ones
-are not stretched by sharing every tick with others.  It keeps every
-admitted state on the device, and on every tick
-advances all admitted requests by one step: the requests of one equation
-family form a batch (one HIP graph per step with a work-list launch per
-degree and stage), the families' graphs are enqueued back to back on one
-stream.  A request leaves as soon as its last step is enqueued; its
-completion time is the GPU time of that step's end (HIP event), so
-time-to-solution = completion - arrival.
+buffers) fits in the budget.  By default a large request is also admitted
+only while the admitted large requests hold at most about one GPU-filling
+solve of nodes (2^21; a larger request runs alone).  Large requests are
+thus not stretched by sharing every tick with each other, and a large
+request that must wait holds back the large requests behind it.  Small
+requests (at most 1/16 of that many nodes) are admitted as soon as they
+fit, past a waiting large request, and are not counted against the cap.
+
+Every admitted state stays on the device.  On every tick, each admitted
+request advances by one step:
+- the requests of one equation family form a batch (one HIP graph per
+  step, with a work-list launch per degree and stage);
+- a family with one admitted request takes the plain path's graph;
+- the families' steps are enqueued back to back on one stream.
+
+A request leaves as soon as its last step is enqueued.  Its completion time
+is the GPU time at the end of that step (HIP event), so time-to-solution =
+completion - arrival.
 
 The same request stream can be run FIFO through the plain path (one
 request at a time, one solve per launch) for comparison.  Every request's
@@ -52,13 +59,19 @@ def footprint_bytes(req: Request) -> int:
 
 class Server:
     def __init__(self, hbm_budget: int, cfl: float = 0.5, keep_results: bool = False,
-                 max_active: int = 0, max_active_nodes: int = 1 << 21):
+                 max_active: int = 0, max_active_nodes: int = 1 << 21, small_nodes: int = -1):
         import torch
         self.torch = torch
         self.max_active = int(max_active)   # 0: no cap on concurrently served requests
-        # 0: no cap; else a request is admitted only while the admitted
-        # requests' nodes stay within it (or nothing else is admitted)
+        # 0: no cap; else a large request is admitted only while the admitted
+        # large requests' nodes stay within it (or no other large one is
+        # admitted)
         self.max_active_nodes = int(max_active_nodes)
+        # requests of at most this many nodes are small: admitted as soon as
+        # their footprint fits, past a large request that waits, and not
+        # counted against max_active_nodes (-1: max_active_nodes / 16; 0: no
+        # small class, every request waits its turn in arrival order)
+        self.small_nodes = (self.max_active_nodes // 16 if small_nodes < 0 else int(small_nodes))
         self.budget = int(hbm_budget)
         self.cfl = cfl
         self.keep = keep_results
@@ -70,70 +83,113 @@ class Server:
     def run(self, requests: List[Request]) -> List[Done]:
         torch = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
+        nxt = 0                            # next request to arrive
+        waiting: List[Request] = []        # arrived, not admitted (arrival order)
         active: Dict[int, dict] = {}
-        used = 0
-        batches: Dict[int, tuple] = {}     # family -> (member ids, Batch)
+        used = 0                           # bytes of the admitted requests
+        large = 0                          # nodes of the admitted large requests
+        groups: Dict[int, list] = {}       # family -> [member ids, Batch, state pointers]
+        dirty = set()                      # families whose membership changed
+        ends: Dict[int, List[int]] = {}    # tick -> requests whose last step it is
+        tick = 0
         finishing = []                     # (request record, end event)
         out: List[Done] = []
         torch.cuda.synchronize()
         self.ref = torch.cuda.Event(enable_timing=True)
         self.ref.record(self.stream)
         t0 = time.perf_counter()
-        while pending or active:
+        while nxt < len(pending) or waiting or active:
             now = time.perf_counter() - t0
-            # admission: FIFO, as long as the footprint fits
-            while (pending and pending[0].arrival <= now and used + footprint_bytes(pending[0]) <= self.budget
-                   and (self.max_active <= 0 or len(active) < self.max_active)
-                   and (self.max_active_nodes <= 0 or not active
-                        or sum(a["req"].problem().num_nodes for a in active.values())
-                        + pending[0].problem().num_nodes <= self.max_active_nodes)):
-                req = pending.pop(0)
-                sv = idp_dg.Solver(req.problem(), stream=self.stream, workspace=True)
+            while nxt < len(pending) and pending[nxt].arrival <= now:
+                waiting.append(pending[nxt])
+                nxt += 1
+            # admission in arrival order while the footprint and the caps
+            # allow; a large request that must wait holds back the large
+            # requests behind it, not the small ones
+            large_blocked = False
+            keep = []
+            for req in waiting:
+                prob = req.problem()
+                fp = footprint_bytes(req)
+                small = prob.num_nodes <= self.small_nodes
+                ok = used + fp <= self.budget and not (0 < self.max_active <= len(active))
+                if not small:
+                    ok = ok and not large_blocked and not (
+                        self.max_active_nodes > 0 and large > 0
+                        and large + prob.num_nodes > self.max_active_nodes)
+                    large_blocked = large_blocked or not ok
+                if not ok:
+                    keep.append(req)
+                    continue
+                sv = idp_dg.Solver(prob, stream=self.stream, workspace=True)
                 u = initial_state_device(req)
-                active[req.rid] = {"req": req, "sv": sv, "u": u, "left": req.steps,
+                fam = idp_dg.family_of(prob)
+                active[req.rid] = {"req": req, "sv": sv, "u": u, "fam": fam, "fp": fp,
+                                   "large": 0 if small else prob.num_nodes,
                                    "admitted": time.perf_counter() - t0}
-                used += footprint_bytes(req)
+                used += fp
+                large += active[req.rid]["large"]
+                ends.setdefault(tick + req.steps - 1, []).append(req.rid)
+                dirty.add(fam)
+            waiting = keep
+            if not active and waiting and not any(
+                    footprint_bytes(r) <= self.budget for r in waiting):
+                raise ValueError("request %d needs %d bytes, more than the HBM budget"
+                                 % (waiting[0].rid, footprint_bytes(waiting[0])))
             if not active:
-                if pending:
-                    wait = pending[0].arrival - (time.perf_counter() - t0)
+                if nxt < len(pending):
+                    wait = pending[nxt].arrival - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
-            # one step of every admitted request, batched per family
-            fams: Dict[int, List[int]] = {}
-            for rid, a in active.items():
-                fams.setdefault(idp_dg.family_of(a["req"].problem()), []).append(rid)
-            for fam, ids in fams.items():
-                ids = sorted(ids)
-                cur = batches.get(fam)
+            # batches of the families whose membership changed
+            for fam in dirty:
+                ids = sorted(r for r, a in active.items() if a["fam"] == fam)
+                g = groups.get(fam)
+                if not ids:
+                    if g is not None:
+                        g[0], g[2] = [], None
+                    continue
                 members = [active[i]["sv"] for i in ids]
-                if cur is None:
-                    batches[fam] = [ids, idp_dg.Batch(members, stream=self.stream)]
-                elif cur[0] != ids:
-                    cur[1].update(members)
-                    cur[0] = ids
-                batches[fam][1].step_cfl([active[i]["u"] for i in ids], self.cfl)
+                if g is None:
+                    g = groups[fam] = [ids, idp_dg.Batch(members, stream=self.stream), None]
+                elif g[0] != ids:
+                    g[1].update(members)
+                    g[0] = ids
+                g[2] = g[1].prepare([active[i]["u"] for i in ids])
+            dirty.clear()
+            # one step of every admitted request, batched per family; a
+            # family with one admitted request takes the plain path (the
+            # same step, bitwise, without the work-list indirection)
+            for ids, b, ptrs in groups.values():
+                if len(ids) == 1:
+                    a = active[ids[0]]
+                    a["sv"].step_cfl(a["u"], self.cfl)
+                elif ids:
+                    b.step_cfl_prepared(ptrs, self.cfl)
             # retire requests whose last step is now enqueued
-            for rid in [r for r, a in active.items() if a["left"] == 1]:
+            for rid in ends.pop(tick, ()):
                 a = active.pop(rid)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.stream)
                 finishing.append((a, ev))
-                used -= footprint_bytes(a["req"])
-            for a in active.values():
-                a["left"] -= 1
+                used -= a["fp"]
+                large -= a["large"]
+                dirty.add(a["fam"])
+            tick += 1
             # record finished requests whose work is complete
-            still = []
-            for a, ev in finishing:
-                if ev.query():
-                    out.append(self._done(a, ev))
-                else:
-                    still.append((a, ev))
-            finishing = still
+            if finishing:
+                still = []
+                for a, ev in finishing:
+                    if ev.query():
+                        out.append(self._done(a, ev))
+                    else:
+                        still.append((a, ev))
+                finishing = still
         for a, ev in finishing:
             ev.synchronize()
             out.append(self._done(a, ev))
-        for ids, b in batches.values():
+        for ids, b, ptrs in groups.values():
             b.close()
         return sorted(out, key=lambda d: d.rid)
 

@@ -41,8 +41,10 @@ def test_served_results_equal_alone(budget_mb):
     assert s["tts_s_p99"] >= s["tts_s_p50"] > 0
 
 
-@pytest.mark.parametrize("caps", [dict(max_active_nodes=700), dict(max_active=1), dict(max_active_nodes=0)],
-                         ids=["node-cap", "one-active", "no-cap"])
+@pytest.mark.parametrize("caps", [dict(max_active_nodes=700), dict(max_active=1), dict(max_active_nodes=0),
+                                  dict(max_active_nodes=700, small_nodes=300),
+                                  dict(max_active_nodes=700, small_nodes=0)],
+                         ids=["node-cap", "one-active", "no-cap", "small-class", "strict-order"])
 def test_admission_caps_keep_results(caps):
     """Admission by node count or request count only changes when requests
     run, not what they compute."""
@@ -62,3 +64,26 @@ def test_fifo_plain_matches():
     done = serve.run_fifo_plain(reqs, keep_results=True)
     for d, r in zip(done, reqs):
         assert torch.equal(d.result, alone(idp_dg, r))
+
+
+def test_small_requests_pass_a_waiting_large_one():
+    """With a node cap that lets one large request run at a time, a small
+    request that arrives behind a second, waiting large one is admitted
+    before it (small requests do not wait their turn in arrival order), and
+    every result still equals the request solved alone."""
+    idp_dg, serve = _mods()
+    from paper_2004_08503_amd.workloads import Request
+    reqs = [Request(rid=0, kind="euler", n=24, p=3, steps=40, arrival=0.0, seed=1),
+            Request(rid=1, kind="euler", n=24, p=3, steps=10, arrival=0.0, seed=2),
+            Request(rid=2, kind="burgers", n=6, p=2, steps=5, arrival=0.0, seed=3)]
+    big = reqs[0].problem().num_nodes
+    small = reqs[2].problem().num_nodes
+    assert small < big // 16
+    srv = serve.Server(hbm_budget=4096 * 2 ** 20, keep_results=True, max_active_nodes=big, small_nodes=big // 16)
+    done = srv.run(reqs)
+    by = {d.rid: d for d in done}
+    assert by[2].admitted <= by[1].admitted          # passed the waiting large request
+    assert by[1].admitted >= by[0].admitted
+    assert by[2].finished < by[0].finished           # ran beside the first large one
+    for d, r in zip(done, reqs):
+        assert torch.equal(d.result, alone(idp_dg, r)), r
