@@ -206,13 +206,18 @@ def double_mach_state(nx=2400, ny=600, p=3):
 
 
 def workload_legs(wl):
-    """The widened paths measured like the benchmark: the paper's
-    solid-body rotation (velocity field, 64^2 and 512^2, p = 3), its double
-    Mach reflection set-up at the paper's own resolution (open boundaries,
-    2400 x 600, p = 3, 23 M nodes) and a large 1-D Euler problem (2^20
-    elements, p = 3, the Sod path)."""
+    """The widened paths measured like the benchmark: the benchmark's own
+    Euler set-up at 512^2 (6.6 M nodes: its 630 MB of stage arrays exceed
+    the 256 MB last-level cache that the 256^2 arrays fit in, so this is the
+    HBM-resident point), the paper's solid-body rotation (velocity field,
+    64^2 and 512^2, p = 3), its double Mach reflection set-up at the paper's
+    own resolution (open boundaries, 2400 x 600, p = 3, 23 M nodes) and a
+    large 1-D Euler problem (2^20 elements, p = 3, the Sod path)."""
     from paper_2004_08503_amd import workloads as W
     out = {}
+    big = W.euler_2d(n=512, p=4)
+    out["euler_2d_512x512_p4"] = mode_leg(big, big.prob, 20)
+    del big
     for n in (64, 512):
         sb = W.solid_body(n=n, p=3)
         out["solid_body_%dx%d_p3" % (n, n)] = mode_leg(sb, sb.prob, 30)
