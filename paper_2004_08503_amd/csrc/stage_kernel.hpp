@@ -407,19 +407,22 @@ __device__ inline bool surely_admissible(double t, const double* uL, const doubl
 //    next points are probes under hi at half the tolerance, doubling the
 //    distance after each inadmissible probe;
 //  - the search stops once the bracket is narrower than 1e-15 or than
-//    RTOL max|uL| / max|P| (the admissible end it returns then moves the
-//    state by less than RTOL of its largest component from any point of
-//    the bracket, the supremum included), and returns the admissible end.
-// RTOL: 1e-14 for a subcell face, whose t moves only that face's flux; 1e-16
-// for elementwise limiting, where one node's t is applied to every node of
-// the element, so that nodes of other scales (the small momentum of a gas
-// near rest next to a node of large energy) still land within rounding.
+//    RTOL max|uL| / max(|P|, pscale), and returns the admissible end.
+// The node's t scales more than this P: a subcell node's coefficient limits
+// every face of the node (through min(alpha_i, alpha_j)), so pscale is the
+// largest |P| over the node's faces, and the answer moves every face's
+// contribution to the state by less than RTOL of its largest component
+// from any point of the bracket, the supremum included.  RTOL: 1e-14 for
+// subcell faces; 1e-16 for elementwise limiting, where one node's t is
+// applied to every node of the element, so that nodes of other scales (the
+// small momentum of a gas near rest next to a node of large energy) still
+// land within rounding.
 template <int DIM, int GN, int RTOL_EXP>
 __device__ double entropy_root(const double* uL, const double* P, double U, bool tang, double kmin,
-                               const Phys& ph) {
+                               double pscale, const Phys& ph) {
   constexpr double RTOL = RTOL_EXP == 16 ? 1e-16 : 1e-14;
   static_assert(RTOL_EXP == 14 || RTOL_EXP == 16, "search tolerance 1e-14 or 1e-16");
-  double us = 0.0, ps = 0.0;
+  double us = 0.0, ps = pscale;
 #pragma unroll
   for (int c = 0; c < DIM + 2; ++c) {
     us = fmax(us, fabs(uL[c]));
@@ -980,7 +983,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
             } else {
               double tn = ea.rho > 0.0 && ea.dphi < 0.0 ? alpha - ea.phi / ea.dphi : alpha;
               tn = fmin(fmax(tn, 0.0), alpha);
-              alpha = entropy_root<DIM, gn_of(EQ), 16>(uL, d, tn, true, kmin, ph_of(A));
+              alpha = entropy_root<DIM, gn_of(EQ), 16>(uL, d, tn, true, kmin, 0.0, ph_of(A));
             }
           }
         }
@@ -1011,33 +1014,43 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         // starting from the exact value at alpha; most faces pass here
         // with integer powers only.  If u^L itself is not certain, the
         // search first checks it exactly (u^L off the set by rounding
-        // leaves the node at alpha = 0).  A face whose whole partial-state
-        // correction is below the search tolerance (max|P| <= 1e-14 max|u^L|)
-        // needs no search: any t in [0, alpha] moves the state by less than
-        // that, which is as close as a search would get (in a uniform
-        // region the antidiffusive fluxes are of rounding size and Phi at
-        // alpha is zero to rounding, which no test could settle).
+        // leaves the node at alpha = 0).  A node whose partial-state
+        // corrections are all below the search tolerance (max|P| over its
+        // faces <= 1e-14 max|u^L|) needs no search: any t in [0, alpha]
+        // moves its state by less than that, which is as close as a search
+        // would get (in a uniform region the antidiffusive fluxes are of
+        // rounding size and Phi at alpha is zero to rounding, which no test
+        // could settle).
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dtm;
         const double ikg = (ph_of(A).gamma - 1.0) / kmin;
-        double us = 0.0;
+        double us = 0.0, rmax = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) us = fmax(us, fabs(uL[c]));
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            rmax = fmax(rmax, fmax(fabs(lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]]),
+                                   fabs(lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]])));
         int act = 0;
+        if (g2 * rmax > 1e-14 * us) {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
+          for (int k = 0; k < DIM; ++k) {
 #pragma unroll
-          for (int sd = 0; sd < 2; ++sd) {
-            const int fidx = sd ? fr[k] : fl[k];
-            const double sg = sd ? 1.0 : -1.0;
-            double Pv[NC], ps = 0.0;
+            for (int sd = 0; sd < 2; ++sd) {
+              const int fidx = sd ? fr[k] : fl[k];
+              const double sg = sd ? 1.0 : -1.0;
+              double Pv[NC];
+              bool nz = false;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              Pv[c] = g2 * (sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx]);
-              ps = fmax(ps, fabs(Pv[c]));
+              for (int c = 0; c < NC; ++c) {
+                Pv[c] = g2 * (sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx]);
+                nz |= Pv[c] != 0.0;
+              }
+              if (nz && !surely_admissible<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ikg, ph_of(A)))
+                act |= 1 << (2 * k + sd);
             }
-            if (ps > 1e-14 * us && !surely_admissible<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ikg, ph_of(A)))
-              act |= 1 << (2 * k + sd);
           }
         }
         if (act) {
@@ -1076,19 +1089,29 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       const double cxn = dt * (lds[C::S_IW + na] * S.ihx);
       const double g2 = 2.0 * DIM * (DIM == 2 ? cxn * (lds[C::S_IW + nb] * S.ihy) : cxn);
       const int fidx = k == 0 ? nle * NF + nb * NFL + na + sd : nle * NF + na * NFL + nb + sd;
-      double ul[NC], Pv[NC];
+      double ul[NC], Pv[NC], rmax = 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         ul[c] = lds[C::C_UL + c * EPB * NP + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
       }
+      // the node's largest face correction scales the search tolerance
+      const int fx = nle * NF + nb * NFL + na, fy = nle * NF + na * NFL + nb;
+#pragma unroll
+      for (int kk = 0; kk < DIM; ++kk)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double* rb = lds + C::B_RB + (kk * NC + c) * EPB * NF + (kk == 0 ? fx : fy);
+          rmax = fmax(rmax, fmax(fabs(rb[0]), fabs(rb[1])));
+        }
       const double km = lds[C::C_KM + node];
       bool feasible = true;
       if (item & 1) {
         const double zero[NC] = {};
         feasible = admissible(phi_at<DIM, gn_of(EQ)>(0.0, ul, zero, km, ph_of(A)));
       }
-      const double t = feasible ? entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], false, km, ph_of(A))
+      const double t = feasible ? entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], false, km,
+                                                                   g2 * rmax, ph_of(A))
                                 : 0.0;
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
