@@ -87,3 +87,13 @@ def test_small_requests_pass_a_waiting_large_one():
     assert by[2].finished < by[0].finished           # ran beside the first large one
     for d, r in zip(done, reqs):
         assert torch.equal(d.result, alone(idp_dg, r)), r
+
+
+def test_request_over_the_budget_is_an_error():
+    """A request whose footprint exceeds the whole HBM budget can never be
+    admitted: the server says so instead of waiting for ever."""
+    idp_dg, serve = _mods()
+    reqs = W.request_stream(2, rate=1000.0, n_range=(32, 32), p_range=(3, 3), steps_range=(2, 2), seed=4)
+    budget = serve.footprint_bytes(reqs[0]) - 1
+    with pytest.raises(ValueError, match="more than the HBM budget"):
+        serve.Server(hbm_budget=budget).run(reqs)
