@@ -1,0 +1,76 @@
+"""The two configurations besides the benchmark's 256^2 p = 4 Euler case
+(which has its own full-size test), at their full sizes:
+
+- 2-D Burgers on a 128^2 mesh, p = 3 (262 144 nodes), 100 device-timestepped
+  SSP-RK3 steps at CFL 1/2 against the oracle stepped with the same time
+  steps, on every node, to 1e-9;
+- the batched mix of 64 independent Euler solves (32^2 to 256^2 elements,
+  p = 2..6, 49.6 M nodes), too large for the oracle: one batched step
+  must equal every solve's own plain step bitwise (a property that holds
+  at any size; the plain path is pinned to the oracle elsewhere), and the
+  three smallest solves of the mix are also compared with the oracle
+  directly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_08503_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08503_amd import idp_dg
+    return idp_dg
+
+
+def rel_err(a, b):
+    a = np.asarray(a).reshape(b.shape)
+    return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).max()
+
+
+def test_burgers_128_p3_full_run():
+    idp_dg = _gpu()
+    wl = W.burgers_2d()
+    prob = wl.prob
+    assert (prob.nx, prob.ny, prob.p, wl.steps) == (128, 128, 3, 100)
+    sv = idp_dg.Solver(prob)
+    u = torch.from_numpy(wl.u0.copy()).cuda()
+    ref = wl.u0.copy()
+    for _ in range(wl.steps):
+        dt_ref = wl.cfl * oracle.max_dt(prob, ref)
+        sv.step_cfl(u, wl.cfl)
+        assert sv.last_dt() == pytest.approx(dt_ref, rel=1e-12)
+        ref = oracle.step(prob, ref, sv.last_dt())
+    sv.close()
+    err = rel_err(u.cpu().numpy(), ref)
+    print("Burgers 128^2 p = 3, 100 steps: max relative error %.2e" % err)
+    assert err <= 1e-9, err
+
+
+def test_batched_64_solve_mix_one_step():
+    idp_dg = _gpu()
+    mix = W.batch_mix(64)
+    assert sum(w.prob.num_nodes for w in mix) > 40_000_000
+    solvers = [idp_dg.Solver(w.prob) for w in mix]
+    u_plain = [torch.from_numpy(w.u0).cuda() for w in mix]
+    u_batch = [t.clone() for t in u_plain]
+    batch = idp_dg.Batch(solvers)
+    batch.step_cfl(u_batch, 0.5)
+    for sv, u in zip(solvers, u_plain):
+        sv.step_cfl(u, 0.5)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(u_plain, u_batch))
+    dts = batch.last_dt()
+    for i in sorted(range(len(mix)), key=lambda i: mix[i].prob.num_nodes)[:3]:
+        prob = mix[i].prob
+        assert dts[i] == pytest.approx(0.5 * oracle.max_dt(prob, mix[i].u0), rel=1e-13)
+        ref = oracle.step(prob, mix[i].u0, dts[i])
+        err = rel_err(u_batch[i].cpu().numpy(), ref)
+        assert err <= 1e-12, (i, prob.nx, prob.p, err)
+    batch.close()
+    for sv in solvers:
+        sv.close()
