@@ -85,7 +85,8 @@ def batched_leg(steps, count=64):
     """The batched workload: `count` independent Euler solves (n in
     [32, 256], p in {2..6}, seeded quadrant data), stepped (a) one solve per
     launch, each through its own cached graph, and (b) all together, one
-    work-list launch per degree and stage, through one cached graph.  Per-round (one
+    work-list launch per degree and stage, through one cached graph, with
+    the tile shape of each degree chosen by the batch's tuner.  Per-round (one
     step of every solve) latencies from HIP events."""
     import torch
     from paper_2004_08503_amd import idp_dg, workloads as W
@@ -96,6 +97,7 @@ def batched_leg(steps, count=64):
     u_batch = [t.clone() for t in u_plain]
     nodes = sum(w.prob.num_nodes for w in mix)
     batch = idp_dg.Batch(solvers)
+    batch.tune(u_batch, 0.5, reps=3)   # tile shape per degree (states only read)
     n_items = batch.num_items
     stream = torch.cuda.current_stream()
 
@@ -266,6 +268,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests in the served stream (0 skips the serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--tune", action="store_true",
+                    help="run the tile-shape tuner on the benchmark solve first (default: the "
+                         "tuned default shape of the degree)")
     ap.add_argument("--serve-overload", type=float, default=1.3,
                     help="offered load of a second served run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -299,6 +304,9 @@ def main():
     dtd = torch.empty(1, dtype=torch.float64, device="cuda")
     cfl = wl.cfl
     stream = torch.cuda.current_stream()
+    if args.tune:   # tile-shape autotuning on the workload itself (u is only read)
+        sv.tune(u, cfl, reps=5)
+    shape, epb = sv.tile_shape, sv.tile_elems
 
     def step(ev=None):
         if ev is not None:
@@ -358,7 +366,8 @@ def main():
         "config": {"workload": "euler_2d_%dx%d_p%d" % (args.n, args.n, args.p),
                    "elements": prob.nx * prob.ny, "p": prob.p, "nodes": nn, "components": prob.nc,
                    "cfl": cfl, "limiter": "subcell convex (density Zalesak + entropy)",
-                   "path": "plain (one solve per launch)", "parallelism": "single GPU"},
+                   "path": "plain (one solve per launch)", "parallelism": "single GPU",
+                   "tile_shape": shape, "elements_per_workgroup": epb},
         "stage_ms_p50": float(np.percentile(stage_ms, 50)),
         "stage_ms_p99": float(np.percentile(stage_ms, 99)),
         "maxdt_ms_mean": float(ms[:, 0].mean()),
@@ -370,7 +379,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "stage_kernel<EULER75,2,4,5>",
+                     "kernel": "stage_kernel<EULER75,2,%d,%d>" % (prob.p, epb),
                      "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn),
                      # the kernel is bound by VALU issue, not HBM: at least 4 cycles
                      # per counted wave64 instruction over the SIMDs' cycles in

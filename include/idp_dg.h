@@ -237,6 +237,27 @@ int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev);
 int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
                     double* u_out, const double* dt_dev, double cfl, int stage);
 
+/* Tile-shape autotuning.  The stage and time-step kernels are compiled
+ * for IDP_DG_NUM_TILE_SHAPES shapes per degree (elements per workgroup);
+ * a new handle uses shape 0.  idp_dg_tune times `reps` (1..100)
+ * device-timestepped SSP-RK3 steps (as idp_dg_step_cfl, with cfl > 0) of
+ * the state u under each shape, twice in turns, and moves to a shape only
+ * if it is at least 2 % faster than the current one; the chosen shape is
+ * written to *shape (may be NULL).  u is only read: the steps write the handle's own stage
+ * buffers and a spare time-step slot, so idp_dg_last_dt is unchanged.
+ * Every shape gives the same results (the same arithmetic per node, only
+ * grouped differently into workgroups).  Synchronises the stream; a
+ * cached idp_dg_step_cfl graph is rebuilt on its next call if the shape
+ * changed.  idp_dg_tile_shape reports the current shape; idp_dg_set_tile_shape
+ * sets one (0 <= shape < IDP_DG_NUM_TILE_SHAPES).  Shape 0 is the faster of
+ * the two on 2-D Euler (256^2 for p = 1..4, 40^2..128^2 for p = 3..8). */
+#define IDP_DG_NUM_TILE_SHAPES 2
+int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape);
+int idp_dg_tile_shape(const idp_dg* h);
+/* Elements per workgroup of the current tile shape (-1 for NULL). */
+int idp_dg_tile_elems(const idp_dg* h);
+int idp_dg_set_tile_shape(idp_dg* h, int shape);
+
 /* Copy out and reset the diagnostics (synchronises the stream). */
 int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out);
 
@@ -282,6 +303,14 @@ int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt);
  * on the device; the launches replay from a HIP graph cached for the
  * pointer set and cfl.  Bitwise identical to idp_dg_step_cfl per solve. */
 int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl);
+
+/* Tile shape per degree for the batch: each degree's work-list kernels
+ * take the tile shape of its member with the most nodes after idp_dg_tune
+ * on that member's state u[i] (states only read; n device pointers as for
+ * the steps), with `reps` steps per shape.  Results are unchanged; the
+ * batch re-plans its work lists before its next step.  Synchronises the
+ * batch's stream. */
+int idp_dg_batch_tune(idp_dg_batch* b, double* const* u, double cfl, int reps);
 
 /* The n time steps used by the last idp_dg_batch_step_cfl (host array;
  * synchronises the stream). */

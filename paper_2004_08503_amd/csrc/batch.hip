@@ -53,7 +53,8 @@ struct idp_dg_batch {
   int n = 0;
   int nitems = 0;
   std::vector<BatchGroup> groups;
-  bool dirty = true;               // membership changed since the last upload
+  int shape[MAXP + 1] = {};        // tile shape of each degree's kernels
+  bool dirty = true;               // membership (or a tile shape) changed since the last upload
   // blob layout (offsets in bytes) for the current n / nitems
   size_t o_args = 0, o_dtargs = 0, o_isolve = 0, o_itile = 0, o_range = 0, o_partial = 0,
          o_dt = 0, blob_bytes = 0, stage_bytes = 0;
@@ -121,7 +122,8 @@ int plan(idp_dg_batch* b, std::vector<int>* isolve, std::vector<int>* itile, std
     gr.ofs = (int)isolve->size();
     for (int i = 0; i < b->n; ++i) {
       if (b->s[i]->d.p != p) continue;
-      if (batch_kernels(b->fam, p, &gr.k)) return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
+      if (batch_kernels(b->fam, p, b->shape[p], &gr.k))
+        return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
       const int nt = (b->s[i]->ne + gr.k.tile_elems - 1) / gr.k.tile_elems;
       (*range)[2 * i] = (int)isolve->size();
       for (int t = 0; t < nt; ++t) {
@@ -442,6 +444,32 @@ int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl) {
   if (rc) return rc;
   hipError_t e = run_step(b, 1);
   if (e != hipSuccess) return bhip(b, e, "batch step");
+  return 0;
+}
+
+int idp_dg_batch_tune(idp_dg_batch* b, double* const* u, double cfl, int reps) {
+  if (!b) return IDP_DG_EINVAL;
+  int rc = check_states(b, u);
+  if (rc) return rc;
+  for (int p = 1; p <= MAXP; ++p) {
+    int big = -1;
+    for (int i = 0; i < b->n; ++i)
+      if (b->s[i]->d.p == p && (big < 0 || b->s[i]->nn > b->s[big]->nn)) big = i;
+    if (big < 0) continue;
+    idp_dg* h = b->s[big];
+    const int keep = h->variant;
+    int shape = 0;
+    rc = idp_dg_tune(h, u[big], cfl, reps, &shape);
+    if (rc) return bfail(b, rc, std::string("tuning a member: ") + h->err);
+    rc = idp_dg_set_tile_shape(h, keep);   // the member's own shape is its own business
+    if (rc) return bfail(b, rc, h->err);
+    if (shape != b->shape[p]) {
+      b->shape[p] = shape;
+      b->dirty = true;
+    }
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bhip(b, e, "batch tune");
   return 0;
 }
 

@@ -139,10 +139,11 @@ struct RetiredGraph {
 #define IDP_DECLARE_LAUNCHERS(NAME)                                               \
   hipError_t launch_stage_##NAME(int p, int variant, const StageArgs& a,          \
                                  hipStream_t s);                                  \
-  hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s);       \
+  hipError_t launch_maxdt_##NAME(int p, int variant, const MaxDtArgs& a,          \
+                                 hipStream_t s);                                  \
   int tile_elems_##NAME(int p, int variant);                                      \
   int num_variants_##NAME(int p);                                                 \
-  int batch_kernels_##NAME(int p, BatchKernels* k);
+  int batch_kernels_##NAME(int p, int variant, BatchKernels* k);
 
 IDP_DECLARE_LAUNCHERS(adv1)
 IDP_DECLARE_LAUNCHERS(adv2)

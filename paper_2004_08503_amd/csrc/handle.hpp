@@ -54,7 +54,10 @@ idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
 // Every side of an open direction has its conditions.
 bool bnd_ready(const idp_dg* h);
-int batch_kernels(int fam, int p, idp::BatchKernels* k);
+// the work-list kernels of family fam, degree p, tile shape `variant`
+int batch_kernels(int fam, int p, int variant, idp::BatchKernels* k);
+// tile shapes compiled per degree
+constexpr int kNumVariants = 2;
 // Retire (graph, exec, event) and destroy retired graphs whose launches
 // have completed; with wait, block until all have completed.
 void retire_graph(std::vector<idp::RetiredGraph>* list, hipGraph_t* g, hipGraphExec_t* e, hipEvent_t* ev);

@@ -189,17 +189,17 @@ hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
 hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
   const int p = h->d.p;
   switch (family(h)) {
-    case 0: return launch_maxdt_adv1(p, a, s);
-    case 1: return launch_maxdt_adv2(p, a, s);
-    case 2: return launch_maxdt_burg1(p, a, s);
-    case 3: return launch_maxdt_burg2(p, a, s);
-    case 4: return launch_maxdt_euler1(p, a, s);
-    case 5: return launch_maxdt_euler2(p, a, s);
-    case 6: return launch_maxdt_euler53_1(p, a, s);
-    case 7: return launch_maxdt_euler53_2(p, a, s);
-    case 8: return launch_maxdt_euler75_1(p, a, s);
-    case 9: return launch_maxdt_euler75_2(p, a, s);
-    case 11: return launch_maxdt_advv2(p, a, s);
+    case 0: return launch_maxdt_adv1(p, h->variant, a, s);
+    case 1: return launch_maxdt_adv2(p, h->variant, a, s);
+    case 2: return launch_maxdt_burg1(p, h->variant, a, s);
+    case 3: return launch_maxdt_burg2(p, h->variant, a, s);
+    case 4: return launch_maxdt_euler1(p, h->variant, a, s);
+    case 5: return launch_maxdt_euler2(p, h->variant, a, s);
+    case 6: return launch_maxdt_euler53_1(p, h->variant, a, s);
+    case 7: return launch_maxdt_euler53_2(p, h->variant, a, s);
+    case 8: return launch_maxdt_euler75_1(p, h->variant, a, s);
+    case 9: return launch_maxdt_euler75_2(p, h->variant, a, s);
+    case 11: return launch_maxdt_advv2(p, h->variant, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -303,19 +303,19 @@ void reap_graphs(std::vector<RetiredGraph>* list, bool wait) {
   list->resize(keep);
 }
 
-int batch_kernels(int fam, int p, BatchKernels* k) {
+int batch_kernels(int fam, int p, int variant, BatchKernels* k) {
   switch (fam) {
-    case 0: return batch_kernels_adv1(p, k);
-    case 1: return batch_kernels_adv2(p, k);
-    case 2: return batch_kernels_burg1(p, k);
-    case 3: return batch_kernels_burg2(p, k);
-    case 4: return batch_kernels_euler1(p, k);
-    case 5: return batch_kernels_euler2(p, k);
-    case 6: return batch_kernels_euler53_1(p, k);
-    case 7: return batch_kernels_euler53_2(p, k);
-    case 8: return batch_kernels_euler75_1(p, k);
-    case 9: return batch_kernels_euler75_2(p, k);
-    case 11: return batch_kernels_advv2(p, k);
+    case 0: return batch_kernels_adv1(p, variant, k);
+    case 1: return batch_kernels_adv2(p, variant, k);
+    case 2: return batch_kernels_burg1(p, variant, k);
+    case 3: return batch_kernels_burg2(p, variant, k);
+    case 4: return batch_kernels_euler1(p, variant, k);
+    case 5: return batch_kernels_euler2(p, variant, k);
+    case 6: return batch_kernels_euler53_1(p, variant, k);
+    case 7: return batch_kernels_euler53_2(p, variant, k);
+    case 8: return batch_kernels_euler75_1(p, variant, k);
+    case 9: return batch_kernels_euler75_2(p, variant, k);
+    case 11: return batch_kernels_advv2(p, variant, k);
   }
   return -1;
 }
@@ -707,6 +707,84 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s, double* u_o
     return fail(h, IDP_DG_EINVAL, "u_out partially overlaps u_n");
   hipError_t e = launch_stage(h, make_stage_args(h, u_n, u_s, u_out, 0.0, dt_dev, cfl, stage), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "stage launch");
+  return 0;
+}
+
+static_assert(kNumVariants == IDP_DG_NUM_TILE_SHAPES, "tile shapes compiled per degree");
+
+int idp_dg_tile_shape(const idp_dg* h) { return h ? h->variant : -1; }
+
+int idp_dg_tile_elems(const idp_dg* h) { return h ? tile_elems(h) : -1; }
+
+int idp_dg_set_tile_shape(idp_dg* h, int shape) {
+  if (!h) return IDP_DG_EINVAL;
+  if (shape < 0 || shape >= kNumVariants) return fail(h, IDP_DG_EINVAL, "tile shape out of range");
+  if (shape != h->variant) {
+    h->variant = shape;
+    drop_graph(h);   // the cached step holds the other shape's kernels
+  }
+  return 0;
+}
+
+int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape) {
+  if (!h) return IDP_DG_EINVAL;
+  if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
+  if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, IDP_DG_EINVAL, "cfl must be finite and > 0");
+  if (reps < 1 || reps > 100) return fail(h, IDP_DG_EINVAL, "reps must be in 1..100");
+  const long long n = (long long)h->nc * h->nn;
+  if (overlaps(u, h->buf1, n) || overlaps(u, h->buf2, n))
+    return fail(h, IDP_DG_EINVAL, "u overlaps the handle's buffers");
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  const int keep = h->variant;
+  double* dtp = h->dtdev + 1;   // the spare slot: idp_dg_last_dt reads dtdev[0]
+  float best_ms = 0.0f;
+  int best = keep;
+  // one step of u into the handle's buffers: u -> buf1 -> buf2 -> buf1
+  auto step = [&]() -> hipError_t {
+    hipError_t r = enqueue_max_dt(h, u, dtp, h->stream);
+    if (r == hipSuccess) r = launch_stage(h, make_stage_args(h, nullptr, u, h->buf1, 0.0, dtp, cfl, 0), h->stream);
+    if (r == hipSuccess) r = launch_stage(h, make_stage_args(h, u, h->buf1, h->buf2, 0.0, dtp, cfl, 1), h->stream);
+    if (r == hipSuccess) r = launch_stage(h, make_stage_args(h, u, h->buf2, h->buf1, 0.0, dtp, cfl, 2), h->stream);
+    return r;
+  };
+  // the shapes take turns, twice, so that drifts of the clock or of the
+  // machine's load affect them alike; a shape replaces the current one only
+  // if it is at least 2 % faster
+  float total[kNumVariants] = {};
+  for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
+    h->variant = v;
+    e = step();   // warm-up (first launch of this shape's kernels)
+  }
+  for (int round = 0; round < 2 && e == hipSuccess; ++round) {
+    for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
+      h->variant = v;
+      e = hipEventRecord(ev[0], h->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = step();
+      if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      total[v] += ms;
+    }
+  }
+  if (ev[0]) hipEventDestroy(ev[0]);
+  if (ev[1]) hipEventDestroy(ev[1]);
+  h->variant = keep;
+  if (e != hipSuccess) return hip_fail(h, e, "tune");
+  best_ms = total[keep];
+  for (int v = 0; v < kNumVariants; ++v)
+    if (total[v] < 0.98f * best_ms) {
+      best_ms = total[v];
+      best = v;
+    }
+  if (best != keep) {
+    h->variant = best;
+    drop_graph(h);
+  }
+  if (shape) *shape = best;
   return 0;
 }
 

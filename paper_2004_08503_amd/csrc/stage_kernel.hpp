@@ -1286,12 +1286,15 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDt
 // ----------------------------------------------------------------------
 constexpr int epb_for(int dim, int p, int variant) {
   if (dim == 1) return (variant == 0 ? 64 : 128) / (p + 1);
-  constexpr int v0[9] = {0, 16, 7, 4, 5, 7, 5, 2, 3};
-  constexpr int v1[9] = {0, 32, 14, 8, 10, 3, 2, 4, 6};
+  // shape 0 (a new handle's): the faster of the two on 2-D Euler (256^2 for
+  // p = 1..4, 40^2..128^2 for p = 3..8), measured with both shapes taking
+  // turns on the same state; shape 1 the alternative for idp_dg_tune
+  constexpr int v0[9] = {0, 16, 14, 8, 5, 7, 5, 2, 3};
+  constexpr int v1[9] = {0, 32, 7, 4, 10, 3, 2, 4, 6};
   return variant == 0 ? v0[p] : v1[p];
 }
 
-#define IDP_NUM_VARIANTS 1
+#define IDP_NUM_VARIANTS 2
 
 // ----------------------------------------------------------------------
 // batched work-list kernels: one kernel per degree, its work list holding
@@ -1344,13 +1347,21 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel
   maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
 }
 
-template <int EQ, int DIM, int P>
-void batch_kernels_t(BatchKernels* k) {
-  constexpr int EPB = epb_for(DIM, P, 0);
+template <int EQ, int DIM, int P, int EPB>
+void batch_kernels_e(BatchKernels* k) {
   k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, EPB>);
   k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, EPB>);
   k->block = Cfg<EQ, DIM, P, EPB>::BS;
   k->tile_elems = EPB;
+}
+
+template <int EQ, int DIM, int P>
+void batch_kernels_t(int variant, BatchKernels* k) {
+#if IDP_NUM_VARIANTS > 1
+  if (variant == 1) return batch_kernels_e<EQ, DIM, P, epb_for(DIM, P, 1)>(k);
+#endif
+  (void)variant;
+  batch_kernels_e<EQ, DIM, P, epb_for(DIM, P, 0)>(k);
 }
 
 template <int EQ, int DIM, int P, int EPB>
@@ -1378,6 +1389,15 @@ hipError_t launch_stage_v(int variant, const StageArgs& a, hipStream_t s) {
   return launch_stage_t<EQ, DIM, P, epb_for(DIM, P, 0)>(a, s);
 }
 
+template <int EQ, int DIM, int P>
+hipError_t launch_maxdt_v(int variant, const MaxDtArgs& a, hipStream_t s) {
+#if IDP_NUM_VARIANTS > 1
+  if (variant == 1) return launch_maxdt_t<EQ, DIM, P, epb_for(DIM, P, 1)>(a, s);
+#endif
+  (void)variant;
+  return launch_maxdt_t<EQ, DIM, P, epb_for(DIM, P, 0)>(a, s);
+}
+
 #define IDP_DEFINE_LAUNCHERS(NAME, EQ, DIM)                                              \
   hipError_t launch_stage_##NAME(int p, int variant, const StageArgs& a, hipStream_t s) { \
     switch (p) {                                                                         \
@@ -1392,30 +1412,30 @@ hipError_t launch_stage_v(int variant, const StageArgs& a, hipStream_t s) {
     }                                                                                    \
     return hipErrorInvalidValue;                                                         \
   }                                                                                      \
-  hipError_t launch_maxdt_##NAME(int p, const MaxDtArgs& a, hipStream_t s) {             \
+  hipError_t launch_maxdt_##NAME(int p, int variant, const MaxDtArgs& a, hipStream_t s) { \
     switch (p) {                                                                         \
-      case 1: return launch_maxdt_t<EQ, DIM, 1, epb_for(DIM, 1, 0)>(a, s);               \
-      case 2: return launch_maxdt_t<EQ, DIM, 2, epb_for(DIM, 2, 0)>(a, s);               \
-      case 3: return launch_maxdt_t<EQ, DIM, 3, epb_for(DIM, 3, 0)>(a, s);               \
-      case 4: return launch_maxdt_t<EQ, DIM, 4, epb_for(DIM, 4, 0)>(a, s);               \
-      case 5: return launch_maxdt_t<EQ, DIM, 5, epb_for(DIM, 5, 0)>(a, s);               \
-      case 6: return launch_maxdt_t<EQ, DIM, 6, epb_for(DIM, 6, 0)>(a, s);               \
-      case 7: return launch_maxdt_t<EQ, DIM, 7, epb_for(DIM, 7, 0)>(a, s);               \
-      case 8: return launch_maxdt_t<EQ, DIM, 8, epb_for(DIM, 8, 0)>(a, s);               \
+      case 1: return launch_maxdt_v<EQ, DIM, 1>(variant, a, s);                          \
+      case 2: return launch_maxdt_v<EQ, DIM, 2>(variant, a, s);                          \
+      case 3: return launch_maxdt_v<EQ, DIM, 3>(variant, a, s);                          \
+      case 4: return launch_maxdt_v<EQ, DIM, 4>(variant, a, s);                          \
+      case 5: return launch_maxdt_v<EQ, DIM, 5>(variant, a, s);                          \
+      case 6: return launch_maxdt_v<EQ, DIM, 6>(variant, a, s);                          \
+      case 7: return launch_maxdt_v<EQ, DIM, 7>(variant, a, s);                          \
+      case 8: return launch_maxdt_v<EQ, DIM, 8>(variant, a, s);                          \
     }                                                                                    \
     return hipErrorInvalidValue;                                                         \
   }                                                                                      \
   int tile_elems_##NAME(int p, int variant) { return epb_for(DIM, p, variant); }         \
-  int batch_kernels_##NAME(int p, BatchKernels* k) {                                     \
+  int batch_kernels_##NAME(int p, int variant, BatchKernels* k) {                        \
     switch (p) {                                                                         \
-      case 1: batch_kernels_t<EQ, DIM, 1>(k); return 0;                                  \
-      case 2: batch_kernels_t<EQ, DIM, 2>(k); return 0;                                  \
-      case 3: batch_kernels_t<EQ, DIM, 3>(k); return 0;                                  \
-      case 4: batch_kernels_t<EQ, DIM, 4>(k); return 0;                                  \
-      case 5: batch_kernels_t<EQ, DIM, 5>(k); return 0;                                  \
-      case 6: batch_kernels_t<EQ, DIM, 6>(k); return 0;                                  \
-      case 7: batch_kernels_t<EQ, DIM, 7>(k); return 0;                                  \
-      case 8: batch_kernels_t<EQ, DIM, 8>(k); return 0;                                  \
+      case 1: batch_kernels_t<EQ, DIM, 1>(variant, k); return 0;                         \
+      case 2: batch_kernels_t<EQ, DIM, 2>(variant, k); return 0;                         \
+      case 3: batch_kernels_t<EQ, DIM, 3>(variant, k); return 0;                         \
+      case 4: batch_kernels_t<EQ, DIM, 4>(variant, k); return 0;                         \
+      case 5: batch_kernels_t<EQ, DIM, 5>(variant, k); return 0;                         \
+      case 6: batch_kernels_t<EQ, DIM, 6>(variant, k); return 0;                         \
+      case 7: batch_kernels_t<EQ, DIM, 7>(variant, k); return 0;                         \
+      case 8: batch_kernels_t<EQ, DIM, 8>(variant, k); return 0;                         \
     }                                                                                    \
     return -1;                                                                           \
   }                                                                                      \

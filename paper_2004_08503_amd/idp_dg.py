@@ -58,6 +58,11 @@ def _declare(lib):
         "idp_dg_max_dt": (ctypes.c_int, [H, _VP, ctypes.POINTER(ctypes.c_double)]),
         "idp_dg_max_dt_async": (ctypes.c_int, [H, _VP, _VP]),
         "idp_dg_stage_dt": (ctypes.c_int, [H, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
+        "idp_dg_tune": (ctypes.c_int, [H, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+        "idp_dg_tile_shape": (ctypes.c_int, [H]),
+        "idp_dg_tile_elems": (ctypes.c_int, [H]),
+        "idp_dg_set_tile_shape": (ctypes.c_int, [H, ctypes.c_int]),
+        "idp_dg_batch_tune": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
         "idp_dg_set_boundary": (ctypes.c_int, [H, ctypes.c_int, _VP, _VP]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
@@ -277,6 +282,27 @@ class Solver:
                                         self._ptr(u_out, "u_out"), self._scalar(dt_dev),
                                         float(cfl), int(stage)))
 
+
+    NUM_TILE_SHAPES = 2
+
+    def tune(self, u, cfl=0.5, reps=5):
+        """idp_dg_tune: time `reps` device-timestepped steps of u (only read)
+        under each tile shape, keep the fastest and return it."""
+        out = ctypes.c_int(-1)
+        self._check(lib.idp_dg_tune(self._h, self._ptr(u, "u"), float(cfl), int(reps), ctypes.byref(out)))
+        return out.value
+
+    @property
+    def tile_shape(self):
+        return lib.idp_dg_tile_shape(self._h)
+
+    @property
+    def tile_elems(self):
+        """Elements per workgroup of the current tile shape."""
+        return lib.idp_dg_tile_elems(self._h)
+
+    def set_tile_shape(self, shape):
+        self._check(lib.idp_dg_set_tile_shape(self._h, int(shape)))
     def _scalar(self, t):
         torch = _torch()
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
@@ -355,6 +381,11 @@ class Batch:
 
     def step_cfl_prepared(self, ptrs, cfl):
         self._check(lib.idp_dg_batch_step_cfl(self._b, ptrs, float(cfl)))
+
+    def tune(self, us, cfl=0.5, reps=5):
+        """idp_dg_batch_tune: per degree, the tile shape idp_dg_tune picks on
+        that degree's largest member (states only read)."""
+        self._check(lib.idp_dg_batch_tune(self._b, self._ptrs(us), float(cfl), int(reps)))
 
     def last_dt(self):
         d = (ctypes.c_double * self.n)()

@@ -1,0 +1,100 @@
+"""Tile-shape autotuning: every compiled tile shape (elements per
+workgroup) gives bitwise the same results, the tuner only reads the state
+it times, and a tuned handle or batch steps exactly as before."""
+import numpy as np
+import pytest
+
+from paper_2004_08503_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_08503_amd import idp_dg
+    return idp_dg
+
+
+CASES = [("euler2d", W.Problem(dim=2, nx=11, ny=7, p=p, eq=W.EULER)) for p in range(1, 9)] + [
+    ("euler1d", W.Problem(dim=1, nx=37, ny=1, p=3, eq=W.EULER)),
+    ("euler53", W.Problem(dim=2, nx=9, ny=5, p=4, eq=W.EULER, gamma=5.0 / 3.0)),
+    ("euler13", W.Problem(dim=2, nx=9, ny=5, p=3, eq=W.EULER, gamma=1.3)),
+    ("burgers", W.Problem(dim=2, nx=13, ny=6, p=5, eq=W.BURGERS)),
+    ("advection", W.Problem(dim=1, nx=40, ny=1, p=2, eq=W.ADVECTION)),
+]
+
+
+def initial(prob, seed):
+    rng = np.random.default_rng(seed)
+    if prob.eq == W.EULER:
+        return W.euler_quadrants(prob, rng)
+    return rng.uniform(-1.0, 1.0, (1, prob.num_nodes))
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=["%s-p%d" % (n, p.p) for n, p in CASES])
+def test_every_tile_shape_gives_the_same_steps(name, prob):
+    idp_dg = _gpu()
+    u0 = initial(prob, prob.p)
+    outs, dts = [], []
+    for shape in range(idp_dg.Solver.NUM_TILE_SHAPES):
+        sv = idp_dg.Solver(prob)
+        sv.set_tile_shape(shape)
+        assert sv.tile_shape == shape
+        u = torch.from_numpy(u0.copy()).cuda()
+        for _ in range(3):
+            sv.step_cfl(u, 0.5)
+        dts.append(sv.last_dt())
+        outs.append(u.cpu())
+        sv.close()
+    for o, d in zip(outs[1:], dts[1:]):
+        assert torch.equal(o, outs[0]) and d == dts[0]
+
+
+def test_tune_reads_only_and_keeps_results():
+    idp_dg = _gpu()
+    wl = W.euler_2d(n=48, p=4)
+    ref = idp_dg.Solver(wl.prob)
+    u_ref = torch.from_numpy(wl.u0.copy()).cuda()
+    ref.step_cfl(u_ref, 0.5)
+    dt_ref = ref.last_dt()
+    sv = idp_dg.Solver(wl.prob)
+    u = torch.from_numpy(wl.u0.copy()).cuda()
+    sv.step_cfl(u, 0.5)                  # a cached step graph and a last dt
+    before = u.clone()
+    shape = sv.tune(u, 0.5, reps=3)
+    assert 0 <= shape < idp_dg.Solver.NUM_TILE_SHAPES and sv.tile_shape == shape
+    assert torch.equal(u, before)        # the timed steps did not touch u
+    assert sv.last_dt() == dt_ref        # nor the dt of the last step
+    sv.step_cfl(u, 0.5)
+    ref.step_cfl(u_ref, 0.5)
+    assert torch.equal(u, u_ref)
+    with pytest.raises(idp_dg.IdpError):
+        sv.tune(u, 0.5, reps=0)
+    with pytest.raises(idp_dg.IdpError):
+        sv.set_tile_shape(idp_dg.Solver.NUM_TILE_SHAPES)
+    sv.close()
+    ref.close()
+
+
+def test_batch_tune_keeps_bitwise_equality_with_plain():
+    idp_dg = _gpu()
+    mix = [W.euler_2d(n=n, p=p, seed=s) for n, p, s in ((12, 2, 1), (20, 2, 2), (9, 5, 3), (16, 4, 4))]
+    solvers = [idp_dg.Solver(w.prob) for w in mix]
+    ub = [torch.from_numpy(w.u0.copy()).cuda() for w in mix]
+    up = [t.clone() for t in ub]
+    b = idp_dg.Batch(solvers)
+    b.step_cfl(ub, 0.5)
+    before = [t.clone() for t in ub]
+    b.tune(ub, 0.5, reps=2)
+    assert all(torch.equal(a, c) for a, c in zip(ub, before))
+    for _ in range(2):
+        b.step_cfl(ub, 0.5)
+    for sv, u in zip(solvers, up):
+        for _ in range(3):
+            sv.step_cfl(u, 0.5)
+    assert all(torch.equal(a, c) for a, c in zip(ub, up))
+    b.close()
+    for sv in solvers:
+        sv.close()
