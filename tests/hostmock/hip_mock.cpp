@@ -129,6 +129,13 @@ hipError_t hipEventQuery(void* e) {
   if (!ev->s->q.empty()) { Op o = ev->s->q.front(); ev->s->q.pop_front(); complete(ev->s, o); }
   return ev->s->done >= ev->seq ? hipSuccess : hipErrorNotReady; }
 hipError_t hipEventDestroy(void* e) { Event* ev = E(e); ev->live = false; return hipSuccess; }
+hipError_t hipEventCreate(void** e) { return hipEventCreateWithFlags(e, 0); }
+// both events must have run: the elapsed time is a stand-in (no clock)
+hipError_t hipEventElapsedTime(float* ms, void* a, void* b) {
+  Event* ea = E(a); Event* eb = E(b);
+  if (!ea->recorded || !eb->recorded || ea->s->done < ea->seq || eb->s->done < eb->seq)
+    FAIL("elapsed time of events that have not completed");
+  *ms = (float)(eb->seq - ea->seq); return hipSuccess; }
 hipError_t hipGraphCreate(void** g, unsigned) { Graph* gr = new Graph; g_graphs.insert(gr); *g = gr; return hipSuccess; }
 static Graph* G(void* g) { Graph* gr = (Graph*)g; if (!g_graphs.count(gr) || !gr->live) FAIL("use of a destroyed or unknown graph %p", g); return gr; }
 // hipKernelNodeParams layout: dim3 blockDim; void** extra; void* func; dim3 gridDim; void** kernelParams; unsigned sharedMemBytes

@@ -130,6 +130,12 @@ int main(int argc, char** argv) {
     const double cfl = (it / 7) % 2 ? 0.5 : 0.4;
     if (idp_dg_step_cfl(h, u[(it / 3) % 2], cfl)) { fprintf(stderr, "step_cfl: %s\n", idp_dg_last_error(h)); return 1; }
     if (it % 50 == 49 && idp_dg_step(h, u[0], 1e-4)) { fprintf(stderr, "step: %s\n", idp_dg_last_error(h)); return 1; }
+    // the tile-shape tuner between queued steps: it may retire the cached graph
+    if (it % 40 == 20) {
+      int shape = -1;
+      if (idp_dg_tune(h, u[(it / 3) % 2], cfl, 2, &shape)) { fprintf(stderr, "tune: %s\n", idp_dg_last_error(h)); return 1; }
+      if (idp_dg_set_tile_shape(h, (it / 40) % 2)) { fprintf(stderr, "shape: %s\n", idp_dg_last_error(h)); return 1; }
+    }
   }
   idp_dg_destroy(h);
   hipFree(u[0]);
