@@ -250,7 +250,8 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
  * cached idp_dg_step_cfl graph is rebuilt on its next call if the shape
  * changed.  idp_dg_tile_shape reports the current shape; idp_dg_set_tile_shape
  * sets one (0 <= shape < IDP_DG_NUM_TILE_SHAPES).  Shape 0 is the faster of
- * the two on 2-D Euler (256^2 for p = 1..4, 40^2..128^2 for p = 3..8). */
+ * the two on 2-D Euler (256^2 for p = 1..4, 40^2..128^2 for p = 3..8) and
+ * on 1-D Euler (2^20 elements, p = 1 and 3). */
 #define IDP_DG_NUM_TILE_SHAPES 2
 int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape);
 int idp_dg_tile_shape(const idp_dg* h);

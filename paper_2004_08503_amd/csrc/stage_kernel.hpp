@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDt
 // elements per workgroup: variant 0 fills 64-lane multiples best
 // ----------------------------------------------------------------------
 constexpr int epb_for(int dim, int p, int variant) {
-  if (dim == 1) return (variant == 0 ? 64 : 128) / (p + 1);
+  if (dim == 1) return (variant == 0 ? 128 : 256) / (p + 1);
   // shape 0 (a new handle's): the faster of the two on 2-D Euler (256^2 for
   // p = 1..4, 40^2..128^2 for p = 3..8), measured with both shapes taking
   // turns on the same state; shape 1 the alternative for idp_dg_tune
