@@ -451,6 +451,11 @@ int idp_dg_batch_tune(idp_dg_batch* b, double* const* u, double cfl, int reps) {
   if (!b) return IDP_DG_EINVAL;
   int rc = check_states(b, u);
   if (rc) return rc;
+  // a member's timed steps write its stage buffers, which queued batch steps
+  // also use: let the batch's work finish first (a member may run on
+  // another stream)
+  hipError_t e0 = hipStreamSynchronize(b->stream);
+  if (e0 != hipSuccess) return bhip(b, e0, "batch tune");
   for (int p = 1; p <= MAXP; ++p) {
     int big = -1;
     for (int i = 0; i < b->n; ++i)
