@@ -9,7 +9,19 @@ kernel's average duration for the roofline and the p50/p99 stage latency.
 
 value = DOF (node) updates per second over the timed region:
 3 * Nn * K / elapsed.  The rocprofv3 counter figures under profiles/ supply
-the measured HBM traffic when they match the current kernel source.
+the measured HBM traffic when they match the current kernel source.  The
+benchmark solve uses its degree's default tile shape (config.tile_shape and
+config.elements_per_workgroup; --tune runs the tile-shape tuner first).
+
+Further legs on the same JSON line:
+- the other limiter modes on the same workload (modes);
+- the widened workloads (workloads): the same set-up at 512^2, the
+  solid-body rotation, the double Mach reflection set-up, 1-D Euler;
+- 64 uneven Euler solves, batched against one solve per launch (batched;
+  the batch tunes its tile shapes per degree);
+- a served request stream against FIFO through the plain path, at offered
+  load 0.8 (serving) and 1.3 (serving_overload);
+- the oracle on the host (cpu_baseline).
 """
 import argparse
 import hashlib
