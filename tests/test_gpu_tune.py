@@ -23,7 +23,18 @@ CASES = [("euler2d", W.Problem(dim=2, nx=11, ny=7, p=p, eq=W.EULER)) for p in ra
     ("euler13", W.Problem(dim=2, nx=9, ny=5, p=3, eq=W.EULER, gamma=1.3)),
     ("burgers", W.Problem(dim=2, nx=13, ny=6, p=5, eq=W.BURGERS)),
     ("advection", W.Problem(dim=1, nx=40, ny=1, p=2, eq=W.ADVECTION)),
+    ("field", W.solid_body(n=12, p=3).prob),
+    ("open", None),
 ]
+
+
+def open_box():
+    """2-D Euler with prescribed inflow, outflow and slip walls."""
+    prob = W.Problem(dim=2, nx=11, ny=6, p=3, eq=W.EULER, bc=(1, 1))
+    u0 = initial(prob, 7)
+    inflow = u0[:, 0]
+    return prob.replace(bnd=W.uniform_boundary(prob, [W.BC_STATE, W.BC_OUTFLOW, W.BC_SLIP, W.BC_SLIP],
+                                               [inflow, None, None, None]))
 
 
 def initial(prob, seed):
@@ -33,10 +44,12 @@ def initial(prob, seed):
     return rng.uniform(-1.0, 1.0, (1, prob.num_nodes))
 
 
-@pytest.mark.parametrize("name,prob", CASES, ids=["%s-p%d" % (n, p.p) for n, p in CASES])
+@pytest.mark.parametrize("name,prob", CASES, ids=["%s-p%d" % (n, p.p if p else 3) for n, p in CASES])
 def test_every_tile_shape_gives_the_same_steps(name, prob):
     idp_dg = _gpu()
-    u0 = initial(prob, prob.p)
+    if prob is None:
+        prob = open_box()
+    u0 = W.solid_body(n=12, p=3).u0 if name == "field" else initial(prob, prob.p)
     outs, dts = [], []
     for shape in range(idp_dg.Solver.NUM_TILE_SHAPES):
         sv = idp_dg.Solver(prob)
