@@ -1290,7 +1290,7 @@ constexpr int epb_for(int dim, int p, int variant) {
   // p = 1..4, 40^2..128^2 for p = 3..8), measured with both shapes taking
   // turns on the same state; shape 1 the alternative for idp_dg_tune
   constexpr int v0[9] = {0, 16, 14, 8, 5, 7, 5, 2, 3};
-  constexpr int v1[9] = {0, 32, 7, 4, 10, 3, 2, 4, 6};
+  constexpr int v1[9] = {0, 32, 7, 16, 10, 3, 2, 4, 6};
   return variant == 0 ? v0[p] : v1[p];
 }
 
