@@ -239,19 +239,26 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
 
 /* Tile-shape autotuning.  The stage and time-step kernels are compiled
  * for IDP_DG_NUM_TILE_SHAPES shapes per degree (elements per workgroup);
- * a new handle uses shape 0.  idp_dg_tune times `reps` (1..100)
- * device-timestepped SSP-RK3 steps (as idp_dg_step_cfl, with cfl > 0) of
- * the state u under each shape, twice in turns, and moves to a shape only
- * if it is at least 2 % faster than the current one; the chosen shape is
- * written to *shape (may be NULL).  u is only read: the steps write the handle's own stage
- * buffers and a spare time-step slot, so idp_dg_last_dt is unchanged.
- * Every shape gives the same results (the same arithmetic per node, only
- * grouped differently into workgroups).  Synchronises the stream; a
- * cached idp_dg_step_cfl graph is rebuilt on its next call if the shape
- * changed.  idp_dg_tile_shape reports the current shape; idp_dg_set_tile_shape
- * sets one (0 <= shape < IDP_DG_NUM_TILE_SHAPES).  Shape 0 is the faster of
- * the two on 2-D Euler (256^2 for p = 1..4, 40^2..128^2 for p = 3..8) and
- * on 1-D Euler (2^20 elements, p = 1 and 3). */
+ * a new handle uses shape 0, the faster of the two on 2-D Euler (256^2 for
+ * p = 1..4, 40^2..128^2 for p = 3..8) and on 1-D Euler (2^20 elements,
+ * p = 1 and 3).  Every shape gives bitwise the same results: the same
+ * arithmetic per node, only grouped differently into workgroups.
+ *
+ * idp_dg_tune times `reps` (1..100) device-timestepped SSP-RK3 steps (as
+ * idp_dg_step_cfl; cfl > 0) of the device state u under each shape, the
+ * shapes taking turns twice, and moves to another shape only if it is at
+ * least 2 % faster than the current one; the shape kept is written to
+ * *shape (may be NULL).  u is only read: the timed steps write the
+ * handle's own stage buffers and a spare time-step slot (idp_dg_last_dt is
+ * unchanged).  Enqueued on the handle's stream after its earlier work;
+ * synchronises that stream.  A cached idp_dg_step_cfl graph is rebuilt on
+ * its next call if the shape changed.  Returns 0, IDP_DG_EINVAL (NULL u,
+ * bad cfl or reps, u overlapping the handle's buffers, an open side
+ * without conditions) or IDP_DG_EHIP.
+ *
+ * idp_dg_tile_shape: the current shape (-1 for NULL).
+ * idp_dg_set_tile_shape: 0 <= shape < IDP_DG_NUM_TILE_SHAPES, else
+ * IDP_DG_EINVAL. */
 #define IDP_DG_NUM_TILE_SHAPES 2
 int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape);
 int idp_dg_tile_shape(const idp_dg* h);
