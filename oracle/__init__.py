@@ -34,7 +34,7 @@ SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 def build():
     """Compile the oracle with gcc (plain FP64, no FMA contraction)."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH, _SRC, "-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH, _SRC, "-lm"]
     subprocess.check_call(cmd)
     global _lib
     _lib = None
@@ -72,6 +72,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     D = ctypes.POINTER(_Desc)
     sig = {
+        "idp_ref_set_threads": (ctypes.c_int, [ctypes.c_int]),
         "idp_ref_check": (ctypes.c_int, [D]),
         "idp_ref_num_nodes": (ctypes.c_long, [D]),
         "idp_ref_num_comp": (ctypes.c_int, [D]),
@@ -154,6 +155,12 @@ def _ptr(a):
 
 def _arr(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n):
+    """Threads of the oracle's node and element loops (results do not
+    depend on the number); returns the number in use."""
+    return _load().idp_ref_set_threads(int(n))
 
 
 def check(prob):

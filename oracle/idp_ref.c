@@ -31,6 +31,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXP 8
 #define MAXN (MAXP + 1)
@@ -50,6 +53,16 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 
 static int field_check(const idp_ref_desc* d);
+
+int idp_ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 int idp_ref_check(const idp_ref_desc* d) {
   if (!d) return -1;
@@ -731,6 +744,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
 #define IDX3(k, c, i) (((long)(k) * nc + (c)) * nn + (i))
 
   /* O1: nodal fluxes */
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < nn; ++i) {
     double ui[MAXC], Fi[2 * MAXC];
     get_state(R, u, i, ui);
@@ -739,7 +753,9 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
       for (int c = 0; c < nc; ++c) F[IDX3(k, c, i)] = Fi[k * nc + c];
   }
 
-  /* O3/O4: per-direction residuals along every line of every element */
+  /* O3/O4: per-direction residuals along every line of every element
+   * (each line writes only its own nodes' entries) */
+#pragma omp parallel for schedule(static)
   for (long ey = 0; ey < R->d.ny; ++ey) {
     for (long ex = 0; ex < R->d.nx; ++ex) {
       for (int k = 0; k < dim; ++k) {
@@ -848,6 +864,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   }
 
   /* O5: low-order and high-order provisional states */
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < nn; ++i) {
     double m = node_mass(R, i);
     for (int c = 0; c < nc; ++c) {
@@ -864,6 +881,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   /* O7: local bounds from the bar states (eq. bar-states, Sec. 4.1.1) and,
    * for Euler, the entropy bound s_min = min over the stencil (Sec. 4.3).
    * Reading: the stencil N(i) includes i itself. */
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < nn; ++i) {
     double ui[MAXC], Fi[2 * MAXC];
     get_state(R, u, i, ui);
@@ -926,6 +944,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
    * over its nodes, u = u^L + alpha_K (u^H - u^L). */
   if (R->d.limiter == IDP_REF_ELEMENTWISE) {
     const long np = nn / R->ne;
+#pragma omp parallel for schedule(dynamic, 256)
     for (long i = 0; i < nn; ++i) {
       double m = node_mass(R, i);
       double ul = uL[(long)lim * nn + i];
@@ -948,11 +967,13 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
       }
       al[i] = a;
     }
+#pragma omp parallel for schedule(static)
     for (long e = 0; e < R->ne; ++e) {
       double aK = 1.0;
       for (long q = 0; q < np; ++q) aK = fmin(aK, al[e * np + q]);
       for (long q = 0; q < np; ++q) al[e * np + q] = aK;
     }
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < nn; ++i)
       for (int c = 0; c < nc; ++c) {
         long ic = (long)c * nn + i;
@@ -961,7 +982,9 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
   }
 
   /* O8: nodal Zalesak coefficients on the limited component */
-  for (long i = 0; i < nn && R->d.limiter != IDP_REF_ELEMENTWISE; ++i) {
+  const long nz_ = R->d.limiter == IDP_REF_ELEMENTWISE ? 0 : nn;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < nz_; ++i) {
     double m = node_mass(R, i);
     double Pp = 0.0, Pm = 0.0;
     for (int k = 0; k < dim; ++k) {
@@ -993,6 +1016,7 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
    * uL + t 2d dt/m (+-rbar) must stay admissible, t <= alpha_z.  Reading:
    * the search runs on [0, alpha_z] and also keeps rho > 0. */
   if (euler && R->d.limiter != IDP_REF_ELEMENTWISE) {
+#pragma omp parallel for schedule(dynamic, 256)
     for (long i = 0; i < nn; ++i) {
       double m = node_mass(R, i);
       double uli[MAXC];
@@ -1031,7 +1055,8 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
    * nodal coefficients and the flux-corrected update (eq. subcell-fct /
    * convex-fct).  Limiter modes TARGET and LOW return the unlimited
    * high-order and the low-order updates. */
-  for (long i = 0; i < nn && R->d.limiter != IDP_REF_ELEMENTWISE; ++i) {
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < nz_; ++i) {
     if (R->d.limiter == IDP_REF_TARGET) {
       for (int c = 0; c < nc; ++c) out[(long)c * nn + i] = uH[(long)c * nn + i];
       continue;
@@ -1104,6 +1129,7 @@ int idp_ref_stage(const idp_ref_desc* d, const double* u_n, const double* u_s,
   if (stage == 0) {
     memcpy(out, fe, sizeof(double) * n);
   } else {
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) out[i] = A[stage] * u_n[i] + B[stage] * fe[i];
   }
   free(fe);
@@ -1128,6 +1154,7 @@ int idp_ref_max_dt(const idp_ref_desc* dsc, const double* u, double* dt) {
   ref_t Rs, *R = &Rs;
   if (setup(R, dsc) || !u || !dt) return -1;
   double best = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : best)
   for (long i = 0; i < R->nn; ++i) {
     double sum = 0.0;
     for (int k = 0; k < R->d.dim; ++k) {

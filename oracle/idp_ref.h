@@ -9,8 +9,11 @@
  * the smoke check and the CPU-baseline leg of the benchmark may load it.
  * It shares no code, header, table or helper with the GPU library.
  *
- * Every routine is single-threaded, allocates with malloc, works on host
- * pointers and is compiled with -ffp-contract=off (no fused multiply-add).
+ * Every routine allocates with malloc, works on host pointers and is
+ * compiled with -ffp-contract=off (no fused multiply-add).  The loops over
+ * nodes and element rows may run on several OpenMP threads
+ * (idp_ref_set_threads); every node's arithmetic is the same on any number
+ * of threads, so results do not depend on it.
  *
  * Mesh: Cartesian box [0,lx) x [0,ly) split into nx x ny elements (ny = 1
  * in 1-D), periodic in each direction unless that direction is open.  Each element carries the (p+1)^d tensor Gauss-Lobatto
@@ -91,6 +94,11 @@ typedef struct {
   double *uL, *uH, *rH, *rL, *rbar;
   double *umin, *umax, *kmin, *alpha_z, *alpha;
 } idp_ref_trace;
+
+/* Threads of the node and element loops (n >= 1; OpenMP's default when
+ * never called).  Returns the number in use after the call (1 when built
+ * without OpenMP). */
+int idp_ref_set_threads(int n);
 
 /* Returns 0 on success, -1 on a bad argument. */
 int idp_ref_check(const idp_ref_desc* d);
