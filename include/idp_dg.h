@@ -210,6 +210,29 @@ int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s,
 /* One SSP-RK3 step in place: three stages through the handle's buffers. */
 int idp_dg_step(idp_dg* h, double* u, double dt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of idp_dg_step without a handle.  Nothing is allocated, here or earlier.
+ * The two stage buffers are one static device array of the library
+ * (2 * IDP_DG_NOALLOC_MAX_DOUBLES doubles = 64 MiB), present on every GPU
+ * the library runs on until the process ends; the first call on a device
+ * only looks up that array's address there.
+ *   - desc: as for idp_dg_create; periodic directions only (bc = 0) and
+ *     any equation but IDP_DG_ADVECTION_FIELD, else IDP_DG_EINVAL;
+ *     nc * Nn <= IDP_DG_NOALLOC_MAX_DOUBLES, else IDP_DG_EINVAL with a
+ *     message giving both sizes;
+ *   - u: device state (layout as for idp_dg_stage), updated in place by
+ *     dt >= 0 on hip_stream (a hipStream_t, 0 for the null stream) of the
+ *     current device; asynchronous;
+ *   - the result is bitwise that of idp_dg_step on a handle of desc (the
+ *     same kernels); no diagnostics are counted;
+ *   - every call on one GPU shares the array: calls whose work may overlap
+ *     on one GPU (other streams, other host threads) race and must be
+ *     ordered by the caller.
+ * Errors: idp_dg_last_error(NULL) gives the message. */
+#define IDP_DG_NOALLOC_MAX_DOUBLES (4LL << 20)
+int idp_dg_step_noalloc(const idp_dg_desc* desc, double* u, double dt, void* hip_stream);
+
 /* One SSP-RK3 step in place with dt = cfl * idp_dg_max_dt(u) computed on
  * the device from u at the start of the step (eq. cfl-low; the paper runs
  * cfl = 1/2).  Nothing is copied to the host: the four kernels replay from

@@ -52,6 +52,9 @@ idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double*
                                double dt, const double* dt_dev, double dt_scale, int stage);
 idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
+bool desc_ok(const idp_dg_desc* d, std::string* why);
+void init_host(idp_dg* h, const idp_dg_desc* desc, void* hip_stream);
+hipError_t launch_stage(const idp_dg* h, const idp::StageArgs& a, hipStream_t s);
 // Every side of an open direction has its conditions.
 bool bnd_ready(const idp_dg* h);
 // the work-list kernels of family fam, degree p, tile shape `variant`

@@ -43,7 +43,7 @@ void legendre_pair(int n, double x, double* pn, double* pnm1) {
 
 void gl_tables(int p, double* xi01, double* w01, double* D) {
   const int n = p + 1;
-  std::vector<double> x(n);
+  double x[MAXP + 1];
   x[0] = -1.0;
   x[p] = 1.0;
   for (int k = 1; k < p; ++k) {
@@ -60,7 +60,7 @@ void gl_tables(int p, double* xi01, double* w01, double* D) {
     }
     x[k] = t;
   }
-  std::vector<double> w(n), bw(n);
+  double w[MAXP + 1], bw[MAXP + 1];
   for (int k = 0; k < n; ++k) {
     double pk, pkm1;
     legendre_pair(p, x[k], &pk, &pkm1);
@@ -112,7 +112,7 @@ void modal_tables(int p, const double* xi01, const double* w01, Tables* T) {
   const int n = p + 1;
   for (int k = 0; k < n; ++k) {
     double g = 0.0;
-    std::vector<double> pk(n);
+    double pk[MAXP + 1];
     for (int a = 0; a < n; ++a) {
       double pn, pm;
       legendre_pair(k, 2.0 * xi01[a] - 1.0, &pn, &pm);
@@ -472,19 +472,18 @@ hipError_t upload_field(idp_dg* h, const idp_dg_desc* desc) {
   return e;
 }
 
-int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long ws_bytes, idp_dg** out) {
-  (void)ws_bytes;
-  if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
-  *out = nullptr;
-  std::string why;
-  if (!desc_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
-  idp_dg* h = new (std::nothrow) idp_dg;
-  if (!h) return fail(nullptr, IDP_DG_ENOMEM, "host allocation failed");
+}  // namespace
+
+extern "C++" {
+namespace idp_host {
+// Host-side set-up of a handle from a checked descriptor: sizes, tables,
+// physics constants and the kernel family (no device calls, no allocation).
+void init_host(idp_dg* h, const idp_dg_desc* desc, void* hip_stream) {
   h->d = *desc;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->nc = desc->eq == IDP_DG_EULER ? desc->dim + 2 : 1;
-  const long long n1 = desc->p + 1;
   h->ne = desc->nx * desc->ny;
+  const long long n1 = desc->p + 1;
   h->nn = (long long)h->ne * (desc->dim == 2 ? n1 * n1 : n1);
   double xi[MAXP + 1], D[(MAXP + 1) * (MAXP + 1)];
   gl_tables(desc->p, xi, h->T.w, D);
@@ -512,6 +511,21 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
   }
   for (int k = 0; k <= desc->p; ++k) h->T.iw[k] = 1.0 / h->T.w[k];
   modal_tables(desc->p, xi, h->T.w, &h->T);
+}
+}  // namespace idp_host
+}  // extern "C++"
+
+namespace {
+int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long ws_bytes, idp_dg** out) {
+  (void)ws_bytes;
+  if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!desc_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  idp_dg* h = new (std::nothrow) idp_dg;
+  if (!h) return fail(nullptr, IDP_DG_ENOMEM, "host allocation failed");
+  init_host(h, desc, hip_stream);
+  const long long n1 = desc->p + 1;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) { int rc = hip_fail(nullptr, e, "hipGetDevice"); delete h; return rc; }
   if (ws) {  // caller workspace: no allocation, diagnostics cleared on the stream

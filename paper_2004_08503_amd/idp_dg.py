@@ -53,6 +53,7 @@ def _declare(lib):
         "idp_dg_stage": (ctypes.c_int, [H, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int]),
         "idp_dg_stage_trace": (ctypes.c_int, [H, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP]),
         "idp_dg_step": (ctypes.c_int, [H, _VP, ctypes.c_double]),
+        "idp_dg_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Desc), _VP, ctypes.c_double, _VP]),
         "idp_dg_step_cfl": (ctypes.c_int, [H, _VP, ctypes.c_double]),
         "idp_dg_last_dt": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
         "idp_dg_max_dt": (ctypes.c_int, [H, _VP, ctypes.POINTER(ctypes.c_double)]),
@@ -132,6 +133,27 @@ def make_desc(prob):
     bc = tuple(getattr(prob, "bc", (0, 0)))
     d.bc[0], d.bc[1] = int(bc[0]), int(bc[1])
     return d
+
+
+NOALLOC_MAX_DOUBLES = 4 << 20
+
+
+def step_noalloc(prob, u, dt):
+    """idp_dg_step_noalloc: one step of u (float64 CUDA tensor (nc, Nn),
+    contiguous) in place on the current torch stream, with the library's
+    static stage buffers; raises IdpError on a non-zero return."""
+    d = make_desc(prob)
+    n1 = d.p + 1
+    nn = d.nx * d.ny * (n1 * n1 if d.dim == 2 else n1)
+    nc = d.dim + 2 if d.eq == EULER else 1
+    if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64
+            and u.is_contiguous() and u.numel() == nc * nn):
+        raise ValueError("u must be a contiguous float64 CUDA tensor of %d values" % (nc * nn))
+    stream = torch.cuda.current_stream(u.device).cuda_stream
+    rc = lib.idp_dg_step_noalloc(ctypes.byref(d), ctypes.c_void_p(u.data_ptr()), float(dt),
+                                 ctypes.c_void_p(stream))
+    if rc:
+        raise IdpError(rc, lib.idp_dg_last_error(None).decode())
 
 
 def family_of(prob):

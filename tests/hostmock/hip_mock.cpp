@@ -169,6 +169,15 @@ hipError_t hipLaunchKernel(const void* f, dim3 grid, dim3 block, void** args, si
   Op op{}; op.kind = 0; push(st, op); return hipSuccess; }
 void** __hipRegisterFatBinary(const void*) { static void* h; return &h; }
 void __hipRegisterFunction(void**, const void*, char*, const char*, unsigned, void*, void*, void*, void*, int*) {}
+void __hipRegisterVar(void**, void*, char*, const char*, int, size_t, int, int) {}
+// a device symbol's "address": a host buffer standing in for it (the
+// library only passes it to kernels, which do not run here)
+hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  static char stand_in[4096];
+  if (!p || !sym) return hipErrorInvalidValue;
+  *p = stand_in;
+  return hipSuccess;
+}
 void __hipUnregisterFatBinary(void**) {}
 // report what is still alive at exit
 void mock_report() {
