@@ -124,7 +124,8 @@ int plan(idp_dg_batch* b, std::vector<int>* isolve, std::vector<int>* itile, std
       if (b->s[i]->d.p != p) continue;
       if (batch_kernels(b->fam, p, b->shape[p], &gr.k))
         return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
-      const int nt = (b->s[i]->ne + gr.k.tile_elems - 1) / gr.k.tile_elems;
+      const int nt = ((b->s[i]->d.nx + gr.k.tile_x - 1) / gr.k.tile_x) *
+                     ((b->s[i]->d.ny + gr.k.tile_y - 1) / gr.k.tile_y);
       (*range)[2 * i] = (int)isolve->size();
       for (int t = 0; t < nt; ++t) {
         isolve->push_back(i);
@@ -198,6 +199,18 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
     a[2 * b->n + i] = make_stage_args(hd, u[i], hd->buf2, u[i], 0.0, dtp, scale, 2);
     m[i] = make_dt_args(hd, u[i]);
     m[i].partial = at<double>(d, b->o_partial);
+    // the tiles are those of the degree's batched kernels, whose shape may
+    // differ from the member's own
+    BatchKernels k;
+    if (batch_kernels(b->fam, hd->d.p, b->shape[hd->d.p], &k)) return bfail(b, IDP_DG_EINVAL, "no batched kernel");
+    const int ntx = (hd->d.nx + k.tile_x - 1) / k.tile_x;
+    const int nt = ntx * ((hd->d.ny + k.tile_y - 1) / k.tile_y);
+    for (int st = 0; st < 3; ++st) {
+      a[st * b->n + i].S.ntx = ntx;
+      a[st * b->n + i].S.ntiles = nt;
+    }
+    m[i].ntx = ntx;
+    m[i].ntiles = nt;
   }
   if (b->nitems) {
     std::memcpy(h + b->o_isolve, isolve.data(), sizeof(int) * b->nitems);

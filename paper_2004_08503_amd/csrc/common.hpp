@@ -31,6 +31,9 @@ struct Phys {
   const double* vrow;  // EQ_ADVV: beta_x of every node row (ny*(p+1), device)
   const double* vcol;  // EQ_ADVV: beta_y of every node column (nx*(p+1), device)
   double gamma;        // Euler
+  double g1;           // (gamma-1)/2
+  double igm1;         // 1/(gamma-1)
+  double fac;          // (gamma+1)/(2 gamma)
   double ex;           // (gamma-1)/(2 gamma)
   double inv_ex;       // 2 gamma/(gamma-1)
   int inv_ex_int;      // inv_ex when it is an integer (7 for gamma = 1.4), else 0
@@ -73,6 +76,7 @@ struct Solve {
   int p;                // polynomial degree
   int nx, ny, ne;       // elements
   int ntiles;           // element tiles of this solve
+  int ntx;              // tiles per row of tiles
   double hx, hy;
   double ihx, ihy;      // 1/hx, 1/hy
 };
@@ -96,6 +100,7 @@ struct MaxDtArgs {
   long long nn;
   int p;
   int nx, ny, ne, ntiles;
+  int ntx;                   // tiles per row of tiles
   double hx, hy;
   Phys ph;
   Tables T;
@@ -122,7 +127,7 @@ struct BatchKernels {
   const void* stage;         // __global__ void(BatchArgs)
   const void* maxdt;         // __global__ void(BatchDtArgs)
   int block;                 // threads per workgroup
-  int tile_elems;            // elements per tile
+  int tile_x, tile_y;        // elements per tile in x and y
 };
 
 // A graph whose last launch may still run: destroyed only once its event
@@ -141,7 +146,7 @@ struct RetiredGraph {
                                  hipStream_t s);                                  \
   hipError_t launch_maxdt_##NAME(int p, int variant, const MaxDtArgs& a,          \
                                  hipStream_t s);                                  \
-  int tile_elems_##NAME(int p, int variant);                                      \
+  void tile_dims_##NAME(int p, int variant, int* tx, int* ty);                    \
   int num_variants_##NAME(int p);                                                 \
   int batch_kernels_##NAME(int p, int variant, BatchKernels* k);
 

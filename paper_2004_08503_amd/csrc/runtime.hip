@@ -204,22 +204,36 @@ hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-int tile_elems(const idp_dg* h) {
+void tile_dims(const idp_dg* h, int* tx, int* ty) {
   const int p = h->d.p;
+  *tx = *ty = 1;
   switch (family(h)) {
-    case 0: return tile_elems_adv1(p, h->variant);
-    case 1: return tile_elems_adv2(p, h->variant);
-    case 2: return tile_elems_burg1(p, h->variant);
-    case 3: return tile_elems_burg2(p, h->variant);
-    case 4: return tile_elems_euler1(p, h->variant);
-    case 5: return tile_elems_euler2(p, h->variant);
-    case 6: return tile_elems_euler53_1(p, h->variant);
-    case 7: return tile_elems_euler53_2(p, h->variant);
-    case 8: return tile_elems_euler75_1(p, h->variant);
-    case 9: return tile_elems_euler75_2(p, h->variant);
-    case 11: return tile_elems_advv2(p, h->variant);
+    case 0: return tile_dims_adv1(p, h->variant, tx, ty);
+    case 1: return tile_dims_adv2(p, h->variant, tx, ty);
+    case 2: return tile_dims_burg1(p, h->variant, tx, ty);
+    case 3: return tile_dims_burg2(p, h->variant, tx, ty);
+    case 4: return tile_dims_euler1(p, h->variant, tx, ty);
+    case 5: return tile_dims_euler2(p, h->variant, tx, ty);
+    case 6: return tile_dims_euler53_1(p, h->variant, tx, ty);
+    case 7: return tile_dims_euler53_2(p, h->variant, tx, ty);
+    case 8: return tile_dims_euler75_1(p, h->variant, tx, ty);
+    case 9: return tile_dims_euler75_2(p, h->variant, tx, ty);
+    case 11: return tile_dims_advv2(p, h->variant, tx, ty);
   }
-  return 1;
+}
+
+int tile_elems(const idp_dg* h) {
+  int tx, ty;
+  tile_dims(h, &tx, &ty);
+  return tx * ty;
+}
+
+// tiles of the handle's mesh, and tiles per row of tiles
+int tiles_of(const idp_dg* h, int* ntx) {
+  int tx, ty;
+  tile_dims(h, &tx, &ty);
+  *ntx = (h->d.nx + tx - 1) / tx;
+  return *ntx * ((h->d.ny + ty - 1) / ty);
 }
 
 StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s, double* u_out,
@@ -239,7 +253,7 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.S.nx = h->d.nx;
   a.S.ny = h->d.ny;
   a.S.ne = h->ne;
-  a.S.ntiles = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  a.S.ntiles = tiles_of(h, &a.S.ntx);
   a.S.hx = h->d.lx / h->d.nx;
   a.S.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
   a.S.ihx = 1.0 / a.S.hx;
@@ -267,7 +281,7 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   a.nx = h->d.nx;
   a.ny = h->d.ny;
   a.ne = h->ne;
-  a.ntiles = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  a.ntiles = tiles_of(h, &a.ntx);
   a.hx = h->d.lx / h->d.nx;
   a.hy = h->d.dim == 2 ? h->d.ly / h->d.ny : 1.0;
   a.ph = h->ph;
@@ -339,7 +353,8 @@ void drop_graph(idp_dg* h) {
 hipError_t enqueue_max_dt(const idp_dg* h, const double* u, double* out, hipStream_t s) {
   hipError_t e = launch_maxdt(h, make_dt_args(h, u), s);
   if (e != hipSuccess) return e;
-  const int nb = (h->ne + tile_elems(h) - 1) / tile_elems(h);
+  int ntx;
+  const int nb = tiles_of(h, &ntx);
   hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(1024), 0, s, h->partial, nb, out);
   return hipGetLastError();
 }
@@ -497,6 +512,9 @@ void init_host(idp_dg* h, const idp_dg_desc* desc, void* hip_stream) {
   h->ph.vel0 = desc->velocity[0];
   h->ph.vel1 = desc->dim == 2 ? desc->velocity[1] : 0.0;
   h->ph.gamma = desc->eq == IDP_DG_EULER ? desc->gamma : 1.4;
+  h->ph.g1 = 0.5 * (h->ph.gamma - 1.0);
+  h->ph.igm1 = 1.0 / (h->ph.gamma - 1.0);
+  h->ph.fac = (h->ph.gamma + 1.0) / (2.0 * h->ph.gamma);
   h->ph.ex = (h->ph.gamma - 1.0) / (2.0 * h->ph.gamma);
   h->ph.inv_ex = 1.0 / h->ph.ex;
   const double r = std::nearbyint(h->ph.inv_ex);

@@ -1,21 +1,34 @@
-// Fused limited SSP-RK stage for gfx950: one workgroup owns a tile of EPB
-// consecutive elements, one thread per node, and runs every step of the
-// stage out of LDS.  Global memory is touched once per node for the stage
-// input (plus the face traces of the 2d neighbouring elements), once for
-// u^n on the second and third stages, and once for the output.
+// Fused limited SSP-RK stage for gfx950.  One workgroup owns a tile of
+// TX x TY elements (TX elements in 1-D), one thread per node, and runs every
+// step of the stage out of LDS.  Global memory is touched once per node for
+// the stage input (plus one ring of face-trace nodes around the tile), once
+// for u^n on the second and third stages, and once for the output.
+//
+// The tile's nodes form one grid of GX = TX (p+1) columns and GY = TY (p+1)
+// rows (one row in 1-D), surrounded by a ring of halo slots holding the
+// facing nodes of the neighbouring elements (or, on an open side of the
+// box, the exterior states).  Along a grid row, consecutive columns are
+// neighbours whether they belong to one element (an interior subcell face)
+// or to two (an element face), so every subcell face of the tile is one
+// pair of adjacent slots and is evaluated once, left state first: element
+// faces inside the tile are not duplicated, and a face on the tile's edge,
+// which the neighbouring tile evaluates too, gives bitwise the same values
+// in both (a face's arithmetic does not depend on which tile runs it).
 //
 // Phases (LDS barriers between them):
-//   1. load the tile's states and the neighbours' face traces;
-//   2. pointwise physics: fluxes F^x, F^y and, for Euler, 1/rho, p, c,
-//      p^{-(gamma-1)/(2 gamma)} and K = p rho^{-gamma};
-//   3. one work item per subcell face of every line (element faces
-//      included): wave-speed bound, low-order flux f^L (eq. lax-friedrichs
-//      on the subgrid), bar state of the limited component (eq.
-//      bar-states), the entropy bound over the pair, and on interior
-//      subcell faces the high-order subcell flux f^H and the antidiffusive
-//      flux rbar = s (f^L - f^H);
-//   4. per node: u^L, local bounds, Zalesak coefficient and, for Euler,
-//      the entropy line search of eq. convex-provisional;
+//   1-2. load the tile's own nodes and its halo ring; pointwise physics on
+//        every slot: fluxes (own nodes: both directions, halo slots: the
+//        direction of their face) and, for Euler, 1/rho, the sound speed c,
+//        c p^{-(gamma-1)/(2 gamma)}, (gamma+1)/(2 gamma p) (the inputs of the
+//        wave-speed bound) and K = p rho^{-gamma};
+//   3. one work item per subcell face: wave-speed bound, low-order flux f^L
+//      (eq. lax-friedrichs on the subgrid), bar state of the limited
+//      component (eq. bar-states) and on interior subcell faces the
+//      high-order subcell flux f^H and the antidiffusive flux
+//      rbar = s (f^L - f^H);
+//   4. per node: u^L, local bounds (K_min over the node and its four grid
+//      neighbours), Zalesak coefficient and, for Euler, the entropy line
+//      search of eq. convex-provisional;
 //   5. per node: subcell-face coefficients min(alpha_i, alpha_j), the
 //      flux-corrected update (eq. convex-fct) and the RK combination.
 //
@@ -30,55 +43,83 @@
 
 namespace idp {
 
-template <int EQ, int DIM, int P, int EPB>
+template <int EQ, int DIM, int P, int TX, int TY>
 struct Cfg {
   static constexpr int N1 = P + 1;
-  static constexpr int NP = DIM == 2 ? N1 * N1 : N1;   // own nodes per element
-  static constexpr int TJ = DIM == 2 ? N1 : 1;          // nodes per face trace
-  static constexpr int NT = 2 * DIM * TJ;               // trace nodes per element
-  static constexpr int NS = NP + NT;                    // LDS slots per element
+  static constexpr int NP = DIM == 2 ? N1 * N1 : N1;    // nodes per element
+  static constexpr int TYE = DIM == 2 ? TY : 1;         // elements per tile in y
+  static constexpr int NE = TX * TYE;                   // elements per tile
+  static constexpr int GX = TX * N1;                    // node columns of the tile
+  static constexpr int GY = DIM == 2 ? TYE * N1 : 1;    // node rows
+  static constexpr int NOWN = NE * NP;                  // own nodes (= GX GY)
+  static constexpr int BS = ((NOWN + 63) / 64) * 64;
+  static constexpr int NW = BS / 64;                    // waves per workgroup
   static constexpr int NC = is_euler(EQ) ? DIM + 2 : 1;
-  // per-slot auxiliaries: Euler 1/rho, p, c, p^-ex, K; EQ_ADVV beta_x, beta_y
-  static constexpr int NAUX = is_euler(EQ) ? 5 : EQ == EQ_ADVV ? 2 : 0;
-  static constexpr int NAUXF = is_euler(EQ) ? 4 : NAUX;   // those fluxes and speeds read
-  static constexpr int NFL = P + 2;                     // subcell faces per line
-  static constexpr int NL = DIM == 2 ? N1 : 1;          // lines per direction
-  static constexpr int NF = NFL * NL;                   // faces per direction
-  static constexpr int BS = ((EPB * NP + 63) / 64) * 64;
-  // phase 3 work: per direction, the element faces (f = 0 or p + 1) and the
-  // interior faces form two groups, each cut into chunks of 64 items; a wave
-  // takes whole chunks, so each of its passes runs one body specialised for
-  // a direction and a face kind
-  static constexpr int NW = BS / 64;                   // waves per workgroup
-  static constexpr int GE = EPB * 2 * NL;              // element-face items per direction
-  static constexpr int GI = EPB * P * NL;              // interior items per direction
-  static constexpr int CE = (GE + 63) / 64;            // chunks per group
-  static constexpr int CI = (GI + 63) / 64;
-  static constexpr int NCHUNK = DIM * (CE + CI);
+  // per-slot auxiliaries the faces read: Euler 1/rho, c, c p^-ex,
+  // (gamma+1)/(2 gamma p); EQ_ADVV beta_x, beta_y.  The Euler K = p rho^-gamma
+  // of every slot goes to the nodal-alpha array, free until phase 4.
+  static constexpr int NAUX = is_euler(EQ) ? 4 : EQ == EQ_ADVV ? 2 : 0;
+  static constexpr int NAUXF = NAUX;
+  // slot grid: own nodes (i, j), 0 <= i < GX, 0 <= j < GY, and the halo ring
+  // i = -1, i = GX (x-neighbours) and j = -1, j = GY (y-neighbours)
+  static constexpr int RP = GX + 2;                     // row pitch
+  static constexpr int NSL = DIM == 2 ? RP * (GY + 2) : RP;
+  static constexpr int NH = 2 * GY + (DIM == 2 ? 2 * GX : 0);   // halo slots
+  // flux grids: F^x on rows 0..GY-1 and columns -1..GX, F^y on rows
+  // -1..GY and columns 0..GX-1
+  static constexpr int NFX = GY * RP;
+  static constexpr int NFY = DIM == 2 ? (GY + 2) * GX : 0;
+  // face grids: x-face i (between columns i-1 and i) of row j, i = 0..GX;
+  // y-face j (between rows j-1 and j) of column i, j = 0..GY
+  static constexpr int FXP = GX + 1;
+  static constexpr int NOX = GY * FXP;
+  static constexpr int NOY = DIM == 2 ? (GY + 1) * GX : 0;
+  // Arrays of several components (or auxiliaries) keep them a multiple of
+  // 64 doubles apart, so that one ds_read2st64 / ds_write2st64 moves two of
+  // them from one address register.
+  static constexpr int up64(int n) { return (n + 63) / 64 * 64; }
+  static constexpr int CSU = up64(NSL), CSX = up64(NFX), CSY = up64(NFY);
+  static constexpr int COX = up64(NOX), COY = up64(NOY), CSO = up64(NOWN);
+  // phase-3 work: per direction the element faces and the interior faces
+  // form two groups, each cut into chunks of 64 items; a wave takes whole
+  // chunks, so each of its passes runs one body specialised for a direction
+  // and a face kind
+  static constexpr int GEX = GY * (TX + 1);
+  static constexpr int GIX = GY * TX * P;
+  static constexpr int GEY = DIM == 2 ? GX * (TYE + 1) : 0;
+  static constexpr int GIY = DIM == 2 ? GX * TYE * P : 0;
+  static constexpr int CEX = (GEX + 63) / 64, CEY = (GEY + 63) / 64;
+  static constexpr int CIX = (GIX + 63) / 64, CIY = (GIY + 63) / 64;
+  static constexpr int NCHUNK = CEX + CEY + CIX + CIY;
   static constexpr int NITEM = (NCHUNK + NW - 1) / NW;  // chunks per wave
-  // region A: phase 1-2 results, read in phase 3 (fluxes of own nodes only:
-  // the face-trace fluxes are formed where a face needs them)
+  // region A: phase 1-2 results, read in phase 3
   static constexpr int A_U = 0;
-  static constexpr int A_X = A_U + NC * EPB * NS;
-  static constexpr int A_F = A_X + NAUX * EPB * NS;
-  static constexpr int A_END = A_F + DIM * NC * EPB * NP;
+  static constexpr int A_X = A_U + NC * CSU;
+  static constexpr int A_FX = A_X + NAUX * CSU;
+  static constexpr int A_FY = A_FX + NC * CSX;
+  static constexpr int A_END = A_FY + NC * CSY;
   // region B (aliases A): phase 3 results, read in phases 4-5
-  static constexpr int B_FL = 0;
-  static constexpr int B_RB = B_FL + DIM * NC * EPB * NF;
-  static constexpr int B_UB = B_RB + DIM * NC * EPB * NF;
-  static constexpr int B_END = B_UB + DIM * EPB * NF;
+  static constexpr int B_FLX = 0;
+  static constexpr int B_FLY = B_FLX + NC * COX;
+  static constexpr int B_RBX = B_FLY + NC * COY;
+  static constexpr int B_RBY = B_RBX + NC * COX;
+  static constexpr int B_UBX = B_RBY + NC * COY;
+  static constexpr int B_UBY = B_UBX + COX;
+  static constexpr int B_END = B_UBY + COY;
   // region C: Euler search data, written once the low-order fluxes are
   // consumed; it overwrites them where it fits
-  static constexpr int C_SIZE = is_euler(EQ) ? (NC + 2 + DIM) * EPB * NP : 0;
-  static constexpr int C_UL = C_SIZE <= DIM * NC * EPB * NF ? B_FL : B_END;   // [NC][EPB*NP]
-  static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * EPB * NP : 0);
-  static constexpr int C_AZ = C_KM + (is_euler(EQ) ? EPB * NP : 0);   // bound U of the node
-  static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? EPB * NP : 0);  // int[2*DIM*EPB*NP]
-  static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * EPB * NP : 0);
+  static constexpr int C_SIZE = is_euler(EQ) ? (NC + 2 + DIM) * CSO : 0;
+  static constexpr int C_UL = C_SIZE <= NC * (COX + COY) ? B_FLX : B_END;   // [NC][CSO]
+  static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * CSO : 0);
+  static constexpr int C_AZ = C_KM + (is_euler(EQ) ? CSO : 0);   // bound U of the node
+  static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? CSO : 0);  // int[2*DIM*CSO]
+  static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * CSO : 0);
   static constexpr int AB0 = A_END > B_END ? A_END : B_END;
   static constexpr int AB = AB0 > C_END ? AB0 : C_END;
-  static constexpr int S_AL = AB;                       // nodal alpha
-  static constexpr int S_W = S_AL + EPB * NP;           // weights
+  // nodal alpha [NOWN] (grid order); before phase 4 the Euler K of every
+  // slot [NSL] (slot order), and the smoothness indicator's scratch
+  static constexpr int S_AL = AB;
+  static constexpr int S_W = S_AL + (is_euler(EQ) ? CSU : NOWN);   // weights
   static constexpr int S_Q = S_W + N1;                  // cumulative D
   static constexpr int S_IW = S_Q + P * N1;             // 1/w
   static constexpr int S_M = S_IW + N1;                 // nodal -> modal map [k][a]
@@ -86,61 +127,41 @@ struct Cfg {
   static constexpr int S_LN = S_NK + N1;                // search list length (int)
   static constexpr int LDS = S_LN + 1;
   static_assert(LDS * 8 <= 160 * 1024, "tile does not fit in LDS");
+
+  // slot of grid point (i, j), -1 <= i <= GX, -1 <= j <= GY
+  static __device__ __forceinline__ int sl(int i, int j) { return DIM == 2 ? (j + 1) * RP + i + 1 : i + 1; }
+  // flux-grid entries
+  static __device__ __forceinline__ int fx(int i, int j) { return j * RP + i + 1; }
+  static __device__ __forceinline__ int fy(int i, int j) { return (j + 1) * GX + i; }
+  // face-grid entries
+  static __device__ __forceinline__ int ox(int i, int j) { return j * FXP + i; }
+  static __device__ __forceinline__ int oy(int i, int j) { return j * GX + i; }
 };
 
+// Where a tile lies: its first element column and row, and how many of its
+// TX x TY elements exist (tiles on the high edges of the mesh are ragged).
+struct TileGeo {
+  int ex0, ey0, tw, th;
+};
+template <int DIM, int TX, int TY>
+__device__ inline TileGeo tile_geo(int tile, int ntx, int nx, int ny) {
+  TileGeo t;
+  const int ty = DIM == 2 ? tile / ntx : 0;
+  const int tx = tile - ty * ntx;
+  t.ex0 = tx * TX;
+  t.ey0 = DIM == 2 ? ty * TY : 0;
+  t.tw = min(TX, nx - t.ex0);
+  t.th = DIM == 2 ? min(TY, ny - t.ey0) : 1;
+  return t;
+}
+
 // Workgroups are dealt round-robin to the eight XCDs; give every XCD a
-// contiguous range of tiles so that the face traces a tile reads from the
-// element rows above and below were fetched into the same XCD's L2.
+// contiguous range of tiles so that the halo nodes a tile reads from the
+// tile rows above and below were fetched into the same XCD's L2.
 __device__ inline int xcd_tile(int b, int nb) {
   const int x = b & 7, i = b >> 3;
   const int q = nb >> 3, r = nb & 7;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
-
-// Global node index of trace t of element e: face 0/1 = the x-neighbours'
-// facing node columns, 2/3 = the y-neighbours' facing rows (periodic).
-template <int DIM, int P>
-__device__ inline long long trace_node(int e, int t, int nx, int ny) {
-  constexpr int N1 = P + 1;
-  const int ex = e % nx, ey = e / nx;
-  if constexpr (DIM == 1) {
-    const int exn = t == 0 ? (ex == 0 ? nx - 1 : ex - 1) : (ex == nx - 1 ? 0 : ex + 1);
-    return (long long)exn * N1 + (t == 0 ? P : 0);
-  } else {
-    constexpr int NP = N1 * N1;
-    const int face = t / N1, j = t - face * N1;
-    int exn = ex, eyn = ey, loc;
-    if (face == 0) { exn = ex == 0 ? nx - 1 : ex - 1; loc = j * N1 + P; }
-    else if (face == 1) { exn = ex == nx - 1 ? 0 : ex + 1; loc = j * N1; }
-    else if (face == 2) { eyn = ey == 0 ? ny - 1 : ey - 1; loc = P * N1 + j; }
-    else { eyn = ey == ny - 1 ? 0 : ey + 1; loc = j; }
-    return ((long long)eyn * nx + exn) * NP + loc;
-  }
-}
-
-// Whether trace t of element e lies on an open side of the box; if so the
-// side, the boundary node's index along that side and the global index of
-// the element's own node at that point.
-template <int DIM, int P>
-__device__ inline bool boundary_trace(int e, int t, int nx, int ny, int open, int* side, int* q,
-                                      long long* own) {
-  constexpr int N1 = P + 1;
-  const int face = DIM == 2 ? t / N1 : t, j = DIM == 2 ? t - face * N1 : 0;
-  const int k = face >> 1;
-  if (!((open >> k) & 1)) return false;
-  const int ex = e % nx, ey = e / nx;
-  const bool edge = k == 0 ? ((face & 1) ? ex == nx - 1 : ex == 0)
-                           : ((face & 1) ? ey == ny - 1 : ey == 0);
-  if (!edge) return false;
-  *side = face;
-  *q = DIM == 1 ? 0 : (k == 0 ? ey * N1 + j : ex * N1 + j);
-  if constexpr (DIM == 1) {
-    *own = (long long)e * N1 + ((face & 1) ? P : 0);
-  } else {
-    const int loc = face == 0 ? j * N1 : face == 1 ? j * N1 + P : face == 2 ? j : P * N1 + j;
-    *own = (long long)e * (N1 * N1) + loc;
-  }
-  return true;
 }
 
 // The advection velocity / Burgers direction component k, selected between
@@ -191,16 +212,47 @@ __device__ inline double inv_root(double x) {
   return ldexp(y, -q);
 }
 
-// Euler auxiliaries of one state: X = (1/rho, p, c, p^-(gamma-1)/(2gamma),
-// K = p rho^-gamma) (K only when WITHK).  For gamma = 1 + 2/n (GN = n = 5:
-// 7/5, n = 3: 5/3) every fractional power is an integer power of
-// z = rho^(-1/n) or of p^(-1/(n+2)): 1/rho = z^n, K = p z^(n+2); otherwise
-// pow and a division are used.  Without K (the time-step pass) 1/rho is a
+// sqrt(x) for x >= 1 (or +infinity): the hardware reciprocal square root
+// refined by Goldschmidt's iteration and two residual corrections, which
+// brings it to within an ulp; no scaling is needed in this range.
+__device__ inline double sqrt_ge1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x < INFINITY ? g : x;
+}
+
+// 1/x for x of normal magnitude: the hardware approximation refined by two
+// Newton steps, within an ulp (infinity gives 0, NaN gives NaN).
+__device__ inline double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// ----------------------------------------------------------------------
+// pointwise physics
+// ----------------------------------------------------------------------
+
+// Euler auxiliaries of one state: X = (1/rho, c, c p^-ex, (gamma+1)/(2 gamma
+// p), and with WITHK K = p rho^-gamma), ex = (gamma-1)/(2 gamma); p is
+// returned for the fluxes.  For gamma = 1 + 2/n (GN = n = 5: 7/5, n = 3:
+// 5/3) every fractional power is an integer power of z = rho^(-1/n) or of
+// x3 = p^(-1/(n+2)): 1/rho = z^n, K = p z^(n+2), 1/p = x3^(n+2); otherwise
+// pow and divisions are used.  Without K (the time-step pass) 1/rho is a
 // plain division, cheaper than the root.
-template <int DIM, int GN, bool WITHK = true>
-__device__ inline void euler_aux(const double* U, const Phys& ph, double* X, bool& bad) {
+template <int DIM, int GN, bool WITHK>
+__device__ inline void euler_aux(const double* U, const Phys& ph, double* X, double& p, bool& bad) {
   double rinv, z = 0.0;
-  if constexpr (GN > 0 && WITHK) {   // z = rho^(-1/n) also gives K below
+  if constexpr (GN > 0 && WITHK) {
     z = inv_root<GN>(U[0]);
     rinv = ipow_c<GN>(z);
   } else {
@@ -209,33 +261,42 @@ __device__ inline void euler_aux(const double* U, const Phys& ph, double* X, boo
   double mm = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) mm += U[1 + k] * U[1 + k];
-  const double p = (ph.gamma - 1.0) * (U[DIM + 1] - 0.5 * mm * rinv);
+  p = (ph.gamma - 1.0) * (U[DIM + 1] - 0.5 * mm * rinv);
   bad = !(U[0] > 0.0) || !(p > 0.0);
-  X[0] = rinv;
-  X[1] = p;
-  X[2] = sqrt(ph.gamma * p * rinv);
+  const double c = sqrt(ph.gamma * p * rinv);
+  double x3, ip;
   if constexpr (GN > 0) {
-    X[3] = inv_root<GN + 2>(p);
-    if constexpr (WITHK) X[4] = p * ipow_c<GN + 2>(z);
+    x3 = inv_root<GN + 2>(p);
+    ip = ipow_c<GN + 2>(x3);
   } else {
-    X[3] = pow(p, -ph.ex);
-    if constexpr (WITHK) X[4] = p * pow(U[0], -ph.gamma);
+    x3 = pow(p, -ph.ex);
+    ip = 1.0 / p;
+  }
+  X[0] = rinv;
+  X[1] = c;
+  X[2] = c * x3;
+  X[3] = ph.fac * ip;
+  if constexpr (WITHK) {
+    if constexpr (GN > 0) X[4] = p * ipow_c<GN + 2>(z);
+    else X[4] = p * pow(U[0], -ph.gamma);
   }
 }
 
-// flux in direction k of one state (X: Euler auxiliaries)
+// flux in direction k (k known at compile time where the caller unrolls;
+// otherwise the components are selected, never indexed at run time).
+// X: Euler auxiliaries (X[0] = 1/rho) with the pressure p, or beta for EQ_ADVV.
 template <int EQ, int DIM>
-__device__ inline void flux_k(int k, const double* U, const double* X, const Phys& ph, double* F) {
+__device__ inline void flux_k(int k, const double* U, const double* X, double p, const Phys& ph, double* F) {
   if constexpr (EQ == EQ_ADV) {
-    F[0] = (vel_k(k, ph)) * U[0];
+    F[0] = vel_k(k, ph) * U[0];
   } else if constexpr (EQ == EQ_ADVV) {
-    F[0] = X[k] * U[0];
+    F[0] = (k == 0 ? X[0] : X[1]) * U[0];
   } else if constexpr (EQ == EQ_BURG) {
-    F[0] = 0.5 * U[0] * U[0] * (vel_k(k, ph));
+    F[0] = 0.5 * U[0] * U[0] * vel_k(k, ph);
   } else {
-    const double vk = U[1 + k] * X[0];
-    const double p = X[1];
-    F[0] = U[1 + k];
+    const double mk = DIM == 2 && k == 1 ? U[2] : U[1];
+    const double vk = mk * X[0];
+    F[0] = mk;
 #pragma unroll
     for (int l = 0; l < DIM; ++l) F[1 + l] = U[1 + l] * vk + (l == k ? p : 0.0);
     F[DIM + 1] = vk * (U[DIM + 1] + p);
@@ -244,73 +305,39 @@ __device__ inline void flux_k(int k, const double* U, const double* X, const Phy
 
 // The two-rarefaction bound of the Euler wave speeds (Guermond and Popov,
 // J. Comput. Phys. 2016, valid for 1 < gamma <= 5/3) from the normal
-// velocities, pressures, sound speeds and p^-(gamma-1)/(2 gamma) of the
-// left and right states.
+// velocities and the auxiliaries X = (1/rho, c, c p^-ex, (gamma+1)/(2 gamma
+// p)) of the left and right states: with
+// p* = ((c_L + c_R - (gamma-1)/2 (v_R - v_L))_+ / (c_L p_L^-ex + c_R p_R^-ex))^(1/ex),
+// lambda = max((v_L - c_L sqrt(1 + (gamma+1)/(2 gamma) (p* - p_L)_+ / p_L))_-,
+//              (v_R + c_R sqrt(1 + (gamma+1)/(2 gamma) (p* - p_R)_+ / p_R))_+).
 template <int GN>
-__device__ inline double euler_lambda(double vl, double vr, double pl, double pr, double cl, double cr,
-                                      double xl3, double xr3, const Phys& ph) {
-  const double g = ph.gamma;
-  double num = cl + cr - 0.5 * (g - 1.0) * (vr - vl);
-  num = num < 0.0 ? 0.0 : num;
-  const double den = cl * xl3 + cr * xr3;
-  const double base = num / den;
-  double pstar, ipl, ipr;
-  if constexpr (GN > 0) {  // 2 gamma/(gamma-1) = n + 2; 1/p = (p^-1/(n+2))^(n+2)
-    pstar = ipow_c<GN + 2>(base);
-    ipl = ipow_c<GN + 2>(xl3);
-    ipr = ipow_c<GN + 2>(xr3);
-  } else {
-    pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
-    ipl = 1.0 / pl;
-    ipr = 1.0 / pr;
-  }
-  const double fac = (g + 1.0) / (2.0 * g);
-  const double lam_l = vl - cl * sqrt(1.0 + fac * fmax(pstar - pl, 0.0) * ipl);
-  const double lam_r = vr + cr * sqrt(1.0 + fac * fmax(pstar - pr, 0.0) * ipr);
-  return fmax(fmax(-lam_l, 0.0), fmax(lam_r, 0.0));
+__device__ inline double euler_lambda(double vl, double vr, const double* XL, const double* XR, const Phys& ph) {
+  const double num = fmax(fma(-ph.g1, vr - vl, XL[1] + XR[1]), 0.0);
+  const double base = num * rcp_nr(XL[2] + XR[2]);   // c p^-ex > 0 on both sides
+  double pstar;
+  if constexpr (GN > 0) pstar = ipow_c<GN + 2>(base);
+  else pstar = ph.inv_ex_int ? ipow(base, ph.inv_ex_int) : pow(base, ph.inv_ex);
+  const double tl = fmax(fma(pstar, XL[3], -ph.fac), 0.0);
+  const double tr = fmax(fma(pstar, XR[3], -ph.fac), 0.0);
+  const double lam_l = fma(-XL[1], sqrt_ge1(1.0 + tl), vl);
+  const double lam_r = fma(XR[1], sqrt_ge1(1.0 + tr), vr);
+  return fmax(fmax(-lam_l, lam_r), 0.0);
 }
 
 // Upper bound of the maximum wave speed of the Riemann problem (UL | UR)
-// along +e_k.  Euler: the two-rarefaction pressure bound (Guermond and
-// Popov, J. Comput. Phys. 2016), valid for 1 < gamma <= 5/3.
-template <int EQ, int DIM>
-__device__ inline double lambda_k(int k, const double* UL, const double* XL, const double* UR,
-                                  const double* XR, const Phys& ph) {
+// along +e_K.
+template <int EQ, int DIM, int K>
+__device__ inline double lambda_k(const double* UL, const double* XL, const double* UR, const double* XR,
+                                  const Phys& ph) {
   if constexpr (EQ == EQ_ADV) {
-    return fabs(vel_k(k, ph));
+    return fabs(vel_k(K, ph));
   } else if constexpr (EQ == EQ_ADVV) {
     // Sec. 3.3: dhat_ij = max(|chat_ij . beta_i|, |chat_ji . beta_j|)
-    return fmax(fabs(XL[k]), fabs(XR[k]));
+    return fmax(fabs(XL[K]), fabs(XR[K]));
   } else if constexpr (EQ == EQ_BURG) {
-    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(vel_k(k, ph));
+    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(vel_k(K, ph));
   } else {
-    const double vl = UL[1 + k] * XL[0], vr = UR[1 + k] * XR[0];
-    return euler_lambda<gn_of(EQ)>(vl, vr, XL[1], XR[1], XL[2], XR[2], XL[3], XR[3], ph);
-  }
-}
-
-// lambda_k of an element face from its own-side state O and its trace T:
-// side 1 is the element's right face (O on the left), side 0 its left face
-// (T on the left).  The Euler bound selects the values it reads into
-// left/right order and then forms the same expressions as lambda_k (so the
-// result is identical to the bound of the pair in that order).
-template <int EQ, int DIM>
-__device__ inline double lambda_face(int k, const double* UO, const double* XO, const double* UT,
-                                     const double* XT, int side, const Phys& ph) {
-  if constexpr (is_euler(EQ)) {
-    const bool r = side != 0;
-    double ul[DIM + 2] = {}, ur[DIM + 2] = {}, xl[4], xr[4];
-    ul[1 + k] = r ? UO[1 + k] : UT[1 + k];
-    ur[1 + k] = r ? UT[1 + k] : UO[1 + k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      xl[q] = r ? XO[q] : XT[q];
-      xr[q] = r ? XT[q] : XO[q];
-    }
-    return lambda_k<EQ, DIM>(k, ul, xl, ur, xr, ph);
-  } else {
-    // symmetric in the two states
-    return lambda_k<EQ, DIM>(k, UO, XO, UT, XT, ph);
+    return euler_lambda<gn_of(EQ)>(UL[1 + K] * XL[0], UR[1 + K] * XR[0], XL, XR, ph);
   }
 }
 
@@ -348,7 +375,7 @@ __device__ inline PhiVal phi_at(double t, const double* uL, const double* P, dou
     mp += m * P[1 + k];
   }
   const double E = fma(t, P[DIM + 1], uL[DIM + 1]);
-  const double kg = kmin / (g - 1.0);
+  const double kg = kmin * ph.igm1;
   const double phi = E - 0.5 * mm * rinv - kg * rg;
   const double dphi = P[DIM + 1] - mp * rinv + 0.5 * mm * rinv * rinv * P[0] - kg * g * rg * rinv * P[0];
   r.phi = pos ? phi : -INFINITY;
@@ -472,237 +499,174 @@ __device__ double entropy_root(const double* uL, const double* P, double U, bool
 
 __device__ inline const Phys& ph_of(const StageArgs& A) { return A.ph; }
 
-// local slot of the node at position pos of line l in direction k
-template <int DIM, int P>
-__device__ inline int own_slot(int k, int l, int pos) {
-  if constexpr (DIM == 1) return pos;
-  return k == 0 ? l * (P + 1) + pos : pos * (P + 1) + l;
-}
-
-// One element face of a tile for phase 3: item -> element le, line l and
-// side (0: f = 0, the trace on the left; 1: f = p + 1, the trace on the
-// right).  Writes the low-order flux, the bar state of the limited
-// component and the face's index in the phase-3 arrays (o < 0: no face).
-template <int EQ, int DIM, int P, int EPB, int K>
-__device__ __forceinline__ void element_face(const double* lds, const Phys& ph, int item, int nel,
-                                             double* FLo, double& UBo, int& o) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NL = C::NL;
-  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
-  const int le = item / (2 * NL);
-  if (le >= nel) return;
-  const int r = item - le * (2 * NL);
-  const int l = r >> 1, side = r & 1;
-  const int base = le * NS;
-  const int st = base + NP + (2 * K + side) * C::TJ + l;             // trace slot
-  const int so = base + own_slot<DIM, P>(K, l, side ? P : 0);       // own slot
-  double UO[NC], UT[NC], XO[NX], XT[NX], FO[NC], FT[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    UO[c] = lds[C::A_U + c * EPB * NS + so];
-    UT[c] = lds[C::A_U + c * EPB * NS + st];
-    FO[c] = lds[C::A_F + (K * NC + c) * EPB * NP + le * NP + (so - base)];
-  }
-#pragma unroll
-  for (int q = 0; q < C::NAUXF; ++q) {
-    XO[q] = lds[C::A_X + q * EPB * NS + so];
-    XT[q] = lds[C::A_X + q * EPB * NS + st];
-  }
-  flux_k<EQ, DIM>(K, UT, XT, ph, FT);
-  const double lam = lambda_face<EQ, DIM>(K, UO, XO, UT, XT, side, ph);
-  // (F_L + F_R) / 2 - lam (U_R - U_L) / 2 with U_R - U_L = sg (U_T - U_O),
-  // sg = +-1 (exact).  The trace flux enters its sums rounded, not fused
-  // into them, as an interior face's fluxes do.
-  const double sg = side ? 1.0 : -1.0;
-  double fs[NC], df0;
-  {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) fs[c] = FO[c] + FT[c];
-    df0 = FT[0] - FO[0];
-  }
-#pragma unroll
-  for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * fs[c] - 0.5 * lam * (sg * (UT[c] - UO[c]));
-  const double avg = 0.5 * (UO[0] + UT[0]);
-  UBo = lam > 0.0 ? avg - (sg * df0) / (2.0 * lam) : avg;
-  o = le * C::NF + l * C::NFL + (side ? P + 1 : 0);
-}
-
-// One interior subcell face (1 <= f <= p) of a tile for phase 3: also the
-// high-order subcell flux and the antidiffusive flux.
-template <int EQ, int DIM, int P, int EPB, int K>
-__device__ __forceinline__ void interior_face(const double* lds, const Phys& ph, const Solve& S, int item,
-                                              int nel, double* FLo, double* RBo, double& UBo, int& o) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NL = C::NL, N1 = C::N1;
-  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
-  const int le = item / (P * NL);
-  if (le >= nel) return;
-  const int r = item - le * (P * NL);
-  const int l = r / P;
-  const int f = 1 + (r - l * P);
-  const int base = le * NS;
-  const int sl = base + own_slot<DIM, P>(K, l, f - 1);
-  const int sr = base + own_slot<DIM, P>(K, l, f);
-  double UL[NC], UR[NC], FL[NC], FR[NC], XL[NX], XR[NX];
-  const double* Fo = lds + C::A_F + K * NC * EPB * NP + le * NP;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    UL[c] = lds[C::A_U + c * EPB * NS + sl];
-    UR[c] = lds[C::A_U + c * EPB * NS + sr];
-    FL[c] = Fo[c * EPB * NP + sl - base];
-    FR[c] = Fo[c * EPB * NP + sr - base];
-  }
-#pragma unroll
-  for (int q = 0; q < C::NAUXF; ++q) {
-    XL[q] = lds[C::A_X + q * EPB * NS + sl];
-    XR[q] = lds[C::A_X + q * EPB * NS + sr];
-  }
-  const double lam = lambda_k<EQ, DIM>(K, UL, XL, UR, XR, ph);
-#pragma unroll
-  for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
-  const double avg = 0.5 * (UL[0] + UR[0]);
-  UBo = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
-  const double sc = DIM == 2 ? lds[C::S_W + l] * (K == 0 ? S.hy : S.hx) : 1.0;
-  const double* q = lds + C::S_Q + (f - 1) * N1;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    const double* Fl = Fo + c * EPB * NP;
-    double fh = Fl[own_slot<DIM, P>(K, l, 0)];
-#pragma unroll
-    for (int e = 0; e <= P; ++e) fh += q[e] * Fl[own_slot<DIM, P>(K, l, e)];
-    RBo[c] = sc * (FLo[c] - fh);
-  }
-  o = le * C::NF + l * C::NFL + f;
-}
-
-// Phase-3 chunk ch (wave-uniform) of a tile: chunks of the element-face
-// groups (direction 0, then 1) come first, then those of the interior
-// groups; lane picks the item within the chunk.
-template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void face_chunk(const double* lds, const Phys& ph, const Solve& S, int ch, int lane,
-                                           int nel, double* FLo, double* RBo, double& UBo, int& o) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  if (ch < DIM * C::CE) {
-    const int k = ch / C::CE;
-    const int item = (ch - k * C::CE) * 64 + lane;
-    if (k == 0) element_face<EQ, DIM, P, EPB, 0>(lds, ph, item, nel, FLo, UBo, o);
-    else if constexpr (DIM == 2) element_face<EQ, DIM, P, EPB, 1>(lds, ph, item, nel, FLo, UBo, o);
-  } else if (ch < C::NCHUNK) {
-    const int c2 = ch - DIM * C::CE;
-    const int k = c2 / C::CI;
-    const int item = (c2 - k * C::CI) * 64 + lane;
-    if (k == 0) interior_face<EQ, DIM, P, EPB, 0>(lds, ph, S, item, nel, FLo, RBo, UBo, o);
-    else if constexpr (DIM == 2) interior_face<EQ, DIM, P, EPB, 1>(lds, ph, S, item, nel, FLo, RBo, UBo, o);
-  }
-}
-
-// direction of phase-3 chunk ch
-template <int EQ, int DIM, int P, int EPB>
-__device__ inline int chunk_dir(int ch) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  if constexpr (DIM == 1) return 0;
-  return ch < DIM * C::CE ? ch / C::CE : (ch - DIM * C::CE) / C::CI;
-}
-
 // ----------------------------------------------------------------------
 // phases 1-2 shared by the stage and the time-step kernels
 // ----------------------------------------------------------------------
-template <int EQ, int DIM, int P, int EPB, bool FLUX>
-__device__ inline void load_tile(double* lds, const double* __restrict__ u, long long nn, int e0,
-                                 int ne, int nx, int ny, const Phys& ph, const Bnd& bnd, double* Uown,
+
+// Halo slot h of a tile: its grid point (hi, hj) and the direction of the
+// face it serves (x-halos: h < 2 GY, left then right; y-halos: bottom then
+// top), and where its state comes from: the facing node of the
+// neighbouring element (periodic wrap), or, on an open side of the box,
+// the tile's own boundary node (ext), with the side and the boundary node's
+// index along it.
+struct Halo {
+  int hi, hj, k, side, q;
+  bool ext;
+  long long g;
+};
+template <int DIM, int P, int TX, int TY>
+__device__ inline bool halo_of(int h, const TileGeo& t, int nx, int ny, int open, Halo* r) {
+  constexpr int N1 = P + 1, NP = DIM == 2 ? N1 * N1 : N1;
+  constexpr int GX = TX * N1, GY = DIM == 2 ? TY * N1 : 1;
+  if (h < 2 * GY) {
+    const bool hiside = h >= GY;
+    const int j = hiside ? h - GY : h;
+    if (j >= (DIM == 2 ? t.th * N1 : 1)) return false;
+    const int ey = t.ey0 + (DIM == 2 ? j / N1 : 0), b = DIM == 2 ? j % N1 : 0;
+    r->hj = j;
+    r->k = 0;
+    r->side = hiside ? 1 : 0;
+    r->q = DIM == 2 ? ey * N1 + b : 0;
+    if (!hiside) {
+      r->hi = -1;
+      r->ext = (open & 1) && t.ex0 == 0;
+      const int ex = r->ext ? t.ex0 : (t.ex0 == 0 ? nx - 1 : t.ex0 - 1);
+      r->g = ((long long)ey * nx + ex) * NP + b * N1 + (r->ext ? 0 : P);
+    } else {
+      r->hi = t.tw * N1;
+      const int exh = t.ex0 + t.tw;
+      r->ext = (open & 1) && exh == nx;
+      const int ex = r->ext ? exh - 1 : (exh == nx ? 0 : exh);
+      r->g = ((long long)ey * nx + ex) * NP + b * N1 + (r->ext ? P : 0);
+    }
+    return true;
+  }
+  if constexpr (DIM == 2) {
+    const bool hiside = h >= 2 * GY + GX;
+    const int i = h - 2 * GY - (hiside ? GX : 0);
+    if (i >= t.tw * N1) return false;
+    const int ex = t.ex0 + i / N1, a = i % N1;
+    r->hi = i;
+    r->k = 1;
+    r->side = hiside ? 3 : 2;
+    r->q = ex * N1 + a;
+    if (!hiside) {
+      r->hj = -1;
+      r->ext = (open & 2) && t.ey0 == 0;
+      const int ey = r->ext ? t.ey0 : (t.ey0 == 0 ? ny - 1 : t.ey0 - 1);
+      r->g = ((long long)ey * nx + ex) * NP + (r->ext ? 0 : P * N1) + a;
+    } else {
+      r->hj = t.th * N1;
+      const int eyh = t.ey0 + t.th;
+      r->ext = (open & 2) && eyh == ny;
+      const int ey = r->ext ? eyh - 1 : (eyh == ny ? 0 : eyh);
+      r->g = ((long long)ey * nx + ex) * NP + (r->ext ? P * N1 : 0) + a;
+    }
+    return true;
+  }
+  return false;
+}
+
+// Velocity of the node at global index g (EQ_ADVV): beta_x of its node row,
+// beta_y of its node column.
+template <int DIM, int P>
+__device__ inline void field_at(long long g, int nx, const Phys& ph, double* X) {
+  constexpr int N1 = P + 1, NP = N1 * N1;
+  const int e = (int)(g / NP), s = (int)(g - (long long)e * NP);
+  const int ey = e / nx, ex = e - ey * nx;
+  X[0] = ph.vrow[ey * N1 + s / N1];
+  X[1] = ph.vcol[ex * N1 + s % N1];
+}
+
+// Phases 1-2: own nodes (one per thread, into Uown) and the halo ring
+// (threads h < NH) into the slot grid, with their auxiliaries and, with
+// FLUX, their fluxes.  Returns after the stores; the caller synchronises.
+template <int EQ, int DIM, int P, int TX, int TY, bool FLUX>
+__device__ inline void load_tile(double* lds, const double* __restrict__ u, long long nn, const TileGeo& tg,
+                                 int nx, int ny, const Phys& ph, const Bnd& bnd, double* Uown,
                                  unsigned int* bad_flag) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NT = C::NT;
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, NX = is_euler(EQ) ? 5 : C::NAUX > 0 ? C::NAUX : 1;
+  constexpr int NXW = C::NAUX;   // auxiliaries stored in the slot arrays
   const int tid = threadIdx.x;
-  const int nel = min(EPB, ne - e0);
+  const int j = tid / C::GX, i = tid - j * C::GX;
+  const int lex = i / N1, ley = DIM == 2 ? j / N1 : 0;
+  const bool own = tid < C::NOWN && lex < tg.tw && ley < tg.th;
+  const int s = DIM == 2 ? (j - ley * N1) * N1 + (i - lex * N1) : i - lex * N1;
+  const long long g = ((long long)(tg.ey0 + ley) * nx + tg.ex0 + lex) * NP + s;
+  Halo hs;
+  const bool halo = tid < C::NH && halo_of<DIM, P, TX, TY>(tid, tg, nx, ny, bnd.open, &hs);
+  // both loads in flight before any use
+  double V[NC];
+  if (own) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Uown[c] = u[c * nn + g];
+  }
+  if (halo) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) V[c] = u[c * nn + hs.g];
+  }
   bool bad = false;
-  // own nodes: one per thread, contiguous in global memory
-  if (tid < nel * NP) {
-    const int le = tid / NP, s = tid - le * NP;
-    const long long g = (long long)e0 * NP + tid;
+  if (own) {
+    const int t = C::sl(i, j);
+    double X[NX], pr = 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Uown[c] = u[c * nn + g];
-      lds[C::A_U + c * EPB * NS + le * NS + s] = Uown[c];
-    }
-  }
-  // face traces of the neighbouring elements, or exterior states on the
-  // open sides of the box
-  for (int t = tid; t < nel * NT; t += C::BS) {
-    const int le = t / NT, j = t - le * NT;
-    int side, q;
-    long long own;
-    if (bnd.open && boundary_trace<DIM, P>(e0 + le, j, nx, ny, bnd.open, &side, &q, &own)) {
-      double v[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) v[c] = u[c * nn + own];
-      const int ty = bnd.type[side][q];
-      if (ty == BC_STATE && bnd.state[side]) {
-        const int n = DIM == 1 ? 1 : (side < 2 ? ny : nx) * (P + 1);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = bnd.state[side][c * n + q];
-      } else if (ty == BC_SLIP && is_euler(EQ)) {
-        v[1 + (side >> 1)] = -v[1 + (side >> 1)];
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = v[c];
-    } else {
-      const long long g = trace_node<DIM, P>(e0 + le, j, nx, ny);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) lds[C::A_U + c * EPB * NS + le * NS + NP + j] = u[c * nn + g];
-    }
-  }
-  __syncthreads();
-  // pointwise physics on every slot: the tile's own slots first, then its
-  // face traces, so that most waves agree on forming their slot's fluxes
-  for (int i = tid; i < nel * NS; i += C::BS) {
-    int le, s;
-    if (i < nel * NP) {
-      le = i / NP;
-      s = i - le * NP;
-    } else {
-      const int j = i - nel * NP;
-      le = j / NT;
-      s = NP + (j - le * NT);
-    }
-    const int t = le * NS + s;
-    double U[NC], X[C::NAUX > 0 ? C::NAUX : 1];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) U[c] = lds[C::A_U + c * EPB * NS + t];
+    for (int c = 0; c < NC; ++c) lds[C::A_U + c * C::CSU + t] = Uown[c];
     if constexpr (is_euler(EQ)) {
       bool b;
-      euler_aux<DIM, gn_of(EQ), FLUX>(U, ph, X, b);
+      euler_aux<DIM, gn_of(EQ), FLUX>(Uown, ph, X, pr, b);
       bad |= b;
-#pragma unroll
-      for (int q = 0; q < (FLUX ? C::NAUX : C::NAUXF); ++q) lds[C::A_X + q * EPB * NS + t] = X[q];
     } else if constexpr (EQ == EQ_ADVV) {
-      // the velocity of the slot's node: beta_x of its row, beta_y of its
-      // column (own slot or face trace; an exterior state sits at the
-      // element's own face node)
-      int side, q;
-      long long g;
-      if (s < NP)
-        g = (long long)(e0 + le) * NP + s;
-      else if (!(bnd.open && boundary_trace<DIM, P>(e0 + le, s - NP, nx, ny, bnd.open, &side, &q, &g)))
-        g = trace_node<DIM, P>(e0 + le, s - NP, nx, ny);
-      const int e = (int)(g / NP), sn = (int)(g - (long long)e * NP);
-      const int ey = e / nx, ex = e - ey * nx;
-      X[0] = ph.vrow[ey * C::N1 + sn / C::N1];
-      X[1] = ph.vcol[ex * C::N1 + sn % C::N1];
-      lds[C::A_X + t] = X[0];
-      lds[C::A_X + EPB * NS + t] = X[1];
+      field_at<DIM, P>(g, nx, ph, X);
     }
+#pragma unroll
+    for (int q = 0; q < NXW; ++q) lds[C::A_X + q * C::CSU + t] = X[q];
+    if constexpr (FLUX && is_euler(EQ)) lds[C::S_AL + t] = X[4];
     if constexpr (FLUX) {
-      if (s < NP) {
+      double F[NC];
+      flux_k<EQ, DIM>(0, Uown, X, pr, ph, F);
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          double F[NC];
-          flux_k<EQ, DIM>(k, U, X, ph, F);
+      for (int c = 0; c < NC; ++c) lds[C::A_FX + c * C::CSX + C::fx(i, j)] = F[c];
+      if constexpr (DIM == 2) {
+        flux_k<EQ, DIM>(1, Uown, X, pr, ph, F);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) lds[C::A_F + (k * NC + c) * EPB * NP + le * NP + s] = F[c];
-        }
+        for (int c = 0; c < NC; ++c) lds[C::A_FY + c * C::CSY + C::fy(i, j)] = F[c];
       }
+    }
+  }
+  if (halo) {
+    if (hs.ext) {   // exterior state of an open side
+      const int ty = bnd.type[hs.side][hs.q];
+      if (ty == BC_STATE && bnd.state[hs.side]) {
+        const int n = DIM == 1 ? 1 : (hs.side < 2 ? ny : nx) * N1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) V[c] = bnd.state[hs.side][c * n + hs.q];
+      } else if (ty == BC_SLIP && is_euler(EQ)) {
+        if (hs.k == 0) V[1] = -V[1];
+        else if constexpr (DIM == 2) V[2] = -V[2];
+      }
+    }
+    const int t = C::sl(hs.hi, hs.hj);
+    double X[NX], pr = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lds[C::A_U + c * C::CSU + t] = V[c];
+    if constexpr (is_euler(EQ)) {
+      bool b;
+      euler_aux<DIM, gn_of(EQ), FLUX>(V, ph, X, pr, b);
+      bad |= b;
+    } else if constexpr (EQ == EQ_ADVV) {
+      field_at<DIM, P>(hs.g, nx, ph, X);   // an exterior state sits at the own boundary node
+    }
+#pragma unroll
+    for (int q = 0; q < NXW; ++q) lds[C::A_X + q * C::CSU + t] = X[q];
+    if constexpr (FLUX && is_euler(EQ)) lds[C::S_AL + t] = X[4];
+    if constexpr (FLUX) {
+      double F[NC];
+      flux_k<EQ, DIM>(hs.k, V, X, pr, ph, F);
+      const int o = hs.k == 0 ? C::A_FX + C::fx(hs.hi, hs.hj) : C::A_FY + C::fy(hs.hi, hs.hj);
+      const int cs = hs.k == 0 ? C::CSX : C::CSY;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) lds[o + c * cs] = F[c];
     }
   }
   if (bad && bad_flag) atomicOr(bad_flag, 1u);
@@ -724,37 +688,160 @@ __device__ inline void load_tables(double* sw, double* sq, double* siw, double* 
     for (int t = threadIdx.x; t < N1 * N1; t += nthreads) sm[t] = T.M[t];
 }
 
+// ----------------------------------------------------------------------
+// phase 3: subcell faces
+// ----------------------------------------------------------------------
+
+// Face item q of direction K, kind INT (interior subcell faces) or element
+// faces, of a tile.  Writes the low-order flux, the bar state of the
+// limited component, on interior faces the antidiffusive flux, and the
+// face's index in its face grid (o < 0: no face).
+template <int EQ, int DIM, int P, int TX, int TY, int K, bool INT>
+__device__ __forceinline__ void face_item(const double* lds, const Phys& ph, const Solve& S, int q,
+                                          const TileGeo& tg, double* FLo, double* RBo, double& UBo, int& o) {
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  constexpr int NC = C::NC, N1 = C::N1, GX = C::GX, NX = C::NAUX > 0 ? C::NAUX : 1;
+  int i, j, f = 0, el;
+  if constexpr (K == 0) {
+    const int jmax = DIM == 2 ? tg.th * N1 : 1;
+    if constexpr (INT) {
+      j = q / (TX * P);
+      const int r = q - j * (TX * P);
+      el = r / P;
+      f = r - el * P + 1;
+      i = el * N1 + f;
+      if (!(j < jmax && el < tg.tw)) return;
+    } else {
+      j = q / (TX + 1);
+      el = q - j * (TX + 1);
+      i = el * N1;
+      if (!(j < jmax && el <= tg.tw)) return;
+    }
+  } else {
+    const int r = q / GX;
+    i = q - r * GX;
+    if constexpr (INT) {
+      el = r / P;
+      f = r - el * P + 1;
+      j = el * N1 + f;
+      if (!(i < tg.tw * N1 && el < tg.th)) return;
+    } else {
+      el = r;
+      j = el * N1;
+      if (!(i < tg.tw * N1 && el <= tg.th)) return;
+    }
+  }
+  // The right state's slot is the left one's plus an offset the compiler
+  // cannot see through: it then pairs the reads of one slot's components
+  // (64 doubles apart, one ds_read2st64 and one address register each)
+  // instead of the left and right values of one component (one address
+  // register per component).
+  int dR = K == 0 ? 1 : C::RP, dF = K == 0 ? 1 : GX;
+  asm volatile("" : "+s"(dR), "+s"(dF));
+  const int sL = K == 0 ? C::sl(i, j) - 1 : C::sl(i, j) - C::RP, sR = sL + dR;
+  const double* Fg = lds + (K == 0 ? C::A_FX : C::A_FY);
+  constexpr int FS = K == 0 ? C::CSX : C::CSY;
+  const int fL = K == 0 ? C::fx(i, j) - 1 : C::fy(i, j) - GX, fR = fL + dF;
+  double UL[NC], UR[NC], FL[NC], FR[NC], XL[NX], XR[NX];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    UL[c] = lds[C::A_U + c * C::CSU + sL];
+    UR[c] = lds[C::A_U + c * C::CSU + sR];
+    FL[c] = Fg[c * FS + fL];
+    FR[c] = Fg[c * FS + fR];
+  }
+#pragma unroll
+  for (int x = 0; x < C::NAUXF; ++x) {
+    XL[x] = lds[C::A_X + x * C::CSU + sL];
+    XR[x] = lds[C::A_X + x * C::CSU + sR];
+  }
+  const double lam = lambda_k<EQ, DIM, K>(UL, XL, UR, XR, ph);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
+  const double avg = 0.5 * (UL[0] + UR[0]);
+  UBo = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
+  if constexpr (INT) {
+    // f^H of the element line through this face, and rbar = s (f^L - f^H)
+    const int tr = K == 0 ? j % N1 : i % N1;   // the line's transverse node index
+    const double sc = DIM == 2 ? lds[C::S_W + tr] * (K == 0 ? S.hy : S.hx) : 1.0;
+    const double* qr = lds + C::S_Q + (f - 1) * N1;
+    const int base = K == 0 ? C::fx(el * N1, j) : C::fy(i, el * N1);
+    constexpr int st = K == 0 ? 1 : GX;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double* Fl = Fg + c * FS + base;
+      double fh = Fl[0];
+#pragma unroll
+      for (int e = 0; e <= P; ++e) fh += qr[e] * Fl[e * st];
+      RBo[c] = sc * (FLo[c] - fh);
+    }
+  }
+  o = K == 0 ? C::ox(i, j) : C::oy(i, j);
+}
+
+// Phase-3 chunk ch (wave-uniform) of a tile: element faces of x, then of
+// y, then interior faces of x and of y; the lane picks the item within
+// the chunk.
+template <int EQ, int DIM, int P, int TX, int TY>
+__device__ __forceinline__ void face_chunk(const double* lds, const Phys& ph, const Solve& S, int ch, int lane,
+                                           const TileGeo& tg, double* FLo, double* RBo, double& UBo, int& o) {
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  if (ch < C::CEX) {
+    face_item<EQ, DIM, P, TX, TY, 0, false>(lds, ph, S, ch * 64 + lane, tg, FLo, RBo, UBo, o);
+  } else if (ch < C::CEX + C::CEY) {
+    if constexpr (DIM == 2)
+      face_item<EQ, DIM, P, TX, TY, 1, false>(lds, ph, S, (ch - C::CEX) * 64 + lane, tg, FLo, RBo, UBo, o);
+  } else if (ch < C::CEX + C::CEY + C::CIX) {
+    face_item<EQ, DIM, P, TX, TY, 0, true>(lds, ph, S, (ch - C::CEX - C::CEY) * 64 + lane, tg, FLo, RBo, UBo,
+                                          o);
+  } else if (ch < C::NCHUNK) {
+    if constexpr (DIM == 2)
+      face_item<EQ, DIM, P, TX, TY, 1, true>(lds, ph, S, (ch - C::CEX - C::CEY - C::CIX) * 64 + lane, tg, FLo,
+                                            RBo, UBo, o);
+  }
+}
+
+// direction of phase-3 chunk ch
+template <int EQ, int DIM, int P, int TX, int TY>
+__device__ inline int chunk_dir(int ch) {
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  if constexpr (DIM == 1) return 0;
+  return (ch >= C::CEX && ch < C::CEX + C::CEY) || ch >= C::CEX + C::CEY + C::CIX ? 1 : 0;
+}
+
 // Subcell-resolution smoothness factor of every element of the tile
-// (Sec. 4.4) from the limited component in LDS (own slots): modal
+// (Sec. 4.4) from the limited component in the slot grid: modal
 // coefficients c = M u (tensor product in 2-D), the energy fraction of the
 // modes of degree p in any variable, s_K = log10 of it and eps_K on the
 // ramp 1/2 + 1/2 sin(pi (s_K - s0)/2) between s0 - 1 (0) and s0 + 1 (1).
 // An element whose polynomial is zero is smooth (0).  Uses scr (2-D:
-// 2 EPB (p+1) + EPB doubles, 1-D: EPB) as scratch; returns the factor of the
+// 2 NE (p+1) + NE doubles, 1-D: NE) as scratch; returns the factor of the
 // calling thread's element (own nodes), 1 for the others.  Sums run in a
 // fixed order, so the result does not depend on the launch.
-template <int DIM, int P, int EPB, int NS, int BS>
+template <int EQ, int DIM, int P, int TX, int TY>
 __device__ inline double smoothness_tile(const double* u0, const double* M, const double* nk, double s0,
-                                         int nel, double* scr) {
+                                         const TileGeo& tg, double* scr) {
   // no multiply-add contraction: the result must not depend on how the
   // kernel that inlines this is compiled (plain and batched agree bitwise)
 #pragma clang fp contract(off)
-  constexpr int N1 = P + 1, NP = DIM == 2 ? N1 * N1 : N1;
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  constexpr int N1 = P + 1, NP = C::NP, NE = C::NE;
   const int tid = threadIdx.x;
-  double* tot_h = scr;                                  // [2][EPB*N1] row sums (2-D)
-  double* eps_e = scr + (DIM == 2 ? 2 * EPB * N1 : 0);  // [EPB]
+  double* tot_h = scr;                                 // [2][NE*N1] row sums (2-D)
+  double* eps_e = scr + (DIM == 2 ? 2 * NE * N1 : 0);  // [NE]
+  auto valid = [&](int le) { return le < NE && le % TX < tg.tw && le / TX < tg.th; };
+  auto at = [&](int le, int a, int b) { return u0[C::sl((le % TX) * N1 + a, (le / TX) * N1 + b)]; };
   if constexpr (DIM == 2) {
     // thread (element, x-mode k): the k-th x-modes of every row, then their
     // y-transforms, squared and weighted
-    if (tid < nel * N1) {
+    if (tid < NE * N1 && valid(tid / N1)) {
       const int le = tid / N1, k = tid - le * N1;
-      const double* ue = u0 + le * NS;
       double t[N1];
 #pragma unroll
       for (int b = 0; b < N1; ++b) {
         double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < N1; ++a) acc += M[k * N1 + a] * ue[b * N1 + a];
+        for (int a = 0; a < N1; ++a) acc += M[k * N1 + a] * at(le, a, b);
         t[b] = acc;
       }
       double tot = 0.0, hi = 0.0;
@@ -768,25 +855,24 @@ __device__ inline double smoothness_tile(const double* u0, const double* M, cons
         if (k == P || l == P) hi += e;
       }
       tot_h[tid] = tot;
-      tot_h[EPB * N1 + tid] = hi;
+      tot_h[NE * N1 + tid] = hi;
     }
     __syncthreads();
   }
-  if (tid < nel) {
+  if (valid(tid)) {
     double tot = 0.0, hi = 0.0;
     if constexpr (DIM == 2) {
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         tot += tot_h[tid * N1 + k];
-        hi += tot_h[EPB * N1 + tid * N1 + k];
+        hi += tot_h[NE * N1 + tid * N1 + k];
       }
     } else {
-      const double* ue = u0 + tid * NS;
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         double c = 0.0;
 #pragma unroll
-        for (int a = 0; a < N1; ++a) c += M[k * N1 + a] * ue[a];
+        for (int a = 0; a < N1; ++a) c += M[k * N1 + a] * at(tid, a, 0);
         const double e = c * c * nk[k];
         tot += e;
         if (k == P) hi += e;
@@ -800,74 +886,79 @@ __device__ inline double smoothness_tile(const double* u0, const double* M, cons
     eps_e[tid] = eps;
   }
   __syncthreads();
-  return tid < nel * NP ? eps_e[tid / NP] : 1.0;
+  const int j = tid / C::GX, i = tid - j * C::GX;
+  return tid < C::NOWN ? eps_e[(DIM == 2 ? (j / N1) * TX : 0) + i / N1] : 1.0;
 }
 
 // ----------------------------------------------------------------------
 // the fused stage kernel
 // ----------------------------------------------------------------------
-// One tile of EPB elements of one solve, run by one workgroup of C::BS
-// threads on C::LDS doubles of LDS, with the degree tables T.  Shared by
-// the plain kernel (the tiles of one solve) and the batched work-list
-// kernel (the tiles of every solve of one degree).
-template <int EQ, int DIM, int P, int EPB>
+// One tile of one solve, run by one workgroup of C::BS threads on C::LDS
+// doubles of LDS, with the degree tables T.  Shared by the plain kernel
+// (the tiles of one solve) and the batched work-list kernel (the tiles of
+// every solve of one degree).
+template <int EQ, int DIM, int P, int TX, int TY>
 __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, const Tables& T, const Bnd& bnd,
                                            int tile) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
-  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, GX = C::GX;
   const int tid = threadIdx.x;
   const Solve& S = A.S;
-  const int e0 = tile * EPB;
-  if (e0 >= S.ne) return;  // whole workgroup
-  const int nel = min(EPB, S.ne - e0);
+  const TileGeo tg = tile_geo<DIM, TX, TY>(tile, S.ntx, S.nx, S.ny);
+  if (tg.tw <= 0 || tg.th <= 0) return;  // whole workgroup
   const long long nn = S.nn;
 
   double dt = S.dt_dev ? S.dt_scale * S.dt_dev[0] : S.dt;
   if (!(dt < INFINITY)) dt = 0.0;  // no dissipation anywhere: nothing moves
 
+  // the calling thread's own node: grid point (i, j) in row-major order
+  // (consecutive lanes read consecutive LDS words: no bank conflicts), in
+  // element (lex, ley) of the tile at local position (a, b)
+  const int j = tid / GX, i = tid - j * GX;
+  const int lex = i / N1, ley = DIM == 2 ? j / N1 : 0;
+  const int a = i - lex * N1, b = DIM == 2 ? j - ley * N1 : 0;
+  const int s = DIM == 2 ? b * N1 + a : a;
+  const bool own = tid < C::NOWN && lex < tg.tw && ley < tg.th;
+  const long long g = ((long long)(tg.ey0 + ley) * S.nx + tg.ex0 + lex) * NP + s;
+
   load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, lds + C::S_M, lds + C::S_NK, T, C::BS);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   double U[NC], Un[NC];
-  load_tile<EQ, DIM, P, EPB, true>(lds, S.u_s, nn, e0, S.ne, S.nx, S.ny, A.ph, bnd, U,
-                                   A.diag ? &A.diag->bad_input : nullptr);
-  const bool own = tid < nel * NP;
   if (A.use_un && own) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) Un[c] = S.u_n[c * nn + (long long)e0 * NP + tid];
+    for (int c = 0; c < NC; ++c) Un[c] = S.u_n[c * nn + g];
   }
+  load_tile<EQ, DIM, P, TX, TY, true>(lds, S.u_s, nn, tg, S.nx, S.ny, A.ph, bnd, U,
+                                      A.diag ? &A.diag->bad_input : nullptr);
   __syncthreads();
 
-  // smoothness factor of the node's element (SUBCELL_SI; p = 1 keeps the
-  // strict bounds); the nodal-alpha array is free scratch until phase 4
-  double eps = 1.0;
-  if constexpr (P > 1) {
-    static_assert(DIM == 1 || 2 * EPB * N1 + EPB <= EPB * NP, "scratch for the smoothness factor");
-    if (A.limiter == LIM_SUBCELL_SI)
-      eps = smoothness_tile<DIM, P, EPB, NS, C::BS>(lds + C::A_U, lds + C::S_M, lds + C::S_NK, T.s0, nel,
-                                                   lds + C::S_AL);
-  }
-
-  // ---- phase 3: subcell faces ----
-  // K_min over the node and its 2d face neighbours (Euler)
+  // K_min over the node and its 2d grid neighbours (Euler), from the K of
+  // every slot in the nodal-alpha array
   double kmin = INFINITY;
   if constexpr (is_euler(EQ)) {
     if (own) {
-      const int le = tid / NP, s = tid - le * NP;
-      const int a = DIM == 2 ? s % N1 : s;
-      const int b = DIM == 2 ? s / N1 : 0;
-      const double* K = lds + C::A_X + 4 * EPB * NS + le * NS;
-      kmin = K[s];
-      kmin = fmin(kmin, K[a > 0 ? s - 1 : NP + b]);
-      kmin = fmin(kmin, K[a < P ? s + 1 : NP + C::TJ + b]);
-      if constexpr (DIM == 2) {
-        kmin = fmin(kmin, K[b > 0 ? s - N1 : NP + 2 * C::TJ + a]);
-        kmin = fmin(kmin, K[b < P ? s + N1 : NP + 3 * C::TJ + a]);
-      }
+      const double* K = lds + C::S_AL;
+      const int t = C::sl(i, j);
+      kmin = fmin(K[t], fmin(K[t - 1], K[t + 1]));
+      if constexpr (DIM == 2) kmin = fmin(kmin, fmin(K[t - C::RP], K[t + C::RP]));
     }
   }
-  // one work item per subcell face of every line (element faces included,
-  // formed by both adjacent elements), in wave-uniform chunks
+
+  // smoothness factor of the node's element (SUBCELL_SI; p = 1 keeps the
+  // strict bounds); the nodal-alpha array is free scratch until phase 4
+  // once every K_min is formed
+  double eps = 1.0;
+  if constexpr (P > 1) {
+    static_assert(DIM == 1 || 2 * C::NE * N1 + C::NE <= C::NOWN, "scratch for the smoothness factor");
+    if (A.limiter == LIM_SUBCELL_SI) {
+      if constexpr (is_euler(EQ)) __syncthreads();
+      eps = smoothness_tile<EQ, DIM, P, TX, TY>(lds + C::A_U, lds + C::S_M, lds + C::S_NK, T.s0, tg,
+                                                lds + C::S_AL);
+    }
+  }
+
+  // ---- phase 3: subcell faces ----
+  // one work item per subcell face, in wave-uniform chunks
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM];
   int rO[C::NITEM];
@@ -877,36 +968,45 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     rO[it] = -1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
-    face_chunk<EQ, DIM, P, EPB>(lds, A.ph, S, wv + it * C::NW, lane, nel, rFL[it], rRB[it], rUB[it], rO[it]);
+    face_chunk<EQ, DIM, P, TX, TY>(lds, A.ph, S, wv + it * C::NW, lane, tg, rFL[it], rRB[it], rUB[it], rO[it]);
   }
   __syncthreads();  // region A is dead from here on
 #pragma unroll
   for (int it = 0; it < C::NITEM; ++it) {
-    const int k = chunk_dir<EQ, DIM, P, EPB>(wv + it * C::NW);
     const int o = rO[it];
     if (o >= 0) {
+      if (chunk_dir<EQ, DIM, P, TX, TY>(wv + it * C::NW) == 0) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        lds[C::B_FL + (k * NC + c) * EPB * NF + o] = rFL[it][c];
-        lds[C::B_RB + (k * NC + c) * EPB * NF + o] = rRB[it][c];
+        for (int c = 0; c < NC; ++c) {
+          lds[C::B_FLX + c * C::COX + o] = rFL[it][c];
+          lds[C::B_RBX + c * C::COX + o] = rRB[it][c];
+        }
+        lds[C::B_UBX + o] = rUB[it];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          lds[C::B_FLY + c * C::COY + o] = rFL[it][c];
+          lds[C::B_RBY + c * C::COY + o] = rRB[it][c];
+        }
+        lds[C::B_UBY + o] = rUB[it];
       }
-      lds[C::B_UB + k * EPB * NF + o] = rUB[it];
     }
   }
   __syncthreads();
 
   // ---- phase 4a: low-order state, bounds, Zalesak, entropy checks ----
-  const int le = tid / NP, s = tid - le * NP;
-  const int a = DIM == 2 ? s % N1 : s;
-  const int b = DIM == 2 ? s / N1 : 0;
+  // the node's faces: x-faces i, i+1 of row j; y-faces j, j+1 of column i
+  const int ox0 = C::ox(i, j), oy0 = C::oy(i, j);
+  auto FLk = [&](int k, int c, int side) -> double {
+    return k == 0 ? lds[C::B_FLX + c * C::COX + ox0 + side] : lds[C::B_FLY + c * C::COY + oy0 + side * GX];
+  };
+  auto RBk = [&](int k, int c, int side) -> double {
+    return k == 0 ? lds[C::B_RBX + c * C::COX + ox0 + side] : lds[C::B_RBY + c * C::COY + oy0 + side * GX];
+  };
+  auto UBk = [&](int k, int side) -> double {
+    return k == 0 ? lds[C::B_UBX + ox0 + side] : lds[C::B_UBY + oy0 + side * GX];
+  };
   double uL[NC], alpha = 1.0, m = 1.0;
-  int fl[DIM], fr[DIM];
-  fl[0] = le * NF + b * NFL + a;
-  fr[0] = fl[0] + 1;
-  if constexpr (DIM == 2) {
-    fl[1] = le * NF + a * NFL + b;
-    fr[1] = fl[1] + 1;
-  }
   bool lov = false;
   double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
   int search = 0, check0 = 0;   // faces of this node for the search list; check u^L first
@@ -922,17 +1022,15 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     dtm = DIM == 2 ? cx * (lds[C::S_IW + b] * S.ihy) : cx;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double d = (lds[C::B_FL + c * EPB * NF + fl[0]] - lds[C::B_FL + c * EPB * NF + fr[0]]) * cx;
-      if constexpr (DIM == 2)
-        d += (lds[C::B_FL + (NC + c) * EPB * NF + fl[1]] - lds[C::B_FL + (NC + c) * EPB * NF + fr[1]]) * cy;
+      double d = (FLk(0, c, 0) - FLk(0, c, 1)) * cx;
+      if constexpr (DIM == 2) d += (FLk(1, c, 0) - FLk(1, c, 1)) * cy;
       uL[c] = U[c] + d;
     }
     umin = U[0];
     umax = U[0];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double b1 = lds[C::B_UB + k * EPB * NF + fl[k]];
-      const double b2 = lds[C::B_UB + k * EPB * NF + fr[k]];
+      const double b1 = UBk(k, 0), b2 = UBk(k, 1);
       umin = fmin(umin, fmin(b1, b2));
       umax = fmax(umax, fmax(b1, b2));
     }
@@ -951,19 +1049,15 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       if (dt > 0.0) {
         // elementwise limiting (Sec. 4.1.2, eq. convex-provisional-
         // elementwise): the node's whole correction d = u^H - u^L, the sum
-        // of its subcell-face antidiffusive fluxes; Zalesak with that single
-        // contribution, then the entropy line search along d; the element
-        // minimum is taken in phase 5
+        // of its subcell-face antidiffusive fluxes (zero on element faces);
+        // Zalesak with that single contribution, then the entropy line
+        // search along d; the element minimum is taken in phase 5
         double d[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           double acc = 0.0;
-          const int pos[2] = {a, b};
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            if (pos[k] < P) acc += lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]];
-            if (pos[k] > 0) acc -= lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
-          }
+          for (int k = 0; k < DIM; ++k) acc += RBk(k, c, 1) - RBk(k, c, 0);
           d[c] = dtm * acc;
         }
         const double mdt = m * idt;
@@ -993,8 +1087,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       double Pp = 0.0, Pm = 0.0;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) {
-        const double cp = lds[C::B_RB + (k * NC) * EPB * NF + fr[k]];
-        const double cm = -lds[C::B_RB + (k * NC) * EPB * NF + fl[k]];
+        const double cp = RBk(k, 0, 1);
+        const double cm = -RBk(k, 0, 0);
         Pp += fmax(cp, 0.0) + fmax(cm, 0.0);
         Pm += fmin(cp, 0.0) + fmin(cm, 0.0);
       }
@@ -1030,25 +1124,26 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            rmax = fmax(rmax, fmax(fabs(lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]]),
-                                   fabs(lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]])));
+          for (int c = 0; c < NC; ++c) rmax = fmax(rmax, fmax(fabs(RBk(k, c, 0)), fabs(RBk(k, c, 1))));
         int act = 0;
         if (g2 * rmax > 1e-14 * us) {
 #pragma unroll
           for (int k = 0; k < DIM; ++k) {
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd) {
-              const int fidx = sd ? fr[k] : fl[k];
-              const double sg = sd ? 1.0 : -1.0;
-              double Pv[NC];
+              // the partial state at alpha, uL + (alpha 2d dt/m) (+-rbar): the
+              // screen only certifies with margins, so how its scale is
+              // rounded does not matter (an uncertified face is searched
+              // from the exact value at alpha)
+              double R[NC];
               bool nz = false;
 #pragma unroll
               for (int c = 0; c < NC; ++c) {
-                Pv[c] = g2 * (sg * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx]);
-                nz |= Pv[c] != 0.0;
+                R[c] = RBk(k, c, sd);
+                nz |= R[c] != 0.0;
               }
-              if (nz && !surely_admissible<DIM, gn_of(EQ)>(alpha, uL, Pv, kmin, ikg, ph_of(A)))
+              const double sc = (sd ? alpha : -alpha) * g2;
+              if (nz && !surely_admissible<DIM, gn_of(EQ)>(sc, uL, R, kmin, ikg, ph_of(A)))
                 act |= 1 << (2 * k + sd);
             }
           }
@@ -1067,7 +1162,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     __syncthreads();  // the low-order fluxes are consumed: region C may overwrite them
     if (search) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) lds[C::C_UL + c * EPB * NP + tid] = uL[c];
+      for (int c = 0; c < NC; ++c) lds[C::C_UL + c * C::CSO + tid] = uL[c];
       lds[C::C_KM + tid] = kmin;
       lds[C::C_AZ + tid] = ubound;
       int* list = reinterpret_cast<int*>(lds + C::C_LIST);
@@ -1083,27 +1178,25 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     for (int w = tid; w < nact; w += C::BS) {
       const int item = list[w];
       const int node = item >> 3, f = (item >> 1) & 3, k = f >> 1, sd = f & 1;
-      const int nle = node / NP, ns = node - nle * NP;
-      const int na = DIM == 2 ? ns % N1 : ns;
-      const int nb = DIM == 2 ? ns / N1 : 0;
+      const int nj = node / GX, ni = node - nj * GX;
+      const int na = ni % N1, nb = DIM == 2 ? nj % N1 : 0;
       const double cxn = dt * (lds[C::S_IW + na] * S.ihx);
       const double g2 = 2.0 * DIM * (DIM == 2 ? cxn * (lds[C::S_IW + nb] * S.ihy) : cxn);
-      const int fidx = k == 0 ? nle * NF + nb * NFL + na + sd : nle * NF + na * NFL + nb + sd;
+      const int nox = C::ox(ni, nj), noy = C::oy(ni, nj);
+      auto rb = [&](int kk, int c, int side) -> double {
+        return kk == 0 ? lds[C::B_RBX + c * C::COX + nox + side] : lds[C::B_RBY + c * C::COY + noy + side * GX];
+      };
       double ul[NC], Pv[NC], rmax = 0.0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        ul[c] = lds[C::C_UL + c * EPB * NP + node];
-        Pv[c] = g2 * (sd ? 1.0 : -1.0) * lds[C::B_RB + (k * NC + c) * EPB * NF + fidx];
+        ul[c] = lds[C::C_UL + c * C::CSO + node];
+        Pv[c] = g2 * (sd ? 1.0 : -1.0) * rb(k, c, sd);
       }
       // the node's largest face correction scales the search tolerance
-      const int fx = nle * NF + nb * NFL + na, fy = nle * NF + na * NFL + nb;
 #pragma unroll
       for (int kk = 0; kk < DIM; ++kk)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double* rb = lds + C::B_RB + (kk * NC + c) * EPB * NF + (kk == 0 ? fx : fy);
-          rmax = fmax(rmax, fmax(fabs(rb[0]), fabs(rb[1])));
-        }
+        for (int c = 0; c < NC; ++c) rmax = fmax(rmax, fmax(fabs(rb(kk, c, 0)), fabs(rb(kk, c, 1))));
       const double km = lds[C::C_KM + node];
       bool feasible = true;
       if (item & 1) {
@@ -1127,12 +1220,12 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     ent = is_euler(EQ) && A.limiter != LIM_TARGET && A.limiter != LIM_LOW && alpha < az_dbg;
     const bool elementwise = A.limiter == LIM_ELEMENTWISE;
     if (elementwise) {  // one coefficient per element: the minimum over its nodes
-      const double* ae = lds + C::S_AL + le * NP;
-      for (int q = 0; q < NP; ++q) alpha = fmin(alpha, ae[q]);
+      const double* ae = lds + C::S_AL + (ley * N1) * GX * (DIM == 2 ? 1 : 0) + lex * N1;
+      for (int bb = 0; bb < (DIM == 2 ? N1 : 1); ++bb)
+        for (int aa = 0; aa < N1; ++aa) alpha = fmin(alpha, ae[bb * GX + aa]);
     }
     limited = alpha < 1.0;
     if (A.trace) {
-      const long long g = (long long)e0 * NP + tid;
       A.trace[g] = umin;
       A.trace[nn + g] = umax;
       A.trace[2 * nn + g] = kmin_dbg;
@@ -1143,21 +1236,20 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 #pragma unroll
     for (int c = 0; c < NC; ++c) corr[c] = 0.0;
     const int pos[2] = {a, b};
-    const int stride[2] = {1, N1};
+    const int stride[2] = {1, GX};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       if (pos[k] < P) {
         const double ap = elementwise ? alpha : fmin(alpha, lds[C::S_AL + tid + stride[k]]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) corr[c] += ap * lds[C::B_RB + (k * NC + c) * EPB * NF + fr[k]];
+        for (int c = 0; c < NC; ++c) corr[c] += ap * RBk(k, c, 1);
       }
       if (pos[k] > 0) {
         const double am = elementwise ? alpha : fmin(alpha, lds[C::S_AL + tid - stride[k]]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) corr[c] -= am * lds[C::B_RB + (k * NC + c) * EPB * NF + fl[k]];
+        for (int c = 0; c < NC; ++c) corr[c] -= am * RBk(k, c, 0);
       }
     }
-    const long long g = (long long)e0 * NP + tid;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double fe = uL[c] + dtm * corr[c];
@@ -1167,7 +1259,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   if (A.diag) {
     const unsigned long long bl = __ballot(limited), be = __ballot(ent), bv = __ballot(lov);
     if ((tid & 63) == 0) {
-      const int slot = (blockIdx.x * (C::BS / 64) + (tid >> 6)) & (DIAG_SLOTS - 1);
+      const int slot = (blockIdx.x * C::NW + (tid >> 6)) & (DIAG_SLOTS - 1);
       if (bl) atomicAdd(&A.diag->limited[slot], (unsigned long long)__popcll(bl));
       if (be) atomicAdd(&A.diag->entropy[slot], (unsigned long long)__popcll(be));
       if (bv) atomicOr(&A.diag->lo_violation, 1u);
@@ -1175,92 +1267,94 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   }
 }
 
-template <int EQ, int DIM, int P, int EPB>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void stage_kernel(StageArgs A) {
-  __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
-  stage_tile<EQ, DIM, P, EPB>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x));
+template <int EQ, int DIM, int P, int TX, int TY>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void stage_kernel(StageArgs A) {
+  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY>::LDS];
+  stage_tile<EQ, DIM, P, TX, TY>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------
 // low-order CFL bound (eq. cfl-low): min over nodes of m_i/(2 sum dhat_ij)
 // ----------------------------------------------------------------------
-template <int EQ, int DIM, int P, int EPB>
+template <int EQ, int DIM, int P, int TX, int TY>
 struct DtCfg {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  static constexpr int L = C::A_X + C::NAUXF * EPB * C::NS;  // [DIM][EPB*NF] wave speeds
-  static constexpr int W = L + DIM * EPB * C::NF;
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  static constexpr int LX = C::A_X + C::NAUXF * C::CSU;   // wave speeds of the x-faces [NOX]
+  static constexpr int LY = LX + C::NOX;                   // of the y-faces [NOY]
+  static constexpr int W = LY + C::NOY;
   static constexpr int R = W + C::N1;
-  static constexpr int LDS = R + C::BS / 64;
-  static constexpr int CH = (EPB * C::NF + 63) / 64;   // chunks of faces per direction
+  static constexpr int LDS = R + C::NW;
+  static constexpr int CX = (C::NOX + 63) / 64;            // chunks of x-faces
+  static constexpr int CY = (C::NOY + 63) / 64;
 };
 
-// Wave speed of face w (element le, line l, position f in 0..p+1) of
-// direction K of a tile, into the time-step kernel's array.
-template <int EQ, int DIM, int P, int EPB, int K>
-__device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int w, int nel) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  using D = DtCfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL;
-  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
-  const int le = w / NF;
-  if (le >= nel) return;
-  const int fi = w - le * NF;
-  const int l = fi / NFL;
-  const int f = fi - l * NFL;
-  const int base = le * NS;
-  const int sl = base + (f == 0 ? NP + (2 * K) * C::TJ + l : own_slot<DIM, P>(K, l, f - 1));
-  const int sr = base + (f == P + 1 ? NP + (2 * K + 1) * C::TJ + l : own_slot<DIM, P>(K, l, f));
+// Wave speed of face item q of direction K of a tile into the time-step
+// kernel's arrays (every face of the tile: element faces and interior ones).
+template <int EQ, int DIM, int P, int TX, int TY, int K>
+__device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, const TileGeo& tg) {
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  using D = DtCfg<EQ, DIM, P, TX, TY>;
+  constexpr int NC = C::NC, N1 = C::N1, NX = C::NAUX > 0 ? C::NAUX : 1;
+  int i, j;
+  if constexpr (K == 0) {
+    j = q / C::FXP;
+    i = q - j * C::FXP;
+    if (!(j < (DIM == 2 ? tg.th * N1 : 1) && i <= tg.tw * N1)) return;
+  } else {
+    j = q / C::GX;
+    i = q - j * C::GX;
+    if (!(i < tg.tw * N1 && j <= tg.th * N1)) return;
+  }
+  const int sR = C::sl(i, j), sL = K == 0 ? sR - 1 : sR - C::RP;
   double UL[NC], UR[NC], XL[NX], XR[NX];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    UL[c] = lds[C::A_U + c * EPB * NS + sl];
-    UR[c] = lds[C::A_U + c * EPB * NS + sr];
+    UL[c] = lds[C::A_U + c * C::CSU + sL];
+    UR[c] = lds[C::A_U + c * C::CSU + sR];
   }
 #pragma unroll
-  for (int q = 0; q < C::NAUXF; ++q) {
-    XL[q] = lds[C::A_X + q * EPB * NS + sl];
-    XR[q] = lds[C::A_X + q * EPB * NS + sr];
+  for (int x = 0; x < C::NAUXF; ++x) {
+    XL[x] = lds[C::A_X + x * C::CSU + sL];
+    XR[x] = lds[C::A_X + x * C::CSU + sR];
   }
-  lds[D::L + K * EPB * NF + le * NF + fi] = lambda_k<EQ, DIM>(K, UL, XL, UR, XR, ph);
+  const double lam = lambda_k<EQ, DIM, K>(UL, XL, UR, XR, ph);
+  if constexpr (K == 0) lds[D::LX + C::ox(i, j)] = lam;
+  else lds[D::LY + C::oy(i, j)] = lam;
 }
 
 // the minimum of one tile into *out
-template <int EQ, int DIM, int P, int EPB>
-__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, const Bnd& bnd, int tile,
-                                           double* out) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  using D = DtCfg<EQ, DIM, P, EPB>;
-  constexpr int NC = C::NC, NS = C::NS, NP = C::NP, NF = C::NF, NFL = C::NFL, N1 = C::N1;
-  constexpr int NX = C::NAUX > 0 ? C::NAUX : 1;
+template <int EQ, int DIM, int P, int TX, int TY>
+__device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, const Bnd& bnd,
+                                           int tile, double* out) {
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  using D = DtCfg<EQ, DIM, P, TX, TY>;
+  constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, GX = C::GX;
   const int tid = threadIdx.x;
-  const int e0 = tile * EPB;
-  if (e0 >= A.ne) return;
-  const int nel = min(EPB, A.ne - e0);
+  const TileGeo tg = tile_geo<DIM, TX, TY>(tile, A.ntx, A.nx, A.ny);
+  if (tg.tw <= 0 || tg.th <= 0) return;
   for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = T.w[t];
   double U[NC];
-  load_tile<EQ, DIM, P, EPB, false>(lds, A.u, A.nn, e0, A.ne, A.nx, A.ny, A.ph, bnd, U, nullptr);
+  load_tile<EQ, DIM, P, TX, TY, false>(lds, A.u, A.nn, tg, A.nx, A.ny, A.ph, bnd, U, nullptr);
   __syncthreads();
-  // wave-uniform chunks of 64 faces of one direction (D::CH per direction)
+  // wave-uniform chunks of 64 faces of one direction
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  for (int ch = wv; ch < DIM * D::CH; ch += C::NW) {
-    const int k = ch / D::CH;
-    const int w = (ch - k * D::CH) * 64 + lane;
-    if (k == 0) dt_face<EQ, DIM, P, EPB, 0>(lds, A.ph, w, nel);
-    else if constexpr (DIM == 2) dt_face<EQ, DIM, P, EPB, 1>(lds, A.ph, w, nel);
+  for (int ch = wv; ch < D::CX + D::CY; ch += C::NW) {
+    if (ch < D::CX) dt_face<EQ, DIM, P, TX, TY, 0>(lds, A.ph, ch * 64 + lane, tg);
+    else if constexpr (DIM == 2) dt_face<EQ, DIM, P, TX, TY, 1>(lds, A.ph, (ch - D::CX) * 64 + lane, tg);
   }
   __syncthreads();
   double dti = INFINITY;
-  if (tid < nel * NP) {
-    const int le = tid / NP, s = tid - le * NP;
-    const int a = DIM == 2 ? s % N1 : s;
-    const int b = DIM == 2 ? s / N1 : 0;
+  const int j = tid / GX, i = tid - j * GX;
+  const int lex = i / N1, ley = DIM == 2 ? j / N1 : 0;
+  if (tid < C::NOWN && lex < tg.tw && ley < tg.th) {
+    const int a = i - lex * N1, b = DIM == 2 ? j - ley * N1 : 0;
     const double wa = lds[D::W + a];
     const double wb = DIM == 2 ? lds[D::W + b] : 1.0;
-    const int fx = le * NF + b * NFL + a;
-    double den = (lds[D::L + fx] + lds[D::L + fx + 1]) * (DIM == 2 ? wb * A.hy : 1.0);
+    const int o = C::ox(i, j);
+    double den = (lds[D::LX + o] + lds[D::LX + o + 1]) * (DIM == 2 ? wb * A.hy : 1.0);
     if constexpr (DIM == 2) {
-      const int fy = le * NF + a * NFL + b;
-      den += (lds[D::L + EPB * NF + fy] + lds[D::L + EPB * NF + fy + 1]) * (wa * A.hx);
+      const int oy = C::oy(i, j);
+      den += (lds[D::LY + oy] + lds[D::LY + oy + GX]) * (wa * A.hx);
     }
     const double m = DIM == 2 ? wa * wb * A.hx * A.hy : wa * A.hx;
     dti = den > 0.0 ? m / den : INFINITY;
@@ -1270,27 +1364,31 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   __syncthreads();
   if (tid == 0) {
     double v = lds[D::R];
-    for (int i = 1; i < C::BS / 64; ++i) v = fmin(v, lds[D::R + i]);
+    for (int w = 1; w < C::NW; ++w) v = fmin(v, lds[D::R + w]);
     *out = v;
   }
 }
 
-template <int EQ, int DIM, int P, int EPB>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void maxdt_kernel(MaxDtArgs A) {
-  __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
-  maxdt_tile<EQ, DIM, P, EPB>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
+template <int EQ, int DIM, int P, int TX, int TY>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void maxdt_kernel(MaxDtArgs A) {
+  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY>::LDS];
+  maxdt_tile<EQ, DIM, P, TX, TY>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
 }
 
 // ----------------------------------------------------------------------
-// elements per workgroup: variant 0 fills 64-lane multiples best
+// tile shapes (TX x TY elements) per degree: variant 0 is a new handle's,
+// variant 1 the alternative the tuner may pick
 // ----------------------------------------------------------------------
-constexpr int epb_for(int dim, int p, int variant) {
+constexpr int tile_x_for(int dim, int p, int variant) {
   if (dim == 1) return (variant == 0 ? 128 : 256) / (p + 1);
-  // shape 0 (a new handle's): the faster of the two on 2-D Euler (256^2 for
-  // p = 1..4, 40^2..128^2 for p = 3..8), measured with both shapes taking
-  // turns on the same state; shape 1 the alternative for idp_dg_tune
-  constexpr int v0[9] = {0, 16, 14, 8, 5, 7, 5, 2, 3};
-  constexpr int v1[9] = {0, 32, 7, 16, 10, 3, 2, 4, 6};
+  constexpr int v0[9] = {0, 8, 5, 4, 3, 3, 5, 2, 3};
+  constexpr int v1[9] = {0, 8, 7, 4, 5, 7, 2, 4, 2};
+  return variant == 0 ? v0[p] : v1[p];
+}
+constexpr int tile_y_for(int dim, int p, int variant) {
+  if (dim == 1) return 1;
+  constexpr int v0[9] = {0, 8, 5, 4, 3, 2, 1, 2, 1};
+  constexpr int v1[9] = {0, 4, 4, 2, 2, 1, 2, 1, 1};
   return variant == 0 ? v0[p] : v1[p];
 }
 
@@ -1304,9 +1402,9 @@ constexpr int epb_for(int dim, int p, int variant) {
 // in scalar registers; the degree tables go straight from global memory to
 // LDS.
 // ----------------------------------------------------------------------
-template <int EQ, int DIM, int P, int EPB>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel(BatchArgs B) {
-  __shared__ double lds[Cfg<EQ, DIM, P, EPB>::LDS];
+template <int EQ, int DIM, int P, int TX, int TY>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_stage_kernel(BatchArgs B) {
+  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY>::LDS];
   const int it = xcd_tile(blockIdx.x, gridDim.x);
   if (it >= B.nitems) return;
   const StageArgs* pa = B.args + B.item_solve[it];
@@ -1323,12 +1421,12 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_stage_kernel
   A.gmax = pa->gmax;
   // the boundary arrays are indexed at run time: read them where they are
   // (a copy in this local struct would move it to scratch memory)
-  stage_tile<EQ, DIM, P, EPB>(lds, A, pa->T, pa->bnd, B.item_tile[it]);
+  stage_tile<EQ, DIM, P, TX, TY>(lds, A, pa->T, pa->bnd, B.item_tile[it]);
 }
 
-template <int EQ, int DIM, int P, int EPB>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel(BatchDtArgs B) {
-  __shared__ double lds[DtCfg<EQ, DIM, P, EPB>::LDS];
+template <int EQ, int DIM, int P, int TX, int TY>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_maxdt_kernel(BatchDtArgs B) {
+  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY>::LDS];
   const int it = xcd_tile(blockIdx.x, gridDim.x);
   if (it >= B.nitems) return;
   const MaxDtArgs* pa = B.args + B.item_solve[it];
@@ -1341,61 +1439,67 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, EPB>::BS)) void batch_maxdt_kernel
   A.ny = pa->ny;
   A.ne = pa->ne;
   A.ntiles = pa->ntiles;
+  A.ntx = pa->ntx;
   A.hx = pa->hx;
   A.hy = pa->hy;
   A.ph = pa->ph;
-  maxdt_tile<EQ, DIM, P, EPB>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
+  maxdt_tile<EQ, DIM, P, TX, TY>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
 }
 
-template <int EQ, int DIM, int P, int EPB>
+template <int EQ, int DIM, int P, int TX, int TY>
 void batch_kernels_e(BatchKernels* k) {
-  k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, EPB>);
-  k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, EPB>);
-  k->block = Cfg<EQ, DIM, P, EPB>::BS;
-  k->tile_elems = EPB;
+  k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, TX, TY>);
+  k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, TX, TY>);
+  k->block = Cfg<EQ, DIM, P, TX, TY>::BS;
+  k->tile_x = TX;
+  k->tile_y = DIM == 2 ? TY : 1;
 }
 
 template <int EQ, int DIM, int P>
 void batch_kernels_t(int variant, BatchKernels* k) {
 #if IDP_NUM_VARIANTS > 1
-  if (variant == 1) return batch_kernels_e<EQ, DIM, P, epb_for(DIM, P, 1)>(k);
+  if (variant == 1)
+    return batch_kernels_e<EQ, DIM, P, tile_x_for(DIM, P, 1), tile_y_for(DIM, P, 1)>(k);
 #endif
   (void)variant;
-  batch_kernels_e<EQ, DIM, P, epb_for(DIM, P, 0)>(k);
+  batch_kernels_e<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0)>(k);
 }
 
-template <int EQ, int DIM, int P, int EPB>
+// tiles of a mesh of nx x ny elements
+inline int num_tiles(int nx, int ny, int tx, int ty) { return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty); }
+
+template <int EQ, int DIM, int P, int TX, int TY>
 hipError_t launch_stage_t(const StageArgs& a, hipStream_t s) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  const int nb = (a.S.ne + EPB - 1) / EPB;
-  hipLaunchKernelGGL((stage_kernel<EQ, DIM, P, EPB>), dim3(nb), dim3(C::BS), 0, s, a);
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  const int nb = num_tiles(a.S.nx, a.S.ny, TX, DIM == 2 ? TY : 1);
+  hipLaunchKernelGGL((stage_kernel<EQ, DIM, P, TX, TY>), dim3(nb), dim3(C::BS), 0, s, a);
   return hipGetLastError();
 }
 
-template <int EQ, int DIM, int P, int EPB>
+template <int EQ, int DIM, int P, int TX, int TY>
 hipError_t launch_maxdt_t(const MaxDtArgs& a, hipStream_t s) {
-  using C = Cfg<EQ, DIM, P, EPB>;
-  const int nb = (a.ne + EPB - 1) / EPB;
-  hipLaunchKernelGGL((maxdt_kernel<EQ, DIM, P, EPB>), dim3(nb), dim3(C::BS), 0, s, a);
+  using C = Cfg<EQ, DIM, P, TX, TY>;
+  const int nb = num_tiles(a.nx, a.ny, TX, DIM == 2 ? TY : 1);
+  hipLaunchKernelGGL((maxdt_kernel<EQ, DIM, P, TX, TY>), dim3(nb), dim3(C::BS), 0, s, a);
   return hipGetLastError();
 }
 
 template <int EQ, int DIM, int P>
 hipError_t launch_stage_v(int variant, const StageArgs& a, hipStream_t s) {
 #if IDP_NUM_VARIANTS > 1
-  if (variant == 1) return launch_stage_t<EQ, DIM, P, epb_for(DIM, P, 1)>(a, s);
+  if (variant == 1) return launch_stage_t<EQ, DIM, P, tile_x_for(DIM, P, 1), tile_y_for(DIM, P, 1)>(a, s);
 #endif
   (void)variant;
-  return launch_stage_t<EQ, DIM, P, epb_for(DIM, P, 0)>(a, s);
+  return launch_stage_t<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0)>(a, s);
 }
 
 template <int EQ, int DIM, int P>
 hipError_t launch_maxdt_v(int variant, const MaxDtArgs& a, hipStream_t s) {
 #if IDP_NUM_VARIANTS > 1
-  if (variant == 1) return launch_maxdt_t<EQ, DIM, P, epb_for(DIM, P, 1)>(a, s);
+  if (variant == 1) return launch_maxdt_t<EQ, DIM, P, tile_x_for(DIM, P, 1), tile_y_for(DIM, P, 1)>(a, s);
 #endif
   (void)variant;
-  return launch_maxdt_t<EQ, DIM, P, epb_for(DIM, P, 0)>(a, s);
+  return launch_maxdt_t<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0)>(a, s);
 }
 
 #define IDP_DEFINE_LAUNCHERS(NAME, EQ, DIM)                                              \
@@ -1425,7 +1529,10 @@ hipError_t launch_maxdt_v(int variant, const MaxDtArgs& a, hipStream_t s) {
     }                                                                                    \
     return hipErrorInvalidValue;                                                         \
   }                                                                                      \
-  int tile_elems_##NAME(int p, int variant) { return epb_for(DIM, p, variant); }         \
+  void tile_dims_##NAME(int p, int variant, int* tx, int* ty) {                          \
+    *tx = tile_x_for(DIM, p, variant);                                                   \
+    *ty = tile_y_for(DIM, p, variant);                                                   \
+  }                                                                                      \
   int batch_kernels_##NAME(int p, int variant, BatchKernels* k) {                        \
     switch (p) {                                                                         \
       case 1: batch_kernels_t<EQ, DIM, 1>(variant, k); return 0;                         \
