@@ -779,25 +779,26 @@ __device__ __forceinline__ void face_item(const double* lds, const Phys& ph, con
   o = K == 0 ? C::ox(i, j) : C::oy(i, j);
 }
 
-// Phase-3 chunk ch (wave-uniform) of a tile: element faces of x, then of
-// y, then interior faces of x and of y; the lane picks the item within
-// the chunk.
+// Phase-3 chunk ch (wave-uniform) of a tile: element faces of x, interior
+// faces of x, element faces of y, interior faces of y; the lane picks the
+// item within the chunk.  Wave w takes chunks w, w + NW, ...: at p = 4 on
+// 3 x 3 elements (eight chunks, four waves) wave 0, which also formed the
+// halo slots in phase 2, gets the two cheaper element-face chunks.
 template <int EQ, int DIM, int P, int TX, int TY>
 __device__ __forceinline__ void face_chunk(const double* lds, const Phys& ph, const Solve& S, int ch, int lane,
                                            const TileGeo& tg, double* FLo, double* RBo, double& UBo, int& o) {
   using C = Cfg<EQ, DIM, P, TX, TY>;
-  if (ch < C::CEX) {
+  constexpr int X1 = C::CEX, X2 = X1 + C::CIX, Y1 = X2 + C::CEY;
+  if (ch < X1) {
     face_item<EQ, DIM, P, TX, TY, 0, false>(lds, ph, S, ch * 64 + lane, tg, FLo, RBo, UBo, o);
-  } else if (ch < C::CEX + C::CEY) {
+  } else if (ch < X2) {
+    face_item<EQ, DIM, P, TX, TY, 0, true>(lds, ph, S, (ch - X1) * 64 + lane, tg, FLo, RBo, UBo, o);
+  } else if (ch < Y1) {
     if constexpr (DIM == 2)
-      face_item<EQ, DIM, P, TX, TY, 1, false>(lds, ph, S, (ch - C::CEX) * 64 + lane, tg, FLo, RBo, UBo, o);
-  } else if (ch < C::CEX + C::CEY + C::CIX) {
-    face_item<EQ, DIM, P, TX, TY, 0, true>(lds, ph, S, (ch - C::CEX - C::CEY) * 64 + lane, tg, FLo, RBo, UBo,
-                                          o);
+      face_item<EQ, DIM, P, TX, TY, 1, false>(lds, ph, S, (ch - X2) * 64 + lane, tg, FLo, RBo, UBo, o);
   } else if (ch < C::NCHUNK) {
     if constexpr (DIM == 2)
-      face_item<EQ, DIM, P, TX, TY, 1, true>(lds, ph, S, (ch - C::CEX - C::CEY - C::CIX) * 64 + lane, tg, FLo,
-                                            RBo, UBo, o);
+      face_item<EQ, DIM, P, TX, TY, 1, true>(lds, ph, S, (ch - Y1) * 64 + lane, tg, FLo, RBo, UBo, o);
   }
 }
 
@@ -806,7 +807,7 @@ template <int EQ, int DIM, int P, int TX, int TY>
 __device__ inline int chunk_dir(int ch) {
   using C = Cfg<EQ, DIM, P, TX, TY>;
   if constexpr (DIM == 1) return 0;
-  return (ch >= C::CEX && ch < C::CEX + C::CEY) || ch >= C::CEX + C::CEY + C::CIX ? 1 : 0;
+  return ch >= C::CEX + C::CIX ? 1 : 0;
 }
 
 // Subcell-resolution smoothness factor of every element of the tile
