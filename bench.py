@@ -80,17 +80,66 @@ def measured_valu():
     return float(v.group(1))
 
 
-def cpu_baseline(wl, dt):
-    """The oracle (single-threaded C, as it stands) on one SSP-RK3 step of
-    the same workload."""
+def cpu_model():
+    """The host's CPU model name (lscpu, else /proc/cpuinfo) and nproc."""
+    import subprocess
+    name = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                name = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    if name is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    return name, os.cpu_count()
+
+
+def cpu_baseline(threads):
+    """The oracle (plain C, as it stands; its node and element loops on
+    `threads` OpenMP threads, results independent of the count) timed on the
+    host on bounded samples of the workloads, in node-updates per second per
+    stage (3 per SSP-RK3 step):
+      - the benchmark's 256^2 p = 4 Euler state, 3 steps on `threads`
+        threads (the headline baseline);
+      - the same recipe at 64^2 (1/16 of the nodes), 3 steps on one thread;
+      - 2-D Burgers 128^2 p = 3, 3 steps on `threads` threads;
+      - 1-D advection 64 elements p = 3, its 200 steps on one thread;
+      - the 512^2 p = 4 Euler state, 1 step on `threads` threads."""
     import oracle
-    t0 = time.perf_counter()
-    oracle.step(wl.prob, wl.u0, dt)
-    el = time.perf_counter() - t0
-    return {"value": 3 * wl.prob.num_nodes / el, "unit": "DOF-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "one SSP-RK3 step (3 limited stages) of the same 256x256 p=4 Euler "
-                      "state on the host, %.1f s" % el}
+    from paper_2004_08503_amd import workloads as W
+
+    def timed(wl, steps, nthreads):
+        oracle.set_threads(nthreads)
+        dt = wl.cfl * oracle.max_dt(wl.prob, wl.u0)
+        u = wl.u0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u = oracle.step(wl.prob, u, dt)
+        el = time.perf_counter() - t0
+        return {"value": 3 * wl.prob.num_nodes * steps / el, "seconds": el, "steps": steps,
+                "threads": nthreads}
+
+    name, nproc = cpu_model()
+    try:
+        c3 = timed(W.euler_2d(), 3, threads)
+        c3_1 = timed(W.euler_2d(n=64), 3, 1)
+        c2 = timed(W.burgers_2d(), 3, threads)
+        c1 = timed(W.advection_1d(), 200, 1)
+        c3b = timed(W.euler_2d(n=512), 1, threads)
+    finally:
+        oracle.set_threads(1)
+    return {"value": c3["value"], "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "3 SSP-RK3 steps (9 limited stages) of the benchmark's 256x256 p=4 Euler "
+                      "state, %.1f s on %d OpenMP threads" % (c3["seconds"], threads),
+            "cpu_model": name, "nproc": nproc,
+            "single_thread": dict(c3_1, sample="64x64 p=4 Euler, same recipe, 3 steps"),
+            "configs": {"euler_2d_256x256_p4": c3, "burgers_2d_128x128_p3": c2,
+                        "advection_1d_64_p3": c1, "euler_2d_512x512_p4": c3b}}
 
 
 def batched_leg(steps, count=64):
@@ -242,26 +291,56 @@ def workload_legs(wl):
     return out
 
 
-def serving_leg(count, load, budget_gb=64.0, busy=None):
+def progress(msg):
+    """One line on stderr per finished leg (the JSON line stays alone on stdout)."""
+    print("bench: %s" % msg, file=sys.stderr, flush=True)
+
+
+def fifo_from_service(reqs, service):
+    """A single server taking the requests in arrival order, each for its
+    measured plain-path service time: completion = max(arrival, previous
+    completion) + service."""
+    from paper_2004_08503_amd import serve
+    t = 0.0
+    done = []
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        start = max(r.arrival, t)
+        t = start + service[r.rid]
+        done.append(serve.Done(rid=r.rid, arrival=r.arrival, admitted=start, finished=t,
+                               nodes=r.problem().num_nodes, steps=r.steps))
+    return done
+
+
+def serving_leg(count, loads, budget_gb=64.0):
     """The served workload: a seeded Poisson stream of `count` requests (half
     Burgers, half Euler; n in [16, 512], p in 2..6, 20..200 steps).  The
-    arrival rate is set for the given offered load of the plain path's own
-    capacity on this stream, measured by running the same requests back to
-    back, one at a time (or given as `busy`, seconds).  The stream then runs
-    once through the continuous-batching server and once FIFO through the
-    plain path."""
+    same requests are first run back to back through the plain path, one at
+    a time: that makespan is the plain path's capacity, and the gaps between
+    consecutive completions are each request's service time.  For each
+    offered load the arrival rate is load * count / makespan; the stream
+    runs through the continuous-batching server, and FIFO through the plain
+    path is the single-server queue over the measured service times."""
     from paper_2004_08503_amd import serve, workloads as W
-    if busy is None:
-        back_to_back = W.request_stream(count, rate=1e9, seed=5)
-        busy = serve.summarize(serve.run_fifo_plain(back_to_back))["makespan_s"]
-    rate = load * count / busy
-    reqs = W.request_stream(count, rate=rate, seed=5)
-    srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
-    served = serve.summarize(srv.run(reqs))
-    fifo = serve.summarize(serve.run_fifo_plain(reqs))
-    return {"workload": "served_stream_%d_requests_burgers_euler_n16-512_p2-6_steps20-200" % count,
-            "offered_load": load, "plain_service_s": busy, "rate_per_s": rate,
-            "hbm_budget_gb": budget_gb, "served": served, "fifo_plain": fifo}
+    back_to_back = W.request_stream(count, rate=1e9, seed=5)
+    b2b = sorted(serve.run_fifo_plain(back_to_back), key=lambda d: d.finished)
+    busy = b2b[-1].finished
+    progress("serving: %d requests back to back through the plain path, %.1f s" % (count, busy))
+    service, prev = {}, 0.0
+    for d in b2b:
+        service[d.rid] = d.finished - prev
+        prev = d.finished
+    out = {"workload": "served_stream_%d_requests_burgers_euler_n16-512_p2-6_steps20-200" % count,
+           "plain_service_s": busy, "hbm_budget_gb": budget_gb, "loads": {}}
+    for load in loads:
+        rate = load * count / busy
+        reqs = W.request_stream(count, rate=rate, seed=5)   # same requests, new arrivals
+        srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
+        served = serve.summarize(srv.run(reqs))
+        fifo = serve.summarize(fifo_from_service(reqs, service))
+        out["loads"]["%.2f" % load] = {"rate_per_s": rate, "served": served, "fifo_plain": fifo,
+                                       "p99_served_over_fifo": served["tts_s_p99"] / fifo["tts_s_p99"]}
+        progress("serving: load %.2f, makespan %.1f s" % (load, served["makespan_s"]))
+    return out
 
 
 def main():
@@ -277,14 +356,15 @@ def main():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the solid-body, double Mach and 1-D Euler legs")
     ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--serve-requests", type=int, default=100,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the served stream (0 skips the serving leg)")
-    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.95",
+                    help="offered loads of the served stream (fractions of the plain path's capacity)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads for the CPU baseline (0: all host cores, at most 16)")
     ap.add_argument("--tune", action="store_true",
                     help="run the tile-shape tuner on the benchmark solve first (default: the "
                          "tuned default shape of the degree)")
-    ap.add_argument("--serve-overload", type=float, default=1.3,
-                    help="offered load of a second served run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (4 times), the reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -319,6 +399,7 @@ def main():
     if args.tune:   # tile-shape autotuning on the workload itself (u is only read)
         sv.tune(u, cfl, reps=5)
     shape, epb = sv.tile_shape, sv.tile_elems
+    tx, ty = sv.tile_dims
 
     def step(ev=None):
         if ev is not None:
@@ -379,7 +460,7 @@ def main():
                    "elements": prob.nx * prob.ny, "p": prob.p, "nodes": nn, "components": prob.nc,
                    "cfl": cfl, "limiter": "subcell convex (density Zalesak + entropy)",
                    "path": "plain (one solve per launch)", "parallelism": "single GPU",
-                   "tile_shape": shape, "elements_per_workgroup": epb},
+                   "tile_shape": shape, "tile_elements": [tx, ty], "elements_per_workgroup": epb},
         "stage_ms_p50": float(np.percentile(stage_ms, 50)),
         "stage_ms_p99": float(np.percentile(stage_ms, 99)),
         "maxdt_ms_mean": float(ms[:, 0].mean()),
@@ -391,7 +472,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "stage_kernel<EULER75,2,%d,%d>" % (prob.p, epb),
+                     "kernel": "stage_kernel<EULER75,2,%d,%d,%d>" % (prob.p, tx, ty),
                      "algorithmic_bytes_per_node_stage": float(bytes_stage.mean() / nn),
                      # the kernel is bound by VALU issue, not HBM: at least 4 cycles
                      # per counted wave64 instruction over the SIMDs' cycles in
@@ -401,6 +482,7 @@ def main():
     }
     sv.close()
     del u, b1, b2
+    progress("headline leg: stage p50 %.4f ms" % out["stage_ms_p50"])
     # the other limiter modes on the same workload (the smoothness-indicator
     # mode with the initial density range as global bounds)
     rho0 = wl.u0[0]
@@ -411,17 +493,20 @@ def main():
         "target_only": mode_leg(wl, prob.replace(limiter=W.TARGET), 50),
         "low_only": mode_leg(wl, prob.replace(limiter=W.LOW), 50),
     }
+    progress("limiter modes done")
     if not args.no_workloads:
         out["workloads"] = workload_legs(wl)
+        progress("workload legs done")
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_steps)
+        progress("batched leg done")
     if args.serve_requests > 0:
-        out["serving"] = serving_leg(args.serve_requests, args.serve_load)
-        if args.serve_overload > 0:   # the same stream arriving faster than the plain path serves it
-            out["serving_overload"] = serving_leg(args.serve_requests, args.serve_overload,
-                                                  busy=out["serving"]["plain_service_s"])
+        out["serving"] = serving_leg(args.serve_requests,
+                                     [float(x) for x in args.serve_loads.split(",") if x])
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, dt_last)
+        threads = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(threads)
+        progress("cpu baseline done")
     print(json.dumps(out))
 
 

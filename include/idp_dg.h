@@ -261,11 +261,11 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
                     double* u_out, const double* dt_dev, double cfl, int stage);
 
 /* Tile-shape autotuning.  The stage and time-step kernels are compiled
- * for IDP_DG_NUM_TILE_SHAPES shapes per degree (elements per workgroup);
- * a new handle uses shape 0, the faster of the two on 2-D Euler (256^2 for
- * p = 1..4, 40^2..128^2 for p = 3..8) and on 1-D Euler (2^20 elements,
- * p = 1 and 3).  Every shape gives bitwise the same results: the same
- * arithmetic per node, only grouped differently into workgroups.
+ * for IDP_DG_NUM_TILE_SHAPES tile shapes per degree: a workgroup owns a
+ * tile of tx x ty elements (tx in 1-D) and evaluates every subcell face of
+ * the tile once.  A new handle uses shape 0.  Every shape gives bitwise the
+ * same results: a face's and a node's arithmetic does not depend on which
+ * tile, workgroup or launch runs it.
  *
  * idp_dg_tune times `reps` (1..100) device-timestepped SSP-RK3 steps (as
  * idp_dg_step_cfl; cfl > 0) of the device state u under each shape, the
@@ -287,6 +287,9 @@ int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape);
 int idp_dg_tile_shape(const idp_dg* h);
 /* Elements per workgroup of the current tile shape (-1 for NULL). */
 int idp_dg_tile_elems(const idp_dg* h);
+/* The current tile shape's elements per tile in x (*tx) and y (*ty; 1 in
+ * 1-D).  Returns 0, or IDP_DG_EINVAL for a NULL argument. */
+int idp_dg_tile_dims(const idp_dg* h, int* tx, int* ty);
 int idp_dg_set_tile_shape(idp_dg* h, int shape);
 
 /* Copy out and reset the diagnostics (synchronises the stream). */

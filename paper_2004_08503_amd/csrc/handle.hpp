@@ -48,6 +48,7 @@ struct idp_dg {
 namespace idp_host {
 int family(const idp_dg* h);
 int tile_elems(const idp_dg* h);
+void tile_dims(const idp_dg* h, int* tx, int* ty);
 // tiles of the handle's mesh; *ntx receives the tiles per row of tiles
 int tiles_of(const idp_dg* h, int* ntx);
 idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s, double* u_out,

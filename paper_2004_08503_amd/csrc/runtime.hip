@@ -748,6 +748,12 @@ int idp_dg_tile_shape(const idp_dg* h) { return h ? h->variant : -1; }
 
 int idp_dg_tile_elems(const idp_dg* h) { return h ? tile_elems(h) : -1; }
 
+int idp_dg_tile_dims(const idp_dg* h, int* tx, int* ty) {
+  if (!h || !tx || !ty) return IDP_DG_EINVAL;
+  tile_dims(h, tx, ty);
+  return 0;
+}
+
 int idp_dg_set_tile_shape(idp_dg* h, int shape) {
   if (!h) return IDP_DG_EINVAL;
   if (shape < 0 || shape >= kNumVariants) return fail(h, IDP_DG_EINVAL, "tile shape out of range");

@@ -62,6 +62,7 @@ def _declare(lib):
         "idp_dg_tune": (ctypes.c_int, [H, _VP, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "idp_dg_tile_shape": (ctypes.c_int, [H]),
         "idp_dg_tile_elems": (ctypes.c_int, [H]),
+        "idp_dg_tile_dims": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "idp_dg_set_tile_shape": (ctypes.c_int, [H, ctypes.c_int]),
         "idp_dg_batch_tune": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
@@ -322,6 +323,13 @@ class Solver:
     def tile_elems(self):
         """Elements per workgroup of the current tile shape."""
         return lib.idp_dg_tile_elems(self._h)
+
+    @property
+    def tile_dims(self):
+        """(elements per tile in x, in y) of the current tile shape."""
+        tx, ty = ctypes.c_int(), ctypes.c_int()
+        self._check(lib.idp_dg_tile_dims(self._h, ctypes.byref(tx), ctypes.byref(ty)))
+        return tx.value, ty.value
 
     def set_tile_shape(self, shape):
         self._check(lib.idp_dg_set_tile_shape(self._h, int(shape)))

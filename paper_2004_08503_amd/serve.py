@@ -53,8 +53,15 @@ class Done:
 
 
 def footprint_bytes(req: Request) -> int:
+    """Device bytes a served request holds: its state and the workspace of
+    its handle as Solver(workspace=True) allocates it (the library's
+    workspace size for the problem plus 256 bytes of alignment slack)."""
+    import ctypes
     prob = req.problem()
-    return 3 * 8 * prob.nc * prob.num_nodes + 4096
+    ws = idp_dg.lib.idp_dg_workspace_bytes(ctypes.byref(idp_dg.make_desc(prob)))
+    if ws < 0:
+        raise ValueError("bad request problem: %s" % idp_dg.lib.idp_dg_last_error(None).decode())
+    return 8 * prob.nc * prob.num_nodes + ws + 256
 
 
 class Server:
@@ -92,6 +99,7 @@ class Server:
         dirty = set()                      # families whose membership changed
         ends: Dict[int, List[int]] = {}    # tick -> requests whose last step it is
         tick = 0
+        self.peak_used = 0                 # most device bytes admitted at once
         finishing = []                     # (request record, end event)
         out: List[Done] = []
         torch.cuda.synchronize()
@@ -128,6 +136,7 @@ class Server:
                                    "large": 0 if small else prob.num_nodes,
                                    "admitted": time.perf_counter() - t0}
                 used += fp
+                self.peak_used = max(self.peak_used, used)
                 large += active[req.rid]["large"]
                 ends.setdefault(tick + req.steps - 1, []).append(req.rid)
                 dirty.add(fam)

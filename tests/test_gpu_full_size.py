@@ -1,5 +1,11 @@
-"""The two configurations besides the benchmark's 256^2 p = 4 Euler case
-(which has its own full-size test), at their full sizes:
+"""The configurations at their full sizes:
+
+- the benchmark's 2-D Euler workload, 256^2 elements, p = 4 (1.64 M
+  nodes), over its whole run of 50 device-timestepped SSP-RK3 steps at
+  CFL 1/2, against the oracle stepped with the device's time steps: every
+  step's time step to 1e-12 and every node after 50 steps to 1e-9 (the
+  oracle's loops run on all host cores; its results do not depend on the
+  thread count);
 
 - 2-D Burgers on a 128^2 mesh, p = 3 (262 144 nodes), 100 device-timestepped
   SSP-RK3 steps at CFL 1/2 against the oracle stepped with the same time
@@ -48,6 +54,32 @@ def test_burgers_128_p3_full_run():
     sv.close()
     err = rel_err(u.cpu().numpy(), ref)
     print("Burgers 128^2 p = 3, 100 steps: max relative error %.2e" % err)
+    assert err <= 1e-9, err
+
+
+def test_euler_256_p4_full_run():
+    idp_dg = _gpu()
+    import os
+    wl = W.euler_2d()
+    prob = wl.prob
+    assert (prob.nx, prob.ny, prob.p, wl.steps) == (256, 256, 4, 50)
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(prob)
+        u = torch.from_numpy(wl.u0.copy()).cuda()
+        ref = wl.u0.copy()
+        for n in range(wl.steps):
+            sv.step_cfl(u, wl.cfl)
+            dt = sv.last_dt()
+            assert dt == pytest.approx(wl.cfl * oracle.max_dt(prob, ref), rel=1e-12)
+            ref = oracle.step(prob, ref, dt)
+            if n % 10 == 9:
+                print("Euler 256^2 p = 4: step %d of %d" % (n + 1, wl.steps), flush=True)
+        sv.close()
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(u.cpu().numpy(), ref)
+    print("Euler 256^2 p = 4, 50 steps: max relative error %.2e" % err)
     assert err <= 1e-9, err
 
 

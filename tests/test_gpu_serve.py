@@ -1,7 +1,12 @@
 """Serving loop: requests that arrive while others run are admitted by HBM
 footprint and co-batched; every result must be bitwise the same as the
-request solved alone through the plain path."""
+request solved alone through the plain path, and a request of each family
+(Burgers, Euler) served in the mix must match the oracle stepped with the
+same CFL time steps (1e-9, the multi-step parity bar)."""
+import numpy as np
 import pytest
+
+import oracle
 
 from paper_2004_08503_amd import workloads as W
 
@@ -34,11 +39,43 @@ def test_served_results_equal_alone(budget_mb):
     srv = serve.Server(hbm_budget=budget_mb * 2 ** 20, keep_results=True)
     done = srv.run(reqs)
     assert [d.rid for d in done] == [r.rid for r in reqs]
+    # admission counted what a request really holds (state, handle workspace,
+    # alignment slack), and never more than the budget at once
+    assert srv.peak_used <= budget_mb * 2 ** 20
+    for r in reqs:
+        prob = r.problem()
+        sv = idp_dg.Solver(prob, workspace=True)
+        held = sv._ws.numel() + 8 * prob.nc * prob.num_nodes
+        sv.close()
+        assert serve.footprint_bytes(r) == held
     for d, r in zip(done, reqs):
         assert d.finished >= d.arrival - 1e-3
         assert torch.equal(d.result, alone(idp_dg, r)), r
     s = serve.summarize(done)
     assert s["tts_s_p99"] >= s["tts_s_p50"] > 0
+
+
+def test_served_results_match_the_oracle():
+    idp_dg, serve = _mods()
+    reqs = W.request_stream(8, rate=600.0, n_range=(4, 10), p_range=(2, 4),
+                            steps_range=(3, 8), seed=23)
+    kinds = {r.kind for r in reqs}
+    assert kinds == {"euler", "burgers"}
+    done = serve.Server(hbm_budget=4096 * 2 ** 20, keep_results=True).run(reqs)
+    checked = set()
+    for d, r in zip(done, reqs):
+        if r.kind in checked:
+            continue
+        checked.add(r.kind)
+        prob = r.problem()
+        ref = W.initial_state_device(r).cpu().numpy()
+        for _ in range(r.steps):
+            ref = oracle.step(prob, ref, 0.5 * oracle.max_dt(prob, ref))
+        got = d.result.numpy().reshape(ref.shape)
+        err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+        print("served %s %d^2 p=%d, %d steps: max relative error %.2e" % (r.kind, r.n, r.p, r.steps, err))
+        assert err <= 1e-9, (r, err)
+    assert checked == kinds
 
 
 @pytest.mark.parametrize("caps", [dict(max_active_nodes=700), dict(max_active=1), dict(max_active_nodes=0),
