@@ -33,7 +33,7 @@ from typing import Dict, List
 
 import numpy as np
 
-from . import idp_dg
+from . import idp_dg, tuning
 from .workloads import Request, initial_state_device
 
 
@@ -83,6 +83,7 @@ class Server:
         self.cfl = cfl
         self.keep = keep_results
         self.stream = torch.cuda.current_stream()
+        self.table = tuning.load_table()   # tile shapes measured on this device, if any
 
     def _clock_ms(self, ev):
         return self.ref.elapsed_time(ev) * 1e-3
@@ -130,6 +131,8 @@ class Server:
                     keep.append(req)
                     continue
                 sv = idp_dg.Solver(prob, stream=self.stream, workspace=True)
+                if self.table:
+                    tuning.apply_solver(sv, self.table)
                 u = initial_state_device(req)
                 fam = idp_dg.family_of(prob)
                 active[req.rid] = {"req": req, "sv": sv, "u": u, "fam": fam, "fp": fp,
@@ -215,6 +218,7 @@ def run_fifo_plain(requests: List[Request], cfl: float = 0.5, keep_results: bool
     """The same stream, one request at a time through the plain path."""
     import torch
     stream = torch.cuda.current_stream()
+    table = tuning.load_table()
     torch.cuda.synchronize()
     ref = torch.cuda.Event(enable_timing=True)
     ref.record(stream)
@@ -226,6 +230,8 @@ def run_fifo_plain(requests: List[Request], cfl: float = 0.5, keep_results: bool
             time.sleep(wait)
         admitted = time.perf_counter() - t0
         sv = idp_dg.Solver(req.problem(), stream=stream, workspace=True)
+        if table:
+            tuning.apply_solver(sv, table)
         u = initial_state_device(req)
         for _ in range(req.steps):
             sv.step_cfl(u, cfl)
