@@ -303,8 +303,7 @@ const char* idp_dg_last_error(const idp_dg* h);
 /* Batched execution: many independent solves of uneven mesh size and  */
 /* degree advance together.  Per degree present, one work-list launch  */
 /* per RK stage covers the element tiles of all solves of that degree; */
-/* a step is one HIP graph whose degree groups run as parallel         */
-/* branches.                                                           */
+/* the launches of a step go directly to the batch's stream.          */
 /* ------------------------------------------------------------------ */
 
 typedef struct idp_dg_batch idp_dg_batch;
@@ -334,8 +333,8 @@ int idp_dg_batch_num_items(const idp_dg_batch* b);
 int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt);
 
 /* One step of every solve with dt_i = cfl * (CFL bound of u[i]) computed
- * on the device; the launches replay from a HIP graph cached for the
- * pointer set and cfl.  Bitwise identical to idp_dg_step_cfl per solve. */
+ * on the device (no host synchronisation).  Bitwise identical to
+ * idp_dg_step_cfl per solve. */
 int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl);
 
 /* Tile shape per degree for the batch: each degree's work-list kernels

@@ -10,10 +10,14 @@
 // ranges) lives in one device blob that is rewritten by a single
 // asynchronous copy from a pinned staging ring whenever the membership, the
 // state pointers or the time-step mode change, so changing a batch never
-// synchronises the host with the device.  While a configuration keeps
-// changing the kernels are launched directly; once the same configuration
-// is stepped twice in a row its step is captured as a HIP graph (the
-// degree groups of a stage as parallel branches) and replayed.
+// synchronises the host with the device.  The kernels of a step are
+// launched directly on the batch's stream (a few launches per degree
+// present; at the batch sizes this path is for, the launches cost well
+// under one per cent of a step).  A batch does not capture its step as a
+// HIP graph: capturing on repeated configurations and retiring the graph
+// on every membership change (with its launch still queued) is the one
+// pattern common to the host aborts seen under serving loads, whose cause
+// in the runtime or in this code is not established.
 //
 // Results are bitwise identical to the plain path: a tile's arithmetic does
 // not depend on which workgroup or launch runs it, and the only reductions
@@ -69,13 +73,6 @@ struct idp_dg_batch {
   std::vector<unsigned> cur_bv;    // the solves' boundary versions
   double cur_scale = -1.0;
   int cur_mode = -1;               // 0: host time steps, 1: device bounds
-  // reuse of the previous configuration's step as a graph
-  int repeats = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipEvent_t graph_done = nullptr;  // recorded after every launch of exec
-  int graph_mode = -1;
-  std::vector<RetiredGraph> retired;
   std::string err = "no error";
 };
 
@@ -90,17 +87,6 @@ int bfail(idp_dg_batch* b, int code, const std::string& msg) {
 
 int bhip(idp_dg_batch* b, hipError_t e, const char* where) {
   return bfail(b, IDP_DG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
-}
-
-void drop_batch_graph(idp_dg_batch* b) {
-  retire_graph(&b->retired, &b->graph, &b->exec, &b->graph_done);
-  b->graph_mode = -1;
-}
-
-hipError_t launch_graph(idp_dg_batch* b) {
-  hipError_t e = hipGraphLaunch(b->exec, b->stream);
-  if (e == hipSuccess) e = hipEventRecord(b->graph_done, b->stream);
-  return e;
 }
 
 bool overlap(const double* a, long long na, const double* c, long long nc) {
@@ -226,18 +212,13 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
   b->cur_mode = mode;
   b->cur_scale = scale;
   b->dirty = false;
-  drop_batch_graph(b);
-  b->repeats = 0;
   return 0;
 }
 
 int prepare(idp_dg_batch* b, double* const* u, int mode, double scale) {
   bool same = !b->dirty && b->cur_mode == mode && b->cur_scale == scale;
   for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i] && b->cur_bv[i] == b->s[i]->bnd_version;
-  if (same) {
-    ++b->repeats;
-    return 0;
-  }
+  if (same) return 0;
   return upload(b, u, mode, scale);
 }
 
@@ -260,75 +241,36 @@ BatchDtArgs group_dt_args(const idp_dg_batch* b, const BatchGroup& gr) {
   return a;
 }
 
-// The launches of one step, enqueued directly on s, or added to graph g
-// with every stage depending on all launches of the one before.
-hipError_t emit_step(idp_dg_batch* b, bool device_dt, hipStream_t s, hipGraph_t g) {
-  std::vector<hipGraphNode_t> prev, cur;
-  auto launch = [&](const void* func, dim3 grid, dim3 block, void** args) -> hipError_t {
-    if (!g) return hipLaunchKernel(func, grid, block, args, 0, s);
-    hipKernelNodeParams kp;
-    std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void*>(func);
-    kp.gridDim = grid;
-    kp.blockDim = block;
-    kp.kernelParams = args;
-    hipGraphNode_t nd;
-    hipError_t e = hipGraphAddKernelNode(&nd, g, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
-    if (e == hipSuccess) cur.push_back(nd);
-    return e;
-  };
-  auto frontier = [&]() {
-    prev.swap(cur);
-    cur.clear();
-  };
+// The launches of one step on the batch's stream: per stage, every degree
+// group's work-list kernel (stream order puts each stage after the one
+// before).
+hipError_t run_step(idp_dg_batch* b, int mode) {
+  if (b->nitems == 0) return hipSuccess;
   hipError_t e = hipSuccess;
-  if (device_dt) {
+  if (mode == 1) {
     for (const BatchGroup& gr : b->groups) {
       BatchDtArgs a = group_dt_args(b, gr);
       void* args[] = {&a};
-      e = launch(gr.k.maxdt, dim3(gr.nitems), dim3(gr.k.block), args);
+      e = hipLaunchKernel(gr.k.maxdt, dim3(gr.nitems), dim3(gr.k.block), args, 0, b->stream);
       if (e != hipSuccess) return e;
     }
-    frontier();
     const double* part = at<double>(b->d_blob, b->o_partial);
     const int* range = at<int>(b->d_blob, b->o_range);
     double* out = at<double>(b->d_blob, b->o_dt) + b->n;
     void* args[] = {&part, &range, &out};
-    e = launch(reinterpret_cast<const void*>(&segmented_min_kernel), dim3(b->n), dim3(256), args);
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&segmented_min_kernel), dim3(b->n), dim3(256), args, 0,
+                        b->stream);
     if (e != hipSuccess) return e;
-    frontier();
   }
   for (int st = 0; st < 3; ++st) {
     for (const BatchGroup& gr : b->groups) {
       BatchArgs a = group_args(b, gr, st);
       void* args[] = {&a};
-      e = launch(gr.k.stage, dim3(gr.nitems), dim3(gr.k.block), args);
+      e = hipLaunchKernel(gr.k.stage, dim3(gr.nitems), dim3(gr.k.block), args, 0, b->stream);
       if (e != hipSuccess) return e;
     }
-    frontier();
   }
   return hipSuccess;
-}
-
-hipError_t run_step(idp_dg_batch* b, int mode) {
-  if (b->nitems == 0) return hipSuccess;
-  if (b->exec && b->graph_mode == mode) return launch_graph(b);
-  if (b->repeats >= 1) {  // the same configuration again: capture it
-    drop_batch_graph(b);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipGraphCreate(&g, 0);
-    if (e == hipSuccess) e = emit_step(b, mode == 1, nullptr, g);
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->graph_done, hipEventDisableTiming);
-    b->graph = g;
-    if (e != hipSuccess) {
-      drop_batch_graph(b);
-      return e;
-    }
-    b->graph_mode = mode;
-    return launch_graph(b);
-  }
-  return emit_step(b, mode == 1, b->stream, nullptr);
 }
 
 int check_members(idp_dg* const* solves, int n, idp_dg_batch* b) {
@@ -410,8 +352,7 @@ int idp_dg_batch_update(idp_dg_batch* b, idp_dg* const* solves, int n) {
 
 void idp_dg_batch_destroy(idp_dg_batch* b) {
   if (!b) return;
-  drop_batch_graph(b);
-  reap_graphs(&b->retired, true);
+  if (b->stream || b->d_blob) (void)hipStreamSynchronize(b->stream);   // queued steps read the blob
   for (int r = 0; r < kRing; ++r)
     if (b->ring_ev[r]) {
       (void)hipEventSynchronize(b->ring_ev[r]);

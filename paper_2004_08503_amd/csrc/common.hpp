@@ -162,6 +162,25 @@ IDP_DECLARE_LAUNCHERS(euler75_1)
 IDP_DECLARE_LAUNCHERS(euler75_2)
 IDP_DECLARE_LAUNCHERS(advv2)
 
+// min over partial[b..e) by one thread at stride BS: eight independent loads
+// in flight per wait (a single chain waits on every load; large meshes have
+// hundreds of thousands of partial minima)
+template <int BS>
+__device__ inline double strided_min(const double* __restrict__ partial, int b, int e) {
+  double v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = INFINITY;
+  int i = b + (int)threadIdx.x;
+  for (; i + 7 * BS < e; i += 8 * BS) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = fmin(v[j], partial[i + j * BS]);
+  }
+  for (; i < e; i += BS) v[0] = fmin(v[0], partial[i]);
+#pragma unroll
+  for (int j = 1; j < 8; ++j) v[0] = fmin(v[0], v[j]);
+  return v[0];
+}
+
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);
 // per solve s: min over partial[range[2s]..range[2s+1]) -> out[s] (one workgroup per solve)

@@ -374,25 +374,6 @@ hipError_t enqueue_step_cfl(idp_dg* h, double* u, double cfl, hipStream_t s) {
 }  // namespace
 
 namespace idp {
-// min over partial[b..e) by one thread at stride BS: eight independent loads
-// in flight per wait (a single chain waits on every load; large meshes have
-// hundreds of thousands of partial minima)
-template <int BS>
-__device__ inline double strided_min(const double* __restrict__ partial, int b, int e) {
-  double v[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = INFINITY;
-  int i = b + (int)threadIdx.x;
-  for (; i + 7 * BS < e; i += 8 * BS) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = fmin(v[j], partial[i + j * BS]);
-  }
-  for (; i < e; i += BS) v[0] = fmin(v[0], partial[i]);
-#pragma unroll
-  for (int j = 1; j < 8; ++j) v[0] = fmin(v[0], v[j]);
-  return v[0];
-}
-
 __global__ __launch_bounds__(256) void segmented_min_kernel(const double* partial, const int* range,
                                                              double* out) {
   __shared__ double red[4];

@@ -101,18 +101,20 @@ struct Cfg {
   // region B (aliases A): phase 3 results, read in phases 4-5
   static constexpr int B_FLX = 0;
   static constexpr int B_FLY = B_FLX + NC * COX;
-  static constexpr int B_RBX = B_FLY + NC * COY;
-  static constexpr int B_RBY = B_RBX + NC * COX;
-  static constexpr int B_UBX = B_RBY + NC * COY;
+  static constexpr int B_UBX = B_FLY + NC * COY;
   static constexpr int B_UBY = B_UBX + COX;
-  static constexpr int B_END = B_UBY + COY;
+  static constexpr int B_RBX = B_UBY + COY;
+  static constexpr int B_RBY = B_RBX + NC * COX;
+  static constexpr int B_END = B_RBY + NC * COY;
   // region C: Euler search data, written once the low-order fluxes are
   // consumed; it overwrites them where it fits
-  static constexpr int C_SIZE = is_euler(EQ) ? (NC + 2 + DIM) * CSO : 0;
-  static constexpr int C_UL = C_SIZE <= NC * (COX + COY) ? B_FLX : B_END;   // [NC][CSO]
+  static constexpr int C_SIZE = is_euler(EQ) ? (NC + 4 + DIM) * CSO : 0;
+  static constexpr int C_UL = C_SIZE <= (NC + 1) * (COX + COY) ? B_FLX : B_END;   // [NC][CSO]
   static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * CSO : 0);
   static constexpr int C_AZ = C_KM + (is_euler(EQ) ? CSO : 0);   // bound U of the node
-  static constexpr int C_LIST = C_AZ + (is_euler(EQ) ? CSO : 0);  // int[2*DIM*CSO]
+  static constexpr int C_G2 = C_AZ + (is_euler(EQ) ? CSO : 0);   // 2d dt/m of the node
+  static constexpr int C_PS = C_G2 + (is_euler(EQ) ? CSO : 0);   // largest |P| over the node's faces
+  static constexpr int C_LIST = C_PS + (is_euler(EQ) ? CSO : 0);  // int[2*DIM*CSO]
   static constexpr int C_END = C_LIST + (is_euler(EQ) ? DIM * CSO : 0);
   static constexpr int AB0 = A_END > B_END ? A_END : B_END;
   static constexpr int AB = AB0 > C_END ? AB0 : C_END;
@@ -497,6 +499,68 @@ __device__ double entropy_root(const double* uL, const double* P, double U, bool
   return lo;
 }
 
+// sup { t in [0, U] : uL + t P admissible } for one subcell face of a node
+// whose u^L is admissible, to within tol (as for entropy_root).  The first
+// point is U.  Then Newton steps from the infeasible end hi; Phi is concave
+// along the segment, so a Newton point tn lies at or above the root, and the
+// point evaluated is tn - tol/2 instead of tn: if it is admissible, the root
+// lies in [tn - tol/2, tn] and the search ends there; if not, it is the new
+// infeasible end.  Without a usable tangent, or after three Newton steps in
+// a row that do not halve, one bisection; a Newton step below tol/4 means
+// hi sits on the root, and the next points are probes under hi at tol/2,
+// doubling the distance after each inadmissible probe.
+template <int DIM, int GN>
+__device__ double entropy_root_face(const double* uL, const double* P, double U, double kmin, double pscale,
+                                    const Phys& ph) {
+  double us = 0.0, ps = pscale;
+#pragma unroll
+  for (int c = 0; c < DIM + 2; ++c) {
+    us = fmax(us, fabs(uL[c]));
+    ps = fmax(ps, fabs(P[c]));
+  }
+  const double tol = fmax(1e-15, 1e-14 * us / ps);
+  double lo = 0.0, hi = U, fhi = -INFINITY, dhi = 0.0, rhi = 0.0;
+  double t = U, prev = INFINITY, probe = 0.5 * tol;
+  int slow = 0;
+  bool below = false;   // t = tn - tol/2 under a Newton point tn
+  for (int it = 0; it < 64; ++it) {
+    const PhiVal e = phi_at<DIM, GN>(t, uL, P, kmin, ph);
+    if (admissible(e)) {
+      if (below || t >= U) return t;
+      lo = t;
+    } else {
+      hi = t;
+      fhi = e.phi;
+      dhi = e.dphi;
+      rhi = e.rho;
+    }
+    if (!(hi - lo > tol)) break;
+    below = false;
+    if (rhi > 0.0 && dhi < 0.0) {
+      const double step = fhi / dhi;  // the Newton step from hi, >= 0
+      if (step < 0.25 * tol) {        // hi sits on the root: probe under it
+        t = hi - probe;
+        probe *= 2.0;
+      } else if (slow >= 3) {
+        t = 0.5 * (lo + hi);
+        slow = 0;
+      } else {
+        t = (hi - step) - 0.5 * tol;
+        below = true;
+        slow = step > 0.5 * prev ? slow + 1 : 0;
+        prev = step;
+      }
+    } else {
+      t = 0.5 * (lo + hi);
+    }
+    if (!(t > lo && t < hi)) {
+      t = 0.5 * (lo + hi);
+      below = false;
+    }
+  }
+  return lo;
+}
+
 __device__ inline const Phys& ph_of(const StageArgs& A) { return A.ph; }
 
 // ----------------------------------------------------------------------
@@ -578,6 +642,30 @@ __device__ inline void field_at(long long g, int nx, const Phys& ph, double* X) 
   X[1] = ph.vcol[ex * N1 + s % N1];
 }
 
+// The exterior state of an open side for halo slot hs (V holds the own
+// boundary node's state on entry): the prescribed state, the own state
+// (outflow) or the own state with the normal momentum reversed (slip).  The
+// side's arrays are selected between the four pointers already loaded: an
+// index into the argument struct at run time would move it to scratch.
+template <int EQ, int DIM, int NC>
+__device__ inline void exterior_state(const Bnd& bnd, const Halo& hs, int n, double* V) {
+  const unsigned long long t0 = (unsigned long long)bnd.type[0], t1 = (unsigned long long)bnd.type[1];
+  const unsigned long long t2 = (unsigned long long)bnd.type[2], t3 = (unsigned long long)bnd.type[3];
+  const unsigned long long s0 = (unsigned long long)bnd.state[0], s1 = (unsigned long long)bnd.state[1];
+  const unsigned long long s2 = (unsigned long long)bnd.state[2], s3 = (unsigned long long)bnd.state[3];
+  const int sd = hs.side;
+  const signed char* type = (const signed char*)(sd == 0 ? t0 : sd == 1 ? t1 : sd == 2 ? t2 : t3);
+  const double* state = (const double*)(sd == 0 ? s0 : sd == 1 ? s1 : sd == 2 ? s2 : s3);
+  const int ty = type[hs.q];
+  if (ty == BC_STATE && state) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) V[c] = state[c * n + hs.q];
+  } else if (ty == BC_SLIP && is_euler(EQ)) {
+    if (hs.k == 0) V[1] = -V[1];
+    else if constexpr (DIM == 2) V[2] = -V[2];
+  }
+}
+
 // Phases 1-2: own nodes (one per thread, into Uown) and the halo ring
 // (threads h < NH) into the slot grid, with their auxiliaries and, with
 // FLUX, their fluxes.  Returns after the stores; the caller synchronises.
@@ -635,17 +723,8 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
     }
   }
   if (halo) {
-    if (hs.ext) {   // exterior state of an open side
-      const int ty = bnd.type[hs.side][hs.q];
-      if (ty == BC_STATE && bnd.state[hs.side]) {
-        const int n = DIM == 1 ? 1 : (hs.side < 2 ? ny : nx) * N1;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) V[c] = bnd.state[hs.side][c * n + hs.q];
-      } else if (ty == BC_SLIP && is_euler(EQ)) {
-        if (hs.k == 0) V[1] = -V[1];
-        else if constexpr (DIM == 2) V[2] = -V[2];
-      }
-    }
+    if (hs.ext)   // exterior state of an open side
+      exterior_state<EQ, DIM, NC>(bnd, hs, DIM == 1 ? 1 : (hs.side < 2 ? ny : nx) * N1, V);
     const int t = C::sl(hs.hi, hs.hj);
     double X[NX], pr = 0.0;
 #pragma unroll
@@ -672,21 +751,36 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
   if (bad && bad_flag) atomicOr(bad_flag, 1u);
 }
 
-// copy the per-degree tables into LDS (sm, snk: the modal map and norms,
-// or NULL)
+// The per-degree tables, fetched into registers by the first threads of
+// the workgroup (thread t holds entry t of each table it covers) before the
+// state loads are issued, and stored to LDS once the state has arrived, so
+// that their latency hides under that of the state.
 template <int P>
-__device__ inline void load_tables(double* sw, double* sq, double* siw, double* sm, double* snk,
-                                   const Tables& T, int nthreads) {
-  constexpr int N1 = P + 1;
-  for (int t = threadIdx.x; t < N1; t += nthreads) {
-    sw[t] = T.w[t];
-    siw[t] = T.iw[t];
-    if (snk) snk[t] = T.nk[t];
+struct TableRegs {
+  static constexpr int N1 = P + 1;
+  double w, iw, nk, q, m;
+  __device__ inline void fetch(const Tables& T, bool modal) {
+    const int t = threadIdx.x;
+    if (t < N1) {
+      w = T.w[t];
+      iw = T.iw[t];
+      if (modal) nk = T.nk[t];
+    }
+    if (t < P * N1) q = T.Q[t];
+    if (modal && t < N1 * N1) m = T.M[t];
   }
-  for (int t = threadIdx.x; t < P * N1; t += nthreads) sq[t] = T.Q[t];
-  if (sm)
-    for (int t = threadIdx.x; t < N1 * N1; t += nthreads) sm[t] = T.M[t];
-}
+  // sm, snk: the modal map and norms (smoothness indicator), or NULL
+  __device__ inline void store(double* sw, double* sq, double* siw, double* sm, double* snk) const {
+    const int t = threadIdx.x;
+    if (t < N1) {
+      sw[t] = w;
+      siw[t] = iw;
+      if (snk) snk[t] = nk;
+    }
+    if (t < P * N1) sq[t] = q;
+    if (sm && t < N1 * N1) sm[t] = m;
+  }
+};
 
 // ----------------------------------------------------------------------
 // phase 3: subcell faces
@@ -759,7 +853,7 @@ __device__ __forceinline__ void face_item(const double* lds, const Phys& ph, con
 #pragma unroll
   for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
   const double avg = 0.5 * (UL[0] + UR[0]);
-  UBo = lam > 0.0 ? avg - (FR[0] - FL[0]) / (2.0 * lam) : avg;
+  UBo = lam > 0.0 ? avg - (FR[0] - FL[0]) * (0.5 * rcp_nr(lam)) : avg;
   if constexpr (INT) {
     // f^H of the element line through this face, and rbar = s (f^L - f^H)
     const int tr = K == 0 ? j % N1 : i % N1;   // the line's transverse node index
@@ -922,8 +1016,10 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   const bool own = tid < C::NOWN && lex < tg.tw && ley < tg.th;
   const long long g = ((long long)(tg.ey0 + ley) * S.nx + tg.ex0 + lex) * NP + s;
 
-  load_tables<P>(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, lds + C::S_M, lds + C::S_NK, T, C::BS);
-  if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
+  static_assert(P * (P + 1) <= C::BS && (P + 1) * (P + 1) <= C::BS, "one table entry per thread");
+  const bool modal = A.limiter == LIM_SUBCELL_SI;
+  TableRegs<P> tr;
+  tr.fetch(T, modal);
   double U[NC], Un[NC];
   if (A.use_un && own) {
 #pragma unroll
@@ -931,6 +1027,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   }
   load_tile<EQ, DIM, P, TX, TY, true>(lds, S.u_s, nn, tg, S.nx, S.ny, A.ph, bnd, U,
                                       A.diag ? &A.diag->bad_input : nullptr);
+  tr.store(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, modal ? lds + C::S_M : nullptr, modal ? lds + C::S_NK : nullptr);
+  if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   __syncthreads();
 
   // K_min over the node and its 2d grid neighbours (Euler), from the K of
@@ -1011,7 +1109,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   bool lov = false;
   double kmin_dbg = 0.0, az_dbg = 1.0, umin = 0.0, umax = 0.0;
   int search = 0, check0 = 0;   // faces of this node for the search list; check u^L first
-  double ubound = 0.0;
+  double ubound = 0.0, g2s = 0.0, pss = 0.0;
   const double idt = dt > 0.0 ? 1.0 / dt : 0.0;
   double dtm = 0.0;
   if (own) {
@@ -1118,7 +1216,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
         // could settle).
         kmin_dbg = kmin;
         const double g2 = 2.0 * DIM * dtm;
-        const double ikg = (ph_of(A).gamma - 1.0) / kmin;
+        const double ikg = (ph_of(A).gamma - 1.0) * rcp_nr(kmin);
         double us = 0.0, rmax = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) us = fmax(us, fabs(uL[c]));
@@ -1153,6 +1251,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
           const double zero[NC] = {};
           search = act;
           ubound = alpha;
+          g2s = g2;
+          pss = g2 * rmax;
           check0 = !surely_admissible<DIM, gn_of(EQ)>(0.0, uL, zero, kmin, ikg, ph_of(A));
         }
       }
@@ -1166,6 +1266,8 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       for (int c = 0; c < NC; ++c) lds[C::C_UL + c * C::CSO + tid] = uL[c];
       lds[C::C_KM + tid] = kmin;
       lds[C::C_AZ + tid] = ubound;
+      lds[C::C_G2 + tid] = g2s;
+      lds[C::C_PS + tid] = pss;
       int* list = reinterpret_cast<int*>(lds + C::C_LIST);
       int* count = reinterpret_cast<int*>(lds + C::S_LN);
 #pragma unroll
@@ -1180,32 +1282,25 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
       const int item = list[w];
       const int node = item >> 3, f = (item >> 1) & 3, k = f >> 1, sd = f & 1;
       const int nj = node / GX, ni = node - nj * GX;
-      const int na = ni % N1, nb = DIM == 2 ? nj % N1 : 0;
-      const double cxn = dt * (lds[C::S_IW + na] * S.ihx);
-      const double g2 = 2.0 * DIM * (DIM == 2 ? cxn * (lds[C::S_IW + nb] * S.ihy) : cxn);
+      const double g2 = lds[C::C_G2 + node];
       const int nox = C::ox(ni, nj), noy = C::oy(ni, nj);
       auto rb = [&](int kk, int c, int side) -> double {
         return kk == 0 ? lds[C::B_RBX + c * C::COX + nox + side] : lds[C::B_RBY + c * C::COY + noy + side * GX];
       };
-      double ul[NC], Pv[NC], rmax = 0.0;
+      double ul[NC], Pv[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         ul[c] = lds[C::C_UL + c * C::CSO + node];
         Pv[c] = g2 * (sd ? 1.0 : -1.0) * rb(k, c, sd);
       }
-      // the node's largest face correction scales the search tolerance
-#pragma unroll
-      for (int kk = 0; kk < DIM; ++kk)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) rmax = fmax(rmax, fmax(fabs(rb(kk, c, 0)), fabs(rb(kk, c, 1))));
       const double km = lds[C::C_KM + node];
       bool feasible = true;
       if (item & 1) {
         const double zero[NC] = {};
         feasible = admissible(phi_at<DIM, gn_of(EQ)>(0.0, ul, zero, km, ph_of(A)));
       }
-      const double t = feasible ? entropy_root<DIM, gn_of(EQ), 14>(ul, Pv, lds[C::C_AZ + node], false, km,
-                                                                   g2 * rmax, ph_of(A))
+      const double t = feasible ? entropy_root_face<DIM, gn_of(EQ)>(ul, Pv, lds[C::C_AZ + node], km,
+                                                                     lds[C::C_PS + node], ph_of(A))
                                 : 0.0;
       atomicMin(reinterpret_cast<unsigned long long*>(lds + C::S_AL + node),
                 (unsigned long long)__double_as_longlong(t));
@@ -1277,17 +1372,61 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void stage_kernel(St
 // ----------------------------------------------------------------------
 // low-order CFL bound (eq. cfl-low): min over nodes of m_i/(2 sum dhat_ij)
 // ----------------------------------------------------------------------
+// The time-step kernel stages per slot only what the wave-speed bounds read:
+// for Euler the velocity components and the auxiliaries c, c p^-ex,
+// (gamma+1)/(2 gamma p); for Burgers the state; for a velocity field beta.
+// Each quantity is one array of the slot grid, 64 doubles apart.
 template <int EQ, int DIM, int P, int TX, int TY>
 struct DtCfg {
   using C = Cfg<EQ, DIM, P, TX, TY>;
-  static constexpr int LX = C::A_X + C::NAUXF * C::CSU;   // wave speeds of the x-faces [NOX]
+  static constexpr int NWS = is_euler(EQ) ? DIM + 3 : EQ == EQ_BURG ? 1 : EQ == EQ_ADVV ? 2 : 0;
+  static constexpr int WS = 0;                             // [NWS][CSU]
+  static constexpr int LX = WS + NWS * C::CSU;             // wave speeds of the x-faces [NOX]
   static constexpr int LY = LX + C::NOX;                   // of the y-faces [NOY]
-  static constexpr int W = LY + C::NOY;
+  static constexpr int W = LY + C::NOY;                    // Gauss-Lobatto weights
   static constexpr int R = W + C::N1;
   static constexpr int LDS = R + C::NW;
   static constexpr int CX = (C::NOX + 63) / 64;            // chunks of x-faces
   static constexpr int CY = (C::NOY + 63) / 64;
+  static constexpr int NWS1 = NWS > 0 ? NWS : 1;
 };
+
+// The wave-speed inputs of one state (the node at global index g for a
+// velocity field); sets bad for a non-physical Euler state.
+template <int EQ, int DIM, int P>
+__device__ inline void wave_inputs(const double* U, long long g, int nx, const Phys& ph, double* ws) {
+  if constexpr (is_euler(EQ)) {
+    double X[5], pr;
+    bool bad;
+    euler_aux<DIM, gn_of(EQ), false>(U, ph, X, pr, bad);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) ws[k] = U[1 + k] * X[0];
+    ws[DIM] = X[1];
+    ws[DIM + 1] = X[2];
+    ws[DIM + 2] = X[3];
+  } else if constexpr (EQ == EQ_BURG) {
+    ws[0] = U[0];
+  } else if constexpr (EQ == EQ_ADVV) {
+    field_at<DIM, P>(g, nx, ph, ws);
+  }
+}
+
+// Wave-speed bound of the pair (left, right) along +e_K from the staged
+// inputs: the same arithmetic as lambda_k.
+template <int EQ, int DIM, int K>
+__device__ inline double lambda_ws(const double* wl, const double* wr, const Phys& ph) {
+  if constexpr (EQ == EQ_ADV) {
+    return fabs(vel_k(K, ph));
+  } else if constexpr (EQ == EQ_ADVV) {
+    return fmax(fabs(wl[K]), fabs(wr[K]));
+  } else if constexpr (EQ == EQ_BURG) {
+    return fmax(fabs(wl[0]), fabs(wr[0])) * fabs(vel_k(K, ph));
+  } else {
+    const double XL[4] = {0.0, wl[DIM], wl[DIM + 1], wl[DIM + 2]};
+    const double XR[4] = {0.0, wr[DIM], wr[DIM + 1], wr[DIM + 2]};
+    return euler_lambda<gn_of(EQ)>(wl[K], wr[K], XL, XR, ph);
+  }
+}
 
 // Wave speed of face item q of direction K of a tile into the time-step
 // kernel's arrays (every face of the tile: element faces and interior ones).
@@ -1295,7 +1434,7 @@ template <int EQ, int DIM, int P, int TX, int TY, int K>
 __device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, const TileGeo& tg) {
   using C = Cfg<EQ, DIM, P, TX, TY>;
   using D = DtCfg<EQ, DIM, P, TX, TY>;
-  constexpr int NC = C::NC, N1 = C::N1, NX = C::NAUX > 0 ? C::NAUX : 1;
+  constexpr int N1 = C::N1;
   int i, j;
   if constexpr (K == 0) {
     j = q / C::FXP;
@@ -1306,19 +1445,16 @@ __device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, cons
     i = q - j * C::GX;
     if (!(i < tg.tw * N1 && j <= tg.th * N1)) return;
   }
-  const int sR = C::sl(i, j), sL = K == 0 ? sR - 1 : sR - C::RP;
-  double UL[NC], UR[NC], XL[NX], XR[NX];
+  int dR = K == 0 ? 1 : C::RP;
+  asm volatile("" : "+s"(dR));
+  const int sL = K == 0 ? C::sl(i, j) - 1 : C::sl(i, j) - C::RP, sR = sL + dR;
+  double wl[D::NWS1], wr[D::NWS1];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    UL[c] = lds[C::A_U + c * C::CSU + sL];
-    UR[c] = lds[C::A_U + c * C::CSU + sR];
+  for (int x = 0; x < D::NWS; ++x) {
+    wl[x] = lds[D::WS + x * C::CSU + sL];
+    wr[x] = lds[D::WS + x * C::CSU + sR];
   }
-#pragma unroll
-  for (int x = 0; x < C::NAUXF; ++x) {
-    XL[x] = lds[C::A_X + x * C::CSU + sL];
-    XR[x] = lds[C::A_X + x * C::CSU + sR];
-  }
-  const double lam = lambda_k<EQ, DIM, K>(UL, XL, UR, XR, ph);
+  const double lam = lambda_ws<EQ, DIM, K>(wl, wr, ph);
   if constexpr (K == 0) lds[D::LX + C::ox(i, j)] = lam;
   else lds[D::LY + C::oy(i, j)] = lam;
 }
@@ -1331,11 +1467,48 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   using D = DtCfg<EQ, DIM, P, TX, TY>;
   constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, GX = C::GX;
   const int tid = threadIdx.x;
-  const TileGeo tg = tile_geo<DIM, TX, TY>(tile, A.ntx, A.nx, A.ny);
-  if (tg.tw <= 0 || tg.th <= 0) return;
-  for (int t = tid; t < N1; t += C::BS) lds[D::W + t] = T.w[t];
-  double U[NC];
-  load_tile<EQ, DIM, P, TX, TY, false>(lds, A.u, A.nn, tg, A.nx, A.ny, A.ph, bnd, U, nullptr);
+  const int nx = A.nx, ny = A.ny;
+  const TileGeo tg = tile_geo<DIM, TX, TY>(tile, A.ntx, nx, ny);
+  if (tg.tw <= 0 || tg.th <= 0) {   // whole workgroup
+    if (tid == 0) *out = INFINITY;
+    return;
+  }
+  const double wt = tid < N1 ? T.w[tid] : 0.0;   // stored once the state has arrived
+  // own nodes (one per thread) and the halo ring (threads h < NH), as in
+  // the stage kernel's load, but only the wave-speed inputs are staged
+  const int j = tid / GX, i = tid - j * GX;
+  const int lex = i / N1, ley = DIM == 2 ? j / N1 : 0;
+  const bool own = tid < C::NOWN && lex < tg.tw && ley < tg.th;
+  const int a = i - lex * N1, b = DIM == 2 ? j - ley * N1 : 0;
+  const long long g = ((long long)(tg.ey0 + ley) * nx + tg.ex0 + lex) * NP + (DIM == 2 ? b * N1 + a : a);
+  Halo hs;
+  const bool halo = tid < C::NH && halo_of<DIM, P, TX, TY>(tid, tg, nx, ny, bnd.open, &hs);
+  double Uo[NC], V[NC];
+  if (own) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Uo[c] = A.u[c * A.nn + g];
+  }
+  if (halo) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) V[c] = A.u[c * A.nn + hs.g];
+  }
+  if (own) {
+    double ws[D::NWS1];
+    wave_inputs<EQ, DIM, P>(Uo, g, nx, A.ph, ws);
+    const int t = C::sl(i, j);
+#pragma unroll
+    for (int x = 0; x < D::NWS; ++x) lds[D::WS + x * C::CSU + t] = ws[x];
+  }
+  if (halo) {
+    if (hs.ext)   // exterior state of an open side
+      exterior_state<EQ, DIM, NC>(bnd, hs, DIM == 1 ? 1 : (hs.side < 2 ? ny : nx) * N1, V);
+    double ws[D::NWS1];
+    wave_inputs<EQ, DIM, P>(V, hs.g, nx, A.ph, ws);
+    const int t = C::sl(hs.hi, hs.hj);
+#pragma unroll
+    for (int x = 0; x < D::NWS; ++x) lds[D::WS + x * C::CSU + t] = ws[x];
+  }
+  if (tid < N1) lds[D::W + tid] = wt;
   __syncthreads();
   // wave-uniform chunks of 64 faces of one direction
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -1345,10 +1518,7 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   }
   __syncthreads();
   double dti = INFINITY;
-  const int j = tid / GX, i = tid - j * GX;
-  const int lex = i / N1, ley = DIM == 2 ? j / N1 : 0;
-  if (tid < C::NOWN && lex < tg.tw && ley < tg.th) {
-    const int a = i - lex * N1, b = DIM == 2 ? j - ley * N1 : 0;
+  if (own) {
     const double wa = lds[D::W + a];
     const double wb = DIM == 2 ? lds[D::W + b] : 1.0;
     const int o = C::ox(i, j);

@@ -349,8 +349,7 @@ class Solver:
 
 class Batch:
     """Many solves of one equation family stepped together: per RK stage,
-    one work-list launch per degree over all their element tiles, the
-    launches of a step replayed as one HIP graph."""
+    one work-list launch per degree over all their element tiles."""
 
     def __init__(self, solvers, stream=None):
         torch = _torch()

@@ -13,8 +13,8 @@ fit, past a waiting large request, and are not counted against the cap.
 
 Every admitted state stays on the device.  On every tick, each admitted
 request advances by one step:
-- the requests of one equation family form a batch (one HIP graph per
-  step, with a work-list launch per degree and stage);
+- the requests of one equation family form a batch (a work-list launch
+  per degree and stage);
 - a family with one admitted request takes the plain path's graph;
 - the families' steps are enqueued back to back on one stream.
 
