@@ -43,8 +43,8 @@
 
 namespace idp {
 
-template <int EQ, int DIM, int P, int TX, int TY>
-struct Cfg {
+template <int EQ, int DIM, int P, int TX, int TY, int PAD>
+struct CfgP {
   static constexpr int N1 = P + 1;
   static constexpr int NP = DIM == 2 ? N1 * N1 : N1;    // nodes per element
   static constexpr int TYE = DIM == 2 ? TY : 1;         // elements per tile in y
@@ -74,10 +74,11 @@ struct Cfg {
   static constexpr int FXP = GX + 1;
   static constexpr int NOX = GY * FXP;
   static constexpr int NOY = DIM == 2 ? (GY + 1) * GX : 0;
-  // Arrays of several components (or auxiliaries) keep them a multiple of
-  // 64 doubles apart, so that one ds_read2st64 / ds_write2st64 moves two of
-  // them from one address register.
-  static constexpr int up64(int n) { return (n + 63) / 64 * 64; }
+  // Consecutive arrays of a multi-component (or multi-auxiliary) field
+  // start PAD doubles past a multiple of 64, so that the components of one
+  // slot fall into different LDS banks (with PAD = 0 every pair of them
+  // would share a bank).
+  static constexpr int up64(int n) { return (n + 63) / 64 * 64 + PAD; }
   static constexpr int CSU = up64(NSL), CSX = up64(NFX), CSY = up64(NFY);
   static constexpr int COX = up64(NOX), COY = up64(NOY), CSO = up64(NOWN);
   // phase-3 work: per direction the element faces and the interior faces
@@ -139,6 +140,17 @@ struct Cfg {
   static __device__ __forceinline__ int ox(int i, int j) { return j * FXP + i; }
   static __device__ __forceinline__ int oy(int i, int j) { return j * GX + i; }
 };
+
+// The bank padding is 4 doubles unless it would lower the number of
+// workgroups whose LDS fits in a CU's 160 KB.
+template <int EQ, int DIM, int P, int TX, int TY>
+constexpr int lds_pad() {
+  constexpr int k0 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 0>::LDS * 8);
+  constexpr int k4 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 4>::LDS * 8);
+  return k4 == k0 ? 4 : 0;
+}
+template <int EQ, int DIM, int P, int TX, int TY>
+using Cfg = CfgP<EQ, DIM, P, TX, TY, lds_pad<EQ, DIM, P, TX, TY>()>;
 
 // Where a tile lies: its first element column and row, and how many of its
 // TX x TY elements exist (tiles on the high edges of the mesh are ragged).
