@@ -19,8 +19,9 @@ Further legs on the same JSON line:
   solid-body rotation, the double Mach reflection set-up, 1-D Euler;
 - 64 uneven Euler solves, batched against one solve per launch (batched;
   the batch tunes its tile shapes per degree);
-- a served request stream against FIFO through the plain path, at offered
-  load 0.8 (serving) and 1.3 (serving_overload);
+- the served stream of 1000 requests against FIFO through the plain path,
+  at offered loads 0.5, 0.8 and 0.95 of the plain path's capacity
+  (serving);
 - the oracle on the host (cpu_baseline).
 """
 import argparse
@@ -296,6 +297,12 @@ def progress(msg):
     print("bench: %s" % msg, file=sys.stderr, flush=True)
 
 
+# The server's tick policy for the served leg: the admitted requests with
+# the least remaining work (less 0.5 s per second waited) step each tick, up
+# to about one GPU-filling solve of nodes; admission by footprint only.
+SERVE_POLICY = {"policy": "srw", "age_weight": 0.5, "max_active_nodes": 0}
+
+
 def fifo_from_service(reqs, service):
     """A single server taking the requests in arrival order, each for its
     measured plain-path service time: completion = max(arrival, previous
@@ -318,8 +325,9 @@ def serving_leg(count, loads, budget_gb=64.0):
     a time: that makespan is the plain path's capacity, and the gaps between
     consecutive completions are each request's service time.  For each
     offered load the arrival rate is load * count / makespan; the stream
-    runs through the continuous-batching server, and FIFO through the plain
-    path is the single-server queue over the measured service times."""
+    runs through the continuous-batching server (shortest remaining work
+    first with aging, SERVE_POLICY), and FIFO through the plain path is the
+    single-server queue over the measured service times."""
     from paper_2004_08503_amd import serve, workloads as W
     back_to_back = W.request_stream(count, rate=1e9, seed=5)
     b2b = sorted(serve.run_fifo_plain(back_to_back), key=lambda d: d.finished)
@@ -330,11 +338,12 @@ def serving_leg(count, loads, budget_gb=64.0):
         service[d.rid] = d.finished - prev
         prev = d.finished
     out = {"workload": "served_stream_%d_requests_burgers_euler_n16-512_p2-6_steps20-200" % count,
-           "plain_service_s": busy, "hbm_budget_gb": budget_gb, "loads": {}}
+           "plain_service_s": busy, "hbm_budget_gb": budget_gb, "policy": dict(SERVE_POLICY),
+           "loads": {}}
     for load in loads:
         rate = load * count / busy
         reqs = W.request_stream(count, rate=rate, seed=5)   # same requests, new arrivals
-        srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30))
+        srv = serve.Server(hbm_budget=int(budget_gb * 2 ** 30), **SERVE_POLICY)
         served = serve.summarize(srv.run(reqs))
         fifo = serve.summarize(fifo_from_service(reqs, service))
         out["loads"]["%.2f" % load] = {"rate_per_s": rate, "served": served, "fifo_plain": fifo,

@@ -11,8 +11,16 @@ request that must wait holds back the large requests behind it.  Small
 requests (at most 1/16 of that many nodes) are admitted as soon as they
 fit, past a waiting large request, and are not counted against the cap.
 
-Every admitted state stays on the device.  On every tick, each admitted
-request advances by one step:
+Every admitted state stays on the device.  On every tick, with the
+processor-sharing policy ("ps", the default), each admitted request
+advances by one step; with the shortest-remaining-work policy ("srw"),
+the admitted requests are taken in order of remaining work (nodes times
+steps left) until the tick holds about one GPU-filling solve of nodes,
+and only those advance (the others keep their state on the device and
+wait); age_weight lowers a request's remaining work by that many seconds
+per second since its arrival, so that a long wait raises its rank (pure
+shortest-remaining-work first starves the largest requests under high
+load).  In both:
 - the requests of one equation family form a batch (a work-list launch
   per degree and stage);
 - a family with one admitted request takes the plain path's graph;
@@ -66,9 +74,21 @@ def footprint_bytes(req: Request) -> int:
 
 class Server:
     def __init__(self, hbm_budget: int, cfl: float = 0.5, keep_results: bool = False,
-                 max_active: int = 0, max_active_nodes: int = 1 << 21, small_nodes: int = -1):
+                 max_active: int = 0, max_active_nodes: int = 1 << 21, small_nodes: int = -1,
+                 policy: str = "ps", tick_nodes: int = 1 << 21, age_weight: float = 0.0,
+                 node_rate: float = 1.5e10):
         import torch
         self.torch = torch
+        if policy not in ("ps", "srw"):
+            raise ValueError("policy must be 'ps' or 'srw'")
+        self.policy = policy
+        # srw: the requests stepped in one tick hold about this many nodes
+        self.tick_nodes = int(tick_nodes)
+        # srw: a request's remaining work, in seconds at node_rate node-steps
+        # per second (three stages per step), is lowered by age_weight times
+        # the seconds since its arrival, so that a long wait raises its rank
+        self.age_weight = float(age_weight)
+        self.node_rate = float(node_rate)
         self.max_active = int(max_active)   # 0: no cap on concurrently served requests
         # 0: no cap; else a large request is admitted only while the admitted
         # large requests' nodes stay within it (or no other large one is
@@ -98,7 +118,6 @@ class Server:
         large = 0                          # nodes of the admitted large requests
         groups: Dict[int, list] = {}       # family -> [member ids, Batch, state pointers]
         dirty = set()                      # families whose membership changed
-        ends: Dict[int, List[int]] = {}    # tick -> requests whose last step it is
         tick = 0
         self.peak_used = 0                 # most device bytes admitted at once
         finishing = []                     # (request record, end event)
@@ -137,11 +156,11 @@ class Server:
                 fam = idp_dg.family_of(prob)
                 active[req.rid] = {"req": req, "sv": sv, "u": u, "fam": fam, "fp": fp,
                                    "large": 0 if small else prob.num_nodes,
+                                   "nodes": prob.num_nodes, "left": req.steps,
                                    "admitted": time.perf_counter() - t0}
                 used += fp
                 self.peak_used = max(self.peak_used, used)
                 large += active[req.rid]["large"]
-                ends.setdefault(tick + req.steps - 1, []).append(req.rid)
                 dirty.add(fam)
             waiting = keep
             if not active and waiting and not any(
@@ -154,9 +173,30 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
+            # the requests that step this tick: all (ps), or those with the
+            # least remaining work up to the tick's node budget (srw)
+            if self.policy == "ps":
+                run = set(active)
+            else:
+                run, held = set(), 0
+
+                def rank(r):
+                    a = active[r]
+                    work = 3.0 * a["nodes"] * a["left"] / self.node_rate
+                    return (work - self.age_weight * (now - a["req"].arrival), r)
+
+                for rid in sorted(active, key=rank):
+                    if run and held + active[rid]["nodes"] > self.tick_nodes:
+                        continue
+                    run.add(rid)
+                    held += active[rid]["nodes"]
+                for fam in {a["fam"] for a in active.values()} | set(groups):
+                    g = groups.get(fam)
+                    if g is None or g[0] != sorted(r for r in run if active[r]["fam"] == fam):
+                        dirty.add(fam)
             # batches of the families whose membership changed
             for fam in dirty:
-                ids = sorted(r for r, a in active.items() if a["fam"] == fam)
+                ids = sorted(r for r in run if active[r]["fam"] == fam)
                 g = groups.get(fam)
                 if not ids:
                     if g is not None:
@@ -180,7 +220,10 @@ class Server:
                 elif ids:
                     b.step_cfl_prepared(ptrs, self.cfl)
             # retire requests whose last step is now enqueued
-            for rid in ends.pop(tick, ()):
+            for rid in sorted(run):
+                active[rid]["left"] -= 1
+                if active[rid]["left"] > 0:
+                    continue
                 a = active.pop(rid)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.stream)

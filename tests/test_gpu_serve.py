@@ -31,12 +31,15 @@ def alone(idp_dg, req):
     return out
 
 
+@pytest.mark.parametrize("policy", ["ps", "srw"])
 @pytest.mark.parametrize("budget_mb", [4096, 3], ids=["roomy", "one-at-a-time"])
-def test_served_results_equal_alone(budget_mb):
+def test_served_results_equal_alone(budget_mb, policy):
     idp_dg, serve = _mods()
     reqs = W.request_stream(10, rate=400.0, n_range=(4, 14), p_range=(2, 5),
                             steps_range=(3, 9), seed=11)
-    srv = serve.Server(hbm_budget=budget_mb * 2 ** 20, keep_results=True)
+    # srw: a small tick budget, so that requests pause and resume
+    srv = serve.Server(hbm_budget=budget_mb * 2 ** 20, keep_results=True, policy=policy,
+                       max_active_nodes=0 if policy == "srw" else 1 << 21, tick_nodes=3000)
     done = srv.run(reqs)
     assert [d.rid for d in done] == [r.rid for r in reqs]
     # admission counted what a request really holds (state, handle workspace,
