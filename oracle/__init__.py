@@ -50,7 +50,8 @@ class _Desc(ctypes.Structure):
                 ("beta", ctypes.POINTER(ctypes.c_double)),
                 ("bc", ctypes.c_int * 2),
                 ("bc_type", ctypes.c_void_p * 4),
-                ("bc_state", ctypes.c_void_p * 4)]
+                ("bc_state", ctypes.c_void_p * 4),
+                ("metric", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Trace(ctypes.Structure):
@@ -126,6 +127,11 @@ def _desc(prob):
                 st = np.ascontiguousarray(bnd.state[side], dtype=np.float64)
                 d.bc_state[side] = st.ctypes.data
                 keep.append(st)
+    if getattr(prob, "coords", None) is not None:   # curved mesh: metric terms (oracle.metric)
+        from . import metric as _metric
+        met = _metric.metric_terms(prob)
+        d.metric = _ptr(met)
+        keep.append(met)
     d._keep = keep          # the arrays live as long as the descriptor
     return d
 

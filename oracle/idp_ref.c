@@ -84,6 +84,15 @@ int idp_ref_check(const idp_ref_desc* d) {
     if (d->bc[k] && (!d->bc_type[2 * k] || !d->bc_type[2 * k + 1])) return -1;
   }
   if (d->dim == 1 && d->bc[1]) return -1;
+  if (d->metric) {
+    /* curved meshes: 2-D, periodic, flux F(u) (not a velocity field) */
+    if (d->dim != 2 || d->eq == IDP_REF_ADVECTION_FIELD || d->bc[0] || d->bc[1]) return -1;
+    long nn = idp_ref_num_nodes(d);
+    for (long q = 0; q < 9 * nn; ++q)
+      if (!isfinite(d->metric[q])) return -1;
+    for (long i = 0; i < nn; ++i)
+      if (!(d->metric[8 * nn + i] > 0.0)) return -1;
+  }
   return 0;
 }
 
@@ -402,13 +411,45 @@ static double line_scale(const ref_t* R, int k, int t) {
   return k == 0 ? R->w[t] * R->hy : R->w[t] * R->hx;
 }
 
-/* node mass m_i: diagonal of M_K = M_ref G (Sec. 2.3) */
+/* metric term q of node i on a curved mesh (see idp_ref_desc.metric) */
+static double met(const ref_t* R, int q, long i) { return R->d.metric[(long)q * R->nn + i]; }
+
+/* node mass m_i: diagonal of M_K = M_ref G (Sec. 2.3), G = det(J) */
 static double node_mass(const ref_t* R, long i) {
   long ex, ey;
   int a, b;
   node_coords(R, i, &ex, &ey, &a, &b);
   if (R->d.dim == 1) return R->w[a] * R->hx;
+  if (R->d.metric) return R->w[a] * R->w[b] * met(R, 8, i);
   return R->w[a] * R->w[b] * R->hx * R->hy;
+}
+
+/* Row k of the metric terms of node i (curved meshes): the high-order
+ * det(J) J^-1 (corr = 0) or the modified terms with the conservative
+ * correction (corr = 1). */
+static void metric_row(const ref_t* R, long i, int k, int corr, double* v) {
+  v[0] = met(R, 4 * corr + 2 * k, i);
+  v[1] = met(R, 4 * corr + 2 * k + 1, i);
+}
+
+/* the contravariant flux (eq. contravariant) of component c of node i
+ * along reference direction k: sum_l (row k of the metric)_l F_l(u_i) */
+static double contra(const ref_t* R, const double* F, long i, int k, int c, int corr) {
+  double v[2];
+  metric_row(R, i, k, corr, v);
+  const long nn = R->nn;
+  const int nc = R->nc;
+  return v[0] * F[((long)0 * nc + c) * nn + i] + v[1] * F[((long)1 * nc + c) * nn + i];
+}
+
+/* The scaled normal (pointing in +xi_k) of the element face between the
+ * k-neighbours jl (on the lower side) and jr: row k of the high-order
+ * metric terms at the face node of the lower element, so that both
+ * elements use one normal and the face flux is single-valued (reading:
+ * the paper evaluates the face normals from the metric terms at the face
+ * nodes; for a continuous mesh the two sides agree up to rounding). */
+static void face_normal(const ref_t* R, long jl, int k, double* n) {
+  metric_row(R, jl, k, 0, n);
 }
 
 static void get_state(const ref_t* R, const double* u, long i, double* ui) {
@@ -514,6 +555,58 @@ static void graph_coeffs(const ref_t* R, const double* u, long i, int k, int s,
     *chat = cij;
     double d1 = lambda(R, ui, uj, e_ij) * fabs(cij);
     double d2 = lambda(R, uj, ui, e_ji) * fabs(cji);
+    *dhat = d1 > d2 ? d1 : d2;
+  }
+  *j_out = j;
+}
+
+/* Graph coefficients on a curved mesh (vector chat_ij, and dhat_ij) for
+ * the neighbour j of i in direction k on side s.
+ *  - j in the same element: chat_ij = w_t Dhat[aj][ai] (row k of the
+ *    modified metric terms at j), the coefficient of F_j in row i of
+ *    Dhat_k^T Jinvidp_k. (eq. dg-lo-cij, eq. dg-lo-modified), and
+ *    dhat_ij = max(lambda(u_i, u_j, n_ij) |chat_ij|, lambda(u_j, u_i,
+ *    n_ji) |chat_ji|) (eq. dij).
+ *  - j across an element face: chat_ij = -1/2 w_t n (n the outward scaled
+ *    normal of i's element) and dhat_ij = lambda/2 |n| w_t.
+ * Reading (as on Cartesian meshes): n_ij is the unit vector pointing from
+ * node i to node j, -chat_ij / |chat_ij|, and lambda_max(u_i, u_j, n) is
+ * taken for u_i on the left and u_j on the right along it. */
+static void graph_coeffs_m(const ref_t* R, const double* u, long i, int k, int s,
+                           long* j_out, double* chat, double* dhat, double* uj_out) {
+  int across, t;
+  long j = neighbour(R, i, k, s, &across);
+  double ui[MAXC], uj[MAXC];
+  get_state(R, u, i, ui);
+  get_state(R, u, j, uj);
+  if (uj_out) memcpy(uj_out, uj, sizeof(double) * R->nc);
+  int ai = line_pos(R, i, k, &t);
+  double wt = R->w[t];
+  if (across) {
+    double n[2];
+    face_normal(R, s > 0 ? i : j, k, n);
+    n[0] *= (double)s;
+    n[1] *= (double)s;
+    double nm = sqrt(n[0] * n[0] + n[1] * n[1]);
+    double nu[2] = {n[0] / nm, n[1] / nm};
+    chat[0] = -0.5 * wt * n[0];
+    chat[1] = -0.5 * wt * n[1];
+    *dhat = 0.5 * lambda(R, ui, uj, nu) * nm * wt;
+  } else {
+    int n1 = R->n1, aj = ai + s;
+    double vj[2], vi[2];
+    metric_row(R, j, k, 1, vj);
+    metric_row(R, i, k, 1, vi);
+    double cij[2] = {wt * R->Dh[aj * n1 + ai] * vj[0], wt * R->Dh[aj * n1 + ai] * vj[1]};
+    double cji[2] = {wt * R->Dh[ai * n1 + aj] * vi[0], wt * R->Dh[ai * n1 + aj] * vi[1]};
+    double mij = sqrt(cij[0] * cij[0] + cij[1] * cij[1]);
+    double mji = sqrt(cji[0] * cji[0] + cji[1] * cji[1]);
+    double nij[2] = {-cij[0] / mij, -cij[1] / mij};
+    double nji[2] = {-cji[0] / mji, -cji[1] / mji};
+    double d1 = lambda(R, ui, uj, nij) * mij;
+    double d2 = lambda(R, uj, ui, nji) * mji;
+    chat[0] = cij[0];
+    chat[1] = cij[1];
     *dhat = d1 > d2 ? d1 : d2;
   }
   *j_out = j;
@@ -708,6 +801,90 @@ int idp_ref_smoothness(const idp_ref_desc* d, const double* u, double* eps) {
 /* forward-Euler sub-step                                              */
 /* ------------------------------------------------------------------ */
 
+/* O3/O4/O6 on one k-line of element (ex, ey) of a curved mesh: the
+ * transverse weight w_t of the Kronecker structure (eq. kronecker) times
+ *  - high order (eq. dg-strong): -sum_m D[a][m] Ft_m with Ft the
+ *    contravariant flux of the high-order metric terms, and on the element
+ *    faces -(Fhat - F . n) with n the outward scaled normal;
+ *  - low order (eq. dg-lo-modified): sum_m Dhat[m][a] Gt_m with Gt the
+ *    contravariant flux of the modified metric terms, -Fhat on the element
+ *    faces, and the graph viscosity d_ij (u_j - u_i) of eq. dij inside;
+ *  - the subcell sums rbar of the line (zero on the element faces).
+ * The face flux is the Lax-Friedrichs flux of eq. lax-friedrichs with the
+ * scaled normal n: |n| Fhat(u^-, u^+, n/|n|). */
+static void curved_line(const ref_t* R, const double* u, const double* F, double* rH, double* rL,
+                        double* rbar, long ex, long ey, int k, int t) {
+  const int nc = R->nc, p = R->d.p, n1 = R->n1;
+  const long nn = R->nn;
+  long line[MAXN];
+  for (int a = 0; a <= p; ++a) line[a] = k == 0 ? node_index(R, ex, ey, a, t) : node_index(R, ex, ey, t, a);
+  const double wt = R->w[t];
+  int across;
+  long jl = neighbour(R, line[0], k, -1, &across);
+  long jr = neighbour(R, line[p], k, +1, &across);
+  double nL[2], nR[2];
+  face_normal(R, jl, k, nL);        /* +xi_k normal of the left face */
+  face_normal(R, line[p], k, nR);   /* of the right face */
+  double u0[MAXC], up[MAXC], ujl[MAXC], ujr[MAXC], FhL[MAXC], FhR[MAXC];
+  get_state(R, u, line[0], u0);
+  get_state(R, u, line[p], up);
+  get_state(R, u, jl, ujl);
+  get_state(R, u, jr, ujr);
+  {
+    /* outward normals of this element: -nL on the left, +nR on the right */
+    double mL = sqrt(nL[0] * nL[0] + nL[1] * nL[1]), mR = sqrt(nR[0] * nR[0] + nR[1] * nR[1]);
+    double oL[2] = {-nL[0] / mL, -nL[1] / mL}, oR[2] = {nR[0] / mR, nR[1] / mR};
+    lax_friedrichs(R, u0, line[0], ujl, jl, oL, FhL);
+    lax_friedrichs(R, up, line[p], ujr, jr, oR, FhR);
+    for (int c = 0; c < nc; ++c) {
+      FhL[c] *= mL;
+      FhR[c] *= mR;
+    }
+  }
+#define IDX3(kk, cc, ii) (((long)(kk) * nc + (cc)) * nn + (ii))
+  for (int a = 0; a <= p; ++a) {
+    long i = line[a];
+    for (int c = 0; c < nc; ++c) {
+      double vol = 0.0;
+      for (int m = 0; m <= p; ++m) vol += R->D[a * n1 + m] * contra(R, F, line[m], k, c, 0);
+      double rh = -wt * vol;
+      if (a == 0) {
+        double fn = F[IDX3(0, c, i)] * (-nL[0]) + F[IDX3(1, c, i)] * (-nL[1]);
+        rh -= wt * (FhL[c] - fn);
+      }
+      if (a == p) {
+        double fn = F[IDX3(0, c, i)] * nR[0] + F[IDX3(1, c, i)] * nR[1];
+        rh -= wt * (FhR[c] - fn);
+      }
+      rH[IDX3(k, c, i)] = rh;
+      double volh = 0.0;
+      for (int m = 0; m <= p; ++m) volh += R->Dh[m * n1 + a] * contra(R, F, line[m], k, c, 1);
+      double rl = wt * volh;
+      if (a == 0) rl -= wt * FhL[c];
+      if (a == p) rl -= wt * FhR[c];
+      rL[IDX3(k, c, i)] = rl;
+    }
+    for (int sd = -1; sd <= 1; sd += 2) {
+      int aj = a + sd;
+      if (aj < 0 || aj > p) continue;
+      long j;
+      double chat[2], dij, ui[MAXC], uj[MAXC];
+      graph_coeffs_m(R, u, i, k, sd, &j, chat, &dij, uj);
+      get_state(R, u, i, ui);
+      for (int c = 0; c < nc; ++c) rL[IDX3(k, c, i)] += dij * (uj[c] - ui[c]);
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    double acc = 0.0;
+    for (int a = 0; a < p; ++a) {
+      acc += rH[IDX3(k, c, line[a])] - rL[IDX3(k, c, line[a])];
+      rbar[IDX3(k, c, line[a])] = acc;
+    }
+    rbar[IDX3(k, c, line[p])] = 0.0;
+  }
+#undef IDX3
+}
+
 int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
                double dt, idp_ref_trace* tr) {
   ref_t Rs, *R = &Rs;
@@ -760,6 +937,10 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
     for (long ex = 0; ex < R->d.nx; ++ex) {
       for (int k = 0; k < dim; ++k) {
         for (int t = 0; t < (dim == 2 ? n1 : 1); ++t) {
+          if (R->d.metric) {
+            curved_line(R, u, F, rH, rL, rbar, ex, ey, k, t);
+            continue;
+          }
           long line[MAXN];
           for (int a = 0; a <= p; ++a)
             line[a] = k == 0 ? node_index(R, ex, ey, a, t)
@@ -894,6 +1075,22 @@ int idp_ref_fe(const idp_ref_desc* dsc, const double* u, double* out,
         long j;
         double chat, dhat;
         double uj[MAXC], Fj[2 * MAXC];
+        if (R->d.metric) {
+          /* eq. bar-states with the vector chat_ij of a curved mesh */
+          double cv[2];
+          graph_coeffs_m(R, u, i, k, sd, &j, cv, &dhat, uj);
+          flux_node(R, uj, j, Fj);
+          double bar = 0.5 * (ui[lim] + uj[lim]);
+          double dF = cv[0] * (Fj[lim] - Fi[lim]) + cv[1] * (Fj[nc + lim] - Fi[nc + lim]);
+          if (dhat > 0.0) bar += dF / (2.0 * dhat);
+          if (bar < lo) lo = bar;
+          if (bar > hi) hi = bar;
+          if (euler) {
+            double kj = euler_pressure(R, uj) * pow(uj[0], -R->d.gamma);
+            if (kj < km) km = kj;
+          }
+          continue;
+        }
         graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, uj);
         flux_node(R, uj, j, Fj);
         double bar = 0.5 * (ui[lim] + uj[lim]);
@@ -1160,8 +1357,9 @@ int idp_ref_max_dt(const idp_ref_desc* dsc, const double* u, double* dt) {
     for (int k = 0; k < R->d.dim; ++k) {
       for (int sd = -1; sd <= 1; sd += 2) {
         long j;
-        double chat, dhat;
-        graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, NULL);
+        double chat, dhat, cv[2];
+        if (R->d.metric) graph_coeffs_m(R, u, i, k, sd, &j, cv, &dhat, NULL);
+        else graph_coeffs(R, u, i, k, sd, &j, &chat, &dhat, NULL);
         sum += dhat;
       }
     }

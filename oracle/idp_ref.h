@@ -80,6 +80,16 @@ typedef struct {
   const double* bc_state[4];     /* the prescribed states of STATE nodes,
                          [c*n + q] for n boundary nodes (NULL: STATE acts
                          as OUTFLOW) */
+  const double* metric; /* curved meshes (2-D, periodic, not a velocity
+                         field): per node i, metric[q*Nn + i] with
+                         q = 0..3 the metric terms det(J) J^-1 of Sec. 2.3,
+                         row-major (row k: reference direction xi_k,
+                         column l: physical direction x_l), evaluated
+                         freestream-preservingly; q = 4..7 the modified
+                         terms det(J) J^-1 + C of Sec. 3.1 (eq.
+                         metric-perturbation); q = 8 det(J).  The mapping
+                         is from the reference square [0,1]^2.  NULL: the
+                         affine Cartesian elements of lx/nx x ly/ny. */
 } idp_ref_desc;
 
 /* Optional per-node outputs of one forward-Euler sub-step.  Any pointer may

@@ -63,6 +63,10 @@ class Problem:
     # conditions in bnd (a Boundary)
     bc: Tuple[int, int] = (0, 0)
     bnd: object = None
+    # curved meshes (2-D, periodic): the physical coordinates of every node,
+    # a float64 array (2, Nn) in state order; None: the Cartesian mesh of
+    # lx/nx x ly/ny elements
+    coords: object = None
 
     @property
     def nc(self) -> int:
@@ -153,6 +157,25 @@ def node_coords(prob: Problem):
     x = (ex + xi[a]) * hx + 0.0 * b
     y = (ey + xi[b]) * hy + 0.0 * a
     return x.reshape(-1), y.reshape(-1), None
+
+
+def perturbed_coords(prob: Problem, amp: float = 0.05):
+    """Node coordinates of a smoothly curved periodic mesh: the Cartesian
+    nodes (X, Y) moved by amp (lx, ly) sin(2 pi X/lx) sin(2 pi Y/ly) in both
+    directions (an invertible map for amp < 1/(2 pi)).  The periodic copies
+    of a point differ by the box lengths, so neighbouring elements share
+    their face nodes."""
+    X, Y, _ = node_coords(prob)
+    s = np.sin(2 * np.pi * X / prob.lx) * np.sin(2 * np.pi * Y / prob.ly)
+    return np.ascontiguousarray(np.stack([X + amp * prob.lx * s, Y + amp * prob.ly * s]))
+
+
+def rotated_coords(prob: Problem, theta: float):
+    """Node coordinates of the Cartesian mesh rotated by theta about the
+    origin (an affine mesh whose faces are not aligned with the axes)."""
+    X, Y, _ = node_coords(prob)
+    c, s = np.cos(theta), np.sin(theta)
+    return np.ascontiguousarray(np.stack([c * X - s * Y, s * X + c * Y]))
 
 
 def _element_centres(prob: Problem):
