@@ -179,6 +179,29 @@ int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream,
  * periodic direction or a NULL type. */
 int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const double* state);
 
+/* Curved mesh (Sec. 2.3 isoparametric elements, Sec. 3.1 conservative
+ * correction): coords is a host array [2][Nn] of the physical node
+ * coordinates (x then y, state order u[c][e][b][a]), read during the call
+ * only.  Each element is the image of the reference square under the
+ * polynomial interpolant of its nodes; neighbouring elements must agree on
+ * their shared face nodes up to the periodic shift (not checked).  From
+ * them the call computes, per node, the metric terms det(J) J^-1 of the
+ * high-order operator (rows xi, eta = (y_eta, -x_eta), (-y_xi, x_xi), the
+ * derivatives by the Gauss-Lobatto derivative matrix along node lines),
+ * det(J), and the corrected terms of the low-order operator: per element
+ * and physical direction the minimum-norm solution C of eq.
+ * metric-perturbation, added to the high-order terms.  They are uploaded to
+ * a device array of 9 Nn doubles that the handle allocates (hipMalloc) and
+ * frees at idp_dg_destroy; every later stage and time-step launch uses the
+ * curved operators (one tile shape; idp_dg_set_tile_shape has no effect).
+ * A second call replaces the mesh.  Waits for the handle's stream.
+ * IDP_DG_EINVAL: NULL coords, a non-2-D problem, an advection field, an open
+ * direction (curved meshes are periodic), a handle created in a caller
+ * workspace (which must not allocate), or a node with det(J) not positive
+ * or a non-finite coordinate.  Handles on curved meshes cannot join a
+ * batch. */
+int idp_dg_set_mesh(idp_dg* h, const double* coords);
+
 /* Release the handle and the buffers it allocated.  NULL-safe. */
 void idp_dg_destroy(idp_dg* h);
 

@@ -277,6 +277,7 @@ int check_members(idp_dg* const* solves, int n, idp_dg_batch* b) {
   if (!solves || n < 1) return bfail(b, IDP_DG_EINVAL, "need at least one solve");
   for (int i = 0; i < n; ++i) {
     if (!solves[i]) return bfail(b, IDP_DG_EINVAL, "NULL solve handle");
+    if (solves[i]->metric) return bfail(b, IDP_DG_EINVAL, "curved-mesh solves cannot join a batch");
     for (int j = 0; j < i; ++j)
       if (solves[j] == solves[i]) return bfail(b, IDP_DG_EINVAL, "a handle appears twice");
   }

@@ -79,6 +79,8 @@ struct Solve {
   int ntx;              // tiles per row of tiles
   double hx, hy;
   double ihx, ihy;      // 1/hx, 1/hy
+  const double* metric; // curved meshes: per node [q][nn] (q < 4 det(J) J^-1, q < 8 the
+                        // corrected terms, q = 8 det(J)); NULL on Cartesian meshes
 };
 
 struct StageArgs {
@@ -105,6 +107,7 @@ struct MaxDtArgs {
   Phys ph;
   Tables T;
   Bnd bnd;
+  const double* metric;      // curved meshes (as Solve::metric), else NULL
 };
 
 // Batched execution: per degree, a work list of (solve, tile) items over
@@ -146,6 +149,8 @@ struct RetiredGraph {
                                  hipStream_t s);                                  \
   hipError_t launch_maxdt_##NAME(int p, int variant, const MaxDtArgs& a,          \
                                  hipStream_t s);                                  \
+  hipError_t launch_stage_curved_##NAME(int p, const StageArgs& a, hipStream_t s); \
+  hipError_t launch_maxdt_curved_##NAME(int p, const MaxDtArgs& a, hipStream_t s); \
   void tile_dims_##NAME(int p, int variant, int* tx, int* ty);                    \
   int num_variants_##NAME(int p);                                                 \
   int batch_kernels_##NAME(int p, int variant, BatchKernels* k);

@@ -30,6 +30,7 @@ struct idp_dg {
   double* dtdev = nullptr;     // [0] bound of the last step_cfl, [1] of max_dt
   double* partial = nullptr;   // per-workgroup minima of the time-step kernel
   double* vel = nullptr;       // IDP_DG_ADVECTION_FIELD: row then column velocities
+  double* metric = nullptr;    // curved meshes (idp_dg_set_mesh): [9][nn] metric terms
   idp::Bnd bnd{};              // open sides: per-node conditions (idp_dg_set_boundary)
   unsigned bnd_version = 0;    // bumped by every idp_dg_set_boundary
   // cached graph of one device-timestepped step
@@ -55,6 +56,10 @@ idp::StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double*
                                double dt, const double* dt_dev, double dt_scale, int stage);
 idp::MaxDtArgs make_dt_args(const idp_dg* h, const double* u);
 int fail(idp_dg* h, int code, const std::string& msg);
+// Gauss-Lobatto weights on [0,1] and the plain derivative matrix
+// Dn[i*(p+1)+j] = l_j'(xi_i) of the Lagrange basis on those points
+void gl_derivative(int p, double* w01, double* Dn);
+void drop_graph(idp_dg* h);
 bool desc_ok(const idp_dg_desc* d, std::string* why);
 void init_host(idp_dg* h, const idp_dg_desc* desc, void* hip_stream);
 hipError_t launch_stage(const idp_dg* h, const idp::StageArgs& a, hipStream_t s);

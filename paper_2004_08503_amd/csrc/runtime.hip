@@ -92,6 +92,14 @@ void gl_tables(int p, double* xi01, double* w01, double* D) {
 
 namespace idp_host {
 
+void gl_derivative(int p, double* w01, double* Dn) {
+  const int n = p + 1;
+  double xi[MAXP + 1], D[(MAXP + 1) * (MAXP + 1)];
+  gl_tables(p, xi, w01, D);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Dn[i * n + j] = D[i * n + j] / w01[i];
+}
+
 int fail(idp_dg* h, int code, const std::string& msg) {
   if (h) h->err = msg; else g_create_error = msg;
   return code;
@@ -170,6 +178,16 @@ int family(const idp_dg* h) { return h->kcode * 2 + (h->d.dim - 1); }
 
 hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
   const int p = h->d.p;
+  if (h->metric) {   // curved mesh: the first tile shape
+    switch (family(h)) {
+      case 1: return launch_stage_curved_adv2(p, a, s);
+      case 3: return launch_stage_curved_burg2(p, a, s);
+      case 5: return launch_stage_curved_euler2(p, a, s);
+      case 7: return launch_stage_curved_euler53_2(p, a, s);
+      case 9: return launch_stage_curved_euler75_2(p, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (family(h)) {
     case 0: return launch_stage_adv1(p, h->variant, a, s);
     case 1: return launch_stage_adv2(p, h->variant, a, s);
@@ -188,6 +206,16 @@ hipError_t launch_stage(const idp_dg* h, const StageArgs& a, hipStream_t s) {
 
 hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
   const int p = h->d.p;
+  if (h->metric) {
+    switch (family(h)) {
+      case 1: return launch_maxdt_curved_adv2(p, a, s);
+      case 3: return launch_maxdt_curved_burg2(p, a, s);
+      case 5: return launch_maxdt_curved_euler2(p, a, s);
+      case 7: return launch_maxdt_curved_euler53_2(p, a, s);
+      case 9: return launch_maxdt_curved_euler75_2(p, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (family(h)) {
     case 0: return launch_maxdt_adv1(p, h->variant, a, s);
     case 1: return launch_maxdt_adv2(p, h->variant, a, s);
@@ -206,19 +234,20 @@ hipError_t launch_maxdt(const idp_dg* h, const MaxDtArgs& a, hipStream_t s) {
 
 void tile_dims(const idp_dg* h, int* tx, int* ty) {
   const int p = h->d.p;
+  const int v = h->metric ? 0 : h->variant;   // curved meshes: the first shape only
   *tx = *ty = 1;
   switch (family(h)) {
-    case 0: return tile_dims_adv1(p, h->variant, tx, ty);
-    case 1: return tile_dims_adv2(p, h->variant, tx, ty);
-    case 2: return tile_dims_burg1(p, h->variant, tx, ty);
-    case 3: return tile_dims_burg2(p, h->variant, tx, ty);
-    case 4: return tile_dims_euler1(p, h->variant, tx, ty);
-    case 5: return tile_dims_euler2(p, h->variant, tx, ty);
-    case 6: return tile_dims_euler53_1(p, h->variant, tx, ty);
-    case 7: return tile_dims_euler53_2(p, h->variant, tx, ty);
-    case 8: return tile_dims_euler75_1(p, h->variant, tx, ty);
-    case 9: return tile_dims_euler75_2(p, h->variant, tx, ty);
-    case 11: return tile_dims_advv2(p, h->variant, tx, ty);
+    case 0: return tile_dims_adv1(p, v, tx, ty);
+    case 1: return tile_dims_adv2(p, v, tx, ty);
+    case 2: return tile_dims_burg1(p, v, tx, ty);
+    case 3: return tile_dims_burg2(p, v, tx, ty);
+    case 4: return tile_dims_euler1(p, v, tx, ty);
+    case 5: return tile_dims_euler2(p, v, tx, ty);
+    case 6: return tile_dims_euler53_1(p, v, tx, ty);
+    case 7: return tile_dims_euler53_2(p, v, tx, ty);
+    case 8: return tile_dims_euler75_1(p, v, tx, ty);
+    case 9: return tile_dims_euler75_2(p, v, tx, ty);
+    case 11: return tile_dims_advv2(p, v, tx, ty);
   }
 }
 
@@ -268,6 +297,7 @@ StageArgs make_stage_args(const idp_dg* h, const double* u_n, const double* u_s,
   a.gmin = h->d.gmin;
   a.gmax = h->d.gmax;
   a.bnd = h->bnd;
+  a.S.metric = h->metric;
   return a;
 }
 
@@ -287,6 +317,7 @@ MaxDtArgs make_dt_args(const idp_dg* h, const double* u) {
   a.ph = h->ph;
   a.T = h->T;
   a.bnd = h->bnd;
+  a.metric = h->metric;
   return a;
 }
 
@@ -334,6 +365,11 @@ int batch_kernels(int fam, int p, int variant, BatchKernels* k) {
   return -1;
 }
 
+void drop_graph(idp_dg* h) {
+  retire_graph(&h->retired, &h->graph, &h->exec, &h->g_done);
+  h->g_u = nullptr;
+}
+
 }  // namespace idp_host
 
 using namespace idp_host;
@@ -342,11 +378,6 @@ namespace {
 
 bool overlaps(const double* a, const double* b, long long n) {
   return a < b + n && b < a + n;
-}
-
-void drop_graph(idp_dg* h) {
-  retire_graph(&h->retired, &h->graph, &h->exec, &h->g_done);
-  h->g_u = nullptr;
 }
 
 // the low-order CFL bound of u into out[0] (device), two launches
@@ -574,6 +605,7 @@ void idp_dg_destroy(idp_dg* h) {
   drop_graph(h);
   reap_graphs(&h->retired, true);
   if (h->cap) hipStreamDestroy(h->cap);
+  hipFree(h->metric);   // allocated by idp_dg_set_mesh
   if (h->owns) {
     hipFree(h->buf1);
     hipFree(h->buf2);

@@ -43,7 +43,7 @@
 
 namespace idp {
 
-template <int EQ, int DIM, int P, int TX, int TY, int PAD>
+template <int EQ, int DIM, int P, int TX, int TY, int PAD, bool CURV = false>
 struct CfgP {
   static constexpr int N1 = P + 1;
   static constexpr int NP = DIM == 2 ? N1 * N1 : N1;    // nodes per element
@@ -98,19 +98,29 @@ struct CfgP {
   static constexpr int A_X = A_U + NC * CSU;
   static constexpr int A_FX = A_X + NAUX * CSU;
   static constexpr int A_FY = A_FX + NC * CSX;
-  static constexpr int A_END = A_FY + NC * CSY;
+  // curved meshes: the flux grids A_FX / A_FY hold the contravariant fluxes
+  // of the high-order metric terms, A_GX / A_GY those of the modified
+  // (corrected) terms, and A_M the eight metric terms of every slot
+  static constexpr int A_GX = A_FY + NC * CSY;
+  static constexpr int A_GY = A_GX + (CURV ? NC * CSX : 0);
+  static constexpr int A_M = A_GY + (CURV ? NC * CSY : 0);
+  static constexpr int A_END = A_M + (CURV ? 8 * CSU : 0);
   // region B (aliases A): phase 3 results, read in phases 4-5
   static constexpr int B_FLX = 0;
   static constexpr int B_FLY = B_FLX + NC * COX;
   static constexpr int B_UBX = B_FLY + NC * COY;
   static constexpr int B_UBY = B_UBX + COX;
-  static constexpr int B_RBX = B_UBY + COY;
+  // curved meshes: the bar state of the right (upper) node of each face
+  // (B_UBX / B_UBY hold the left (lower) node's)
+  static constexpr int B_UBX2 = B_UBY + COY;
+  static constexpr int B_UBY2 = B_UBX2 + (CURV ? COX : 0);
+  static constexpr int B_RBX = B_UBY2 + (CURV ? COY : 0);
   static constexpr int B_RBY = B_RBX + NC * COX;
   static constexpr int B_END = B_RBY + NC * COY;
   // region C: Euler search data, written once the low-order fluxes are
   // consumed; it overwrites them where it fits
   static constexpr int C_SIZE = is_euler(EQ) ? (NC + 4 + DIM) * CSO : 0;
-  static constexpr int C_UL = C_SIZE <= (NC + 1) * (COX + COY) ? B_FLX : B_END;   // [NC][CSO]
+  static constexpr int C_UL = C_SIZE <= (NC + (CURV ? 2 : 1)) * (COX + COY) ? B_FLX : B_END;   // [NC][CSO]
   static constexpr int C_KM = C_UL + (is_euler(EQ) ? NC * CSO : 0);
   static constexpr int C_AZ = C_KM + (is_euler(EQ) ? CSO : 0);   // bound U of the node
   static constexpr int C_G2 = C_AZ + (is_euler(EQ) ? CSO : 0);   // 2d dt/m of the node
@@ -143,14 +153,14 @@ struct CfgP {
 
 // The bank padding is 4 doubles unless it would lower the number of
 // workgroups whose LDS fits in a CU's 160 KB.
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV>
 constexpr int lds_pad() {
-  constexpr int k0 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 0>::LDS * 8);
-  constexpr int k4 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 4>::LDS * 8);
+  constexpr int k0 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 0, CURV>::LDS * 8);
+  constexpr int k4 = 160 * 1024 / (CfgP<EQ, DIM, P, TX, TY, 4, CURV>::LDS * 8);
   return k4 == k0 ? 4 : 0;
 }
-template <int EQ, int DIM, int P, int TX, int TY>
-using Cfg = CfgP<EQ, DIM, P, TX, TY, lds_pad<EQ, DIM, P, TX, TY>()>;
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
+using Cfg = CfgP<EQ, DIM, P, TX, TY, lds_pad<EQ, DIM, P, TX, TY, CURV>(), CURV>;
 
 // Where a tile lies: its first element column and row, and how many of its
 // TX x TY elements exist (tiles on the high edges of the mesh are ragged).
@@ -681,11 +691,17 @@ __device__ inline void exterior_state(const Bnd& bnd, const Halo& hs, int n, dou
 // Phases 1-2: own nodes (one per thread, into Uown) and the halo ring
 // (threads h < NH) into the slot grid, with their auxiliaries and, with
 // FLUX, their fluxes.  Returns after the stores; the caller synchronises.
-template <int EQ, int DIM, int P, int TX, int TY, bool FLUX>
+// On a curved mesh (CURV) every slot also stages its eight metric terms,
+// the own nodes' flux grids hold the contravariant fluxes of the high-order
+// terms (A_FX, A_FY) and of the corrected terms (A_GX, A_GY), halo slots
+// store no flux (an element face takes the flux of both states along its
+// normal), and *det receives det(J) of the own node.
+template <int EQ, int DIM, int P, int TX, int TY, bool FLUX, bool CURV = false>
 __device__ inline void load_tile(double* lds, const double* __restrict__ u, long long nn, const TileGeo& tg,
                                  int nx, int ny, const Phys& ph, const Bnd& bnd, double* Uown,
-                                 unsigned int* bad_flag) {
-  using C = Cfg<EQ, DIM, P, TX, TY>;
+                                 unsigned int* bad_flag, const double* __restrict__ metric = nullptr,
+                                 double* det = nullptr) {
+  using C = Cfg<EQ, DIM, P, TX, TY, CURV>;
   constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, NX = is_euler(EQ) ? 5 : C::NAUX > 0 ? C::NAUX : 1;
   constexpr int NXW = C::NAUX;   // auxiliaries stored in the slot arrays
   const int tid = threadIdx.x;
@@ -697,14 +713,22 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
   Halo hs;
   const bool halo = tid < C::NH && halo_of<DIM, P, TX, TY>(tid, tg, nx, ny, bnd.open, &hs);
   // both loads in flight before any use
-  double V[NC];
+  double V[NC], Mo[CURV ? 9 : 1], Mh[CURV ? 8 : 1];
   if (own) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) Uown[c] = u[c * nn + g];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Mo[q] = metric[q * nn + g];
+    }
   }
   if (halo) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) V[c] = u[c * nn + hs.g];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Mh[q] = metric[q * nn + hs.g];
+    }
   }
   bool bad = false;
   if (own) {
@@ -722,7 +746,21 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
 #pragma unroll
     for (int q = 0; q < NXW; ++q) lds[C::A_X + q * C::CSU + t] = X[q];
     if constexpr (FLUX && is_euler(EQ)) lds[C::S_AL + t] = X[4];
-    if constexpr (FLUX) {
+    if constexpr (CURV) {
+      double Fx[NC], Fy[NC];
+      flux_k<EQ, DIM>(0, Uown, X, pr, ph, Fx);
+      flux_k<EQ, DIM>(1, Uown, X, pr, ph, Fy);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        lds[C::A_FX + c * C::CSX + C::fx(i, j)] = Mo[0] * Fx[c] + Mo[1] * Fy[c];
+        lds[C::A_FY + c * C::CSY + C::fy(i, j)] = Mo[2] * Fx[c] + Mo[3] * Fy[c];
+        lds[C::A_GX + c * C::CSX + C::fx(i, j)] = Mo[4] * Fx[c] + Mo[5] * Fy[c];
+        lds[C::A_GY + c * C::CSY + C::fy(i, j)] = Mo[6] * Fx[c] + Mo[7] * Fy[c];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) lds[C::A_M + q * C::CSU + t] = Mo[q];
+      *det = Mo[8];
+    } else if constexpr (FLUX) {
       double F[NC];
       flux_k<EQ, DIM>(0, Uown, X, pr, ph, F);
 #pragma unroll
@@ -751,7 +789,10 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
 #pragma unroll
     for (int q = 0; q < NXW; ++q) lds[C::A_X + q * C::CSU + t] = X[q];
     if constexpr (FLUX && is_euler(EQ)) lds[C::S_AL + t] = X[4];
-    if constexpr (FLUX) {
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) lds[C::A_M + q * C::CSU + t] = Mh[q];
+    } else if constexpr (FLUX) {
       double F[NC];
       flux_k<EQ, DIM>(hs.k, V, X, pr, ph, F);
       const int o = hs.k == 0 ? C::A_FX + C::fx(hs.hi, hs.hj) : C::A_FY + C::fy(hs.hi, hs.hj);
@@ -916,6 +957,187 @@ __device__ inline int chunk_dir(int ch) {
   return ch >= C::CEX + C::CIX ? 1 : 0;
 }
 
+// ----------------------------------------------------------------------
+// curved meshes (Sec. 2.3 metric terms, Sec. 3.1 corrected terms)
+// ----------------------------------------------------------------------
+
+// The flux along a (scaled) normal n, F(U) . n.  X: the auxiliaries (Euler
+// 1/rho first).
+template <int EQ, int DIM>
+__device__ inline void flux_dot(const double* U, const double* X, const Phys& ph, const double* n,
+                                double* Fn) {
+  if constexpr (EQ == EQ_ADV) {
+    Fn[0] = (ph.vel0 * n[0] + ph.vel1 * n[1]) * U[0];
+  } else if constexpr (EQ == EQ_BURG) {
+    Fn[0] = 0.5 * U[0] * U[0] * (ph.vel0 * n[0] + ph.vel1 * n[1]);
+  } else {
+    const double mn = U[1] * n[0] + U[2] * n[1];
+    const double vn = mn * X[0];
+    const double pr = (ph.gamma - 1.0) * (U[3] - 0.5 * (U[1] * U[1] + U[2] * U[2]) * X[0]);
+    Fn[0] = mn;
+    Fn[1] = U[1] * vn + pr * n[0];
+    Fn[2] = U[2] * vn + pr * n[1];
+    Fn[3] = vn * (U[3] + pr);
+  }
+}
+
+// Upper bound of the wave speeds of the Riemann problem (UL | UR) along
+// the unit vector nh.
+template <int EQ, int DIM>
+__device__ inline double lambda_n(const double* UL, const double* XL, const double* UR, const double* XR,
+                                  const double* nh, const Phys& ph) {
+  if constexpr (EQ == EQ_ADV) {
+    return fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
+  } else if constexpr (EQ == EQ_BURG) {
+    return fmax(fabs(UL[0]), fabs(UR[0])) * fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
+  } else {
+    return euler_lambda<gn_of(EQ)>((UL[1] * nh[0] + UL[2] * nh[1]) * XL[0],
+                                   (UR[1] * nh[0] + UR[2] * nh[1]) * XR[0], XL, XR, ph);
+  }
+}
+
+// The difference of the limited component's flux, F_0(UR) - F_0(UL), as a
+// vector (the momentum for Euler).
+template <int EQ>
+__device__ inline void flux_diff0(const double* UL, const double* UR, const Phys& ph, double* d) {
+  if constexpr (is_euler(EQ)) {
+    d[0] = UR[1] - UL[1];
+    d[1] = UR[2] - UL[2];
+  } else {
+    const double f = EQ == EQ_BURG ? 0.5 * (UR[0] * UR[0] - UL[0] * UL[0]) : UR[0] - UL[0];
+    d[0] = f * ph.vel0;
+    d[1] = f * ph.vel1;
+  }
+}
+
+// Face item q of direction K (kind INT or element faces) of a tile on a
+// curved mesh, the counterpart of face_item.  With J the corrected metric
+// row K of a node (|J| its length, Jh = J/|J|):
+//  - interior subcell face (L, R): the viscosity coefficient of eq. dij,
+//    2 d_LR / w_t = max(|J_R| lambda(L, R, Jh_R), |J_L| lambda(L, R, Jh_L))
+//    =: lt (the two wave speeds of eq. dij along n_LR and n_RL), the
+//    low-order flux 1/2 (G_L + G_R) - lt/2 (U_R - U_L) from the corrected
+//    contravariant fluxes G, the bar states of L and R,
+//    1/2 (U_L + U_R) - J_R . (F_R - F_L) / (2 lt) and the same with J_L,
+//    and rbar = w_t (f^L - f^H) with f^H from the high-order contravariant
+//    fluxes;
+//  - element face: the high-order metric row K of the lower node is the
+//    face's scaled normal n, the flux is |n| times the Lax-Friedrichs flux
+//    along n/|n| (F(U) . n taken from both states), and both bar states are
+//    1/2 (U_L + U_R) - (n/|n|) . (F_R - F_L) / (2 lambda).
+template <int EQ, int DIM, int P, int TX, int TY, int K, bool INT>
+__device__ __forceinline__ void face_item_c(const double* lds, const Phys& ph, int q, const TileGeo& tg,
+                                            double* FLo, double* RBo, double& UBo, double& UBo2, int& o) {
+  using C = Cfg<EQ, DIM, P, TX, TY, true>;
+  constexpr int NC = C::NC, N1 = C::N1, GX = C::GX, NX = C::NAUX > 0 ? C::NAUX : 1;
+  int i, j, f = 0, el;
+  if constexpr (K == 0) {
+    const int jmax = tg.th * N1;
+    if constexpr (INT) {
+      j = q / (TX * P);
+      const int r = q - j * (TX * P);
+      el = r / P;
+      f = r - el * P + 1;
+      i = el * N1 + f;
+      if (!(j < jmax && el < tg.tw)) return;
+    } else {
+      j = q / (TX + 1);
+      el = q - j * (TX + 1);
+      i = el * N1;
+      if (!(j < jmax && el <= tg.tw)) return;
+    }
+  } else {
+    const int r = q / GX;
+    i = q - r * GX;
+    if constexpr (INT) {
+      el = r / P;
+      f = r - el * P + 1;
+      j = el * N1 + f;
+      if (!(i < tg.tw * N1 && el < tg.th)) return;
+    } else {
+      el = r;
+      j = el * N1;
+      if (!(i < tg.tw * N1 && el <= tg.th)) return;
+    }
+  }
+  const int sR = C::sl(i, j), sL = K == 0 ? sR - 1 : sR - C::RP;
+  const int fR = K == 0 ? C::fx(i, j) : C::fy(i, j), fL = K == 0 ? fR - 1 : fR - GX;
+  double UL[NC], UR[NC], XL[NX], XR[NX];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    UL[c] = lds[C::A_U + c * C::CSU + sL];
+    UR[c] = lds[C::A_U + c * C::CSU + sR];
+  }
+#pragma unroll
+  for (int x = 0; x < C::NAUXF; ++x) {
+    XL[x] = lds[C::A_X + x * C::CSU + sL];
+    XR[x] = lds[C::A_X + x * C::CSU + sR];
+  }
+  const double* M = lds + C::A_M;
+  const double avg = 0.5 * (UL[0] + UR[0]);
+  double dF[2];
+  flux_diff0<EQ>(UL, UR, ph, dF);
+  if constexpr (INT) {
+    const double JL[2] = {M[(4 + 2 * K) * C::CSU + sL], M[(5 + 2 * K) * C::CSU + sL]};
+    const double JR[2] = {M[(4 + 2 * K) * C::CSU + sR], M[(5 + 2 * K) * C::CSU + sR]};
+    const double mL = sqrt(JL[0] * JL[0] + JL[1] * JL[1]), mR = sqrt(JR[0] * JR[0] + JR[1] * JR[1]);
+    const double hL[2] = {JL[0] / mL, JL[1] / mL}, hR[2] = {JR[0] / mR, JR[1] / mR};
+    const double lt = fmax(mR * lambda_n<EQ, DIM>(UL, XL, UR, XR, hR, ph),
+                           mL * lambda_n<EQ, DIM>(UL, XL, UR, XR, hL, ph));
+    const double* G = lds + (K == 0 ? C::A_GX : C::A_GY);
+    constexpr int FS = K == 0 ? C::CSX : C::CSY;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (G[c * FS + fL] + G[c * FS + fR]) - 0.5 * lt * (UR[c] - UL[c]);
+    UBo = lt > 0.0 ? avg - (JR[0] * dF[0] + JR[1] * dF[1]) / (2.0 * lt) : avg;
+    UBo2 = lt > 0.0 ? avg - (JL[0] * dF[0] + JL[1] * dF[1]) / (2.0 * lt) : avg;
+    // f^H of the element line through this face, and rbar = w_t (f^L - f^H)
+    const int tr = K == 0 ? j % N1 : i % N1;
+    const double sc = lds[C::S_W + tr];
+    const double* qr = lds + C::S_Q + (f - 1) * N1;
+    const double* Fg = lds + (K == 0 ? C::A_FX : C::A_FY);
+    const int base = K == 0 ? C::fx(el * N1, j) : C::fy(i, el * N1);
+    constexpr int st = K == 0 ? 1 : GX;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double* Fl = Fg + c * FS + base;
+      double fh = Fl[0];
+#pragma unroll
+      for (int e = 0; e <= P; ++e) fh += qr[e] * Fl[e * st];
+      RBo[c] = sc * (FLo[c] - fh);
+    }
+  } else {
+    const double n[2] = {M[(2 * K) * C::CSU + sL], M[(2 * K + 1) * C::CSU + sL]};
+    const double mn = sqrt(n[0] * n[0] + n[1] * n[1]);
+    const double nh[2] = {n[0] / mn, n[1] / mn};
+    const double lam = lambda_n<EQ, DIM>(UL, XL, UR, XR, nh, ph);
+    double FnL[NC], FnR[NC];
+    flux_dot<EQ, DIM>(UL, XL, ph, n, FnL);
+    flux_dot<EQ, DIM>(UR, XR, ph, n, FnR);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) FLo[c] = 0.5 * (FnL[c] + FnR[c]) - 0.5 * (mn * lam) * (UR[c] - UL[c]);
+    UBo = lam > 0.0 ? avg - (nh[0] * dF[0] + nh[1] * dF[1]) / (2.0 * lam) : avg;
+    UBo2 = UBo;
+  }
+  o = K == 0 ? C::ox(i, j) : C::oy(i, j);
+}
+
+template <int EQ, int DIM, int P, int TX, int TY>
+__device__ __forceinline__ void face_chunk_c(const double* lds, const Phys& ph, int ch, int lane,
+                                             const TileGeo& tg, double* FLo, double* RBo, double& UBo,
+                                             double& UBo2, int& o) {
+  using C = Cfg<EQ, DIM, P, TX, TY, true>;
+  constexpr int X1 = C::CEX, X2 = X1 + C::CIX, Y1 = X2 + C::CEY;
+  if (ch < X1) {
+    face_item_c<EQ, DIM, P, TX, TY, 0, false>(lds, ph, ch * 64 + lane, tg, FLo, RBo, UBo, UBo2, o);
+  } else if (ch < X2) {
+    face_item_c<EQ, DIM, P, TX, TY, 0, true>(lds, ph, (ch - X1) * 64 + lane, tg, FLo, RBo, UBo, UBo2, o);
+  } else if (ch < Y1) {
+    face_item_c<EQ, DIM, P, TX, TY, 1, false>(lds, ph, (ch - X2) * 64 + lane, tg, FLo, RBo, UBo, UBo2, o);
+  } else if (ch < C::NCHUNK) {
+    face_item_c<EQ, DIM, P, TX, TY, 1, true>(lds, ph, (ch - Y1) * 64 + lane, tg, FLo, RBo, UBo, UBo2, o);
+  }
+}
+
 // Subcell-resolution smoothness factor of every element of the tile
 // (Sec. 4.4) from the limited component in the slot grid: modal
 // coefficients c = M u (tensor product in 2-D), the energy fraction of the
@@ -1004,10 +1226,11 @@ __device__ inline double smoothness_tile(const double* u0, const double* M, cons
 // doubles of LDS, with the degree tables T.  Shared by the plain kernel
 // (the tiles of one solve) and the batched work-list kernel (the tiles of
 // every solve of one degree).
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, const Tables& T, const Bnd& bnd,
                                            int tile) {
-  using C = Cfg<EQ, DIM, P, TX, TY>;
+  using C = Cfg<EQ, DIM, P, TX, TY, CURV>;
+  static_assert(!CURV || (DIM == 2 && EQ != EQ_ADVV), "curved meshes: 2-D, flux F(u)");
   constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, GX = C::GX;
   const int tid = threadIdx.x;
   const Solve& S = A.S;
@@ -1037,8 +1260,9 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
 #pragma unroll
     for (int c = 0; c < NC; ++c) Un[c] = S.u_n[c * nn + g];
   }
-  load_tile<EQ, DIM, P, TX, TY, true>(lds, S.u_s, nn, tg, S.nx, S.ny, A.ph, bnd, U,
-                                      A.diag ? &A.diag->bad_input : nullptr);
+  double detn = 1.0;   // det(J) of the own node (curved meshes)
+  load_tile<EQ, DIM, P, TX, TY, true, CURV>(lds, S.u_s, nn, tg, S.nx, S.ny, A.ph, bnd, U,
+                                            A.diag ? &A.diag->bad_input : nullptr, S.metric, &detn);
   tr.store(lds + C::S_W, lds + C::S_Q, lds + C::S_IW, modal ? lds + C::S_M : nullptr, modal ? lds + C::S_NK : nullptr);
   if (tid == 0) *reinterpret_cast<int*>(lds + C::S_LN) = 0;
   __syncthreads();
@@ -1071,7 +1295,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   // ---- phase 3: subcell faces ----
   // one work item per subcell face, in wave-uniform chunks
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM];
+  double rFL[C::NITEM][NC], rRB[C::NITEM][NC], rUB[C::NITEM], rUB2[CURV ? C::NITEM : 1];
   int rO[C::NITEM];
 #pragma unroll
   for (int it = 0; it < C::NITEM; ++it) {
@@ -1079,7 +1303,13 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
     rO[it] = -1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) rFL[it][c] = rRB[it][c] = 0.0;
-    face_chunk<EQ, DIM, P, TX, TY>(lds, A.ph, S, wv + it * C::NW, lane, tg, rFL[it], rRB[it], rUB[it], rO[it]);
+    if constexpr (CURV) {
+      rUB2[it] = 0.0;
+      face_chunk_c<EQ, DIM, P, TX, TY>(lds, A.ph, wv + it * C::NW, lane, tg, rFL[it], rRB[it], rUB[it],
+                                       rUB2[it], rO[it]);
+    } else {
+      face_chunk<EQ, DIM, P, TX, TY>(lds, A.ph, S, wv + it * C::NW, lane, tg, rFL[it], rRB[it], rUB[it], rO[it]);
+    }
   }
   __syncthreads();  // region A is dead from here on
 #pragma unroll
@@ -1093,6 +1323,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
           lds[C::B_RBX + c * C::COX + o] = rRB[it][c];
         }
         lds[C::B_UBX + o] = rUB[it];
+        if constexpr (CURV) lds[C::B_UBX2 + o] = rUB2[it];
       } else {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1100,6 +1331,7 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
           lds[C::B_RBY + c * C::COY + o] = rRB[it][c];
         }
         lds[C::B_UBY + o] = rUB[it];
+        if constexpr (CURV) lds[C::B_UBY2 + o] = rUB2[it];
       }
     }
   }
@@ -1114,7 +1346,13 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   auto RBk = [&](int k, int c, int side) -> double {
     return k == 0 ? lds[C::B_RBX + c * C::COX + ox0 + side] : lds[C::B_RBY + c * C::COY + oy0 + side * GX];
   };
+  // the bar state of the node toward its neighbour on side `side` of
+  // direction k (on a curved mesh the node is the right node of its side-0
+  // face and the left node of its side-1 face)
   auto UBk = [&](int k, int side) -> double {
+    if constexpr (CURV) {
+      if (side == 0) return k == 0 ? lds[C::B_UBX2 + ox0] : lds[C::B_UBY2 + oy0];
+    }
     return k == 0 ? lds[C::B_UBX + ox0 + side] : lds[C::B_UBY + oy0 + side * GX];
   };
   double uL[NC], alpha = 1.0, m = 1.0;
@@ -1127,10 +1365,21 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   if (own) {
     const double wa = lds[C::S_W + a];
     const double wb = DIM == 2 ? lds[C::S_W + b] : 1.0;
-    m = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
-    const double cx = dt * (lds[C::S_IW + a] * S.ihx);
-    const double cy = DIM == 2 ? dt * (lds[C::S_IW + b] * S.ihy) : 0.0;
-    dtm = DIM == 2 ? cx * (lds[C::S_IW + b] * S.ihy) : cx;
+    double cx, cy;
+    if constexpr (CURV) {
+      // m = w_a w_b det(J); the line scale of the fluxes is w_b (x-lines)
+      // or w_a (y-lines), so dt w_b / m = dt / (w_a det(J))
+      m = wa * wb * detn;
+      const double idet = 1.0 / detn;
+      cx = dt * (lds[C::S_IW + a] * idet);
+      cy = dt * (lds[C::S_IW + b] * idet);
+      dtm = cx * lds[C::S_IW + b];
+    } else {
+      m = DIM == 2 ? wa * wb * S.hx * S.hy : wa * S.hx;
+      cx = dt * (lds[C::S_IW + a] * S.ihx);
+      cy = DIM == 2 ? dt * (lds[C::S_IW + b] * S.ihy) : 0.0;
+      dtm = DIM == 2 ? cx * (lds[C::S_IW + b] * S.ihy) : cx;
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       double d = (FLk(0, c, 0) - FLk(0, c, 1)) * cx;
@@ -1375,10 +1624,10 @@ __device__ __forceinline__ void stage_tile(double* lds, const StageArgs& A, cons
   }
 }
 
-template <int EQ, int DIM, int P, int TX, int TY>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void stage_kernel(StageArgs A) {
-  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY>::LDS];
-  stage_tile<EQ, DIM, P, TX, TY>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x));
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY, CURV>::BS)) void stage_kernel(StageArgs A) {
+  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY, CURV>::LDS];
+  stage_tile<EQ, DIM, P, TX, TY, CURV>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------
@@ -1388,12 +1637,14 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void stage_kernel(St
 // for Euler the velocity components and the auxiliaries c, c p^-ex,
 // (gamma+1)/(2 gamma p); for Burgers the state; for a velocity field beta.
 // Each quantity is one array of the slot grid, 64 doubles apart.
-template <int EQ, int DIM, int P, int TX, int TY>
+// On a curved mesh the slot also stages its eight metric terms.
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 struct DtCfg {
   using C = Cfg<EQ, DIM, P, TX, TY>;
   static constexpr int NWS = is_euler(EQ) ? DIM + 3 : EQ == EQ_BURG ? 1 : EQ == EQ_ADVV ? 2 : 0;
   static constexpr int WS = 0;                             // [NWS][CSU]
-  static constexpr int LX = WS + NWS * C::CSU;             // wave speeds of the x-faces [NOX]
+  static constexpr int WM = WS + NWS * C::CSU;             // curved: metric terms [8][CSU]
+  static constexpr int LX = WM + (CURV ? 8 * C::CSU : 0);  // wave speeds of the x-faces [NOX]
   static constexpr int LY = LX + C::NOX;                   // of the y-faces [NOY]
   static constexpr int W = LY + C::NOY;                    // Gauss-Lobatto weights
   static constexpr int R = W + C::N1;
@@ -1440,12 +1691,32 @@ __device__ inline double lambda_ws(const double* wl, const double* wr, const Phy
   }
 }
 
+// Wave speed of the pair (left, right) along the unit vector nh from the
+// staged inputs (Euler: velocity components first, then c, c p^-ex,
+// (gamma+1)/(2 gamma p)).
+template <int EQ, int DIM>
+__device__ inline double lambda_ws_n(const double* wl, const double* wr, const double* nh, const Phys& ph) {
+  if constexpr (EQ == EQ_ADV) {
+    return fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
+  } else if constexpr (EQ == EQ_BURG) {
+    return fmax(fabs(wl[0]), fabs(wr[0])) * fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
+  } else {
+    const double XL[4] = {0.0, wl[DIM], wl[DIM + 1], wl[DIM + 2]};
+    const double XR[4] = {0.0, wr[DIM], wr[DIM + 1], wr[DIM + 2]};
+    return euler_lambda<gn_of(EQ)>(wl[0] * nh[0] + wl[1] * nh[1], wr[0] * nh[0] + wr[1] * nh[1], XL, XR, ph);
+  }
+}
+
 // Wave speed of face item q of direction K of a tile into the time-step
 // kernel's arrays (every face of the tile: element faces and interior ones).
-template <int EQ, int DIM, int P, int TX, int TY, int K>
+// On a curved mesh (CURV) the face's value is the one the stage kernel uses
+// in its graph viscosity: max(|J_R| lambda(Jh_R), |J_L| lambda(Jh_L)) with
+// the corrected metric rows J on an interior subcell face, and |n| lambda(n/|n|)
+// with the high-order row of the lower node on an element face.
+template <int EQ, int DIM, int P, int TX, int TY, int K, bool CURV = false>
 __device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, const TileGeo& tg) {
   using C = Cfg<EQ, DIM, P, TX, TY>;
-  using D = DtCfg<EQ, DIM, P, TX, TY>;
+  using D = DtCfg<EQ, DIM, P, TX, TY, CURV>;
   constexpr int N1 = C::N1;
   int i, j;
   if constexpr (K == 0) {
@@ -1466,17 +1737,35 @@ __device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, cons
     wl[x] = lds[D::WS + x * C::CSU + sL];
     wr[x] = lds[D::WS + x * C::CSU + sR];
   }
-  const double lam = lambda_ws<EQ, DIM, K>(wl, wr, ph);
+  double lam;
+  if constexpr (CURV) {
+    const double* M = lds + D::WM;
+    const bool elem = (K == 0 ? i : j) % N1 == 0;   // an element face
+    if (elem) {
+      const double n[2] = {M[(2 * K) * C::CSU + sL], M[(2 * K + 1) * C::CSU + sL]};
+      const double mn = sqrt(n[0] * n[0] + n[1] * n[1]);
+      const double nh[2] = {n[0] / mn, n[1] / mn};
+      lam = mn * lambda_ws_n<EQ, DIM>(wl, wr, nh, ph);
+    } else {
+      const double JL[2] = {M[(4 + 2 * K) * C::CSU + sL], M[(5 + 2 * K) * C::CSU + sL]};
+      const double JR[2] = {M[(4 + 2 * K) * C::CSU + sR], M[(5 + 2 * K) * C::CSU + sR]};
+      const double mL = sqrt(JL[0] * JL[0] + JL[1] * JL[1]), mR = sqrt(JR[0] * JR[0] + JR[1] * JR[1]);
+      const double hL[2] = {JL[0] / mL, JL[1] / mL}, hR[2] = {JR[0] / mR, JR[1] / mR};
+      lam = fmax(mR * lambda_ws_n<EQ, DIM>(wl, wr, hR, ph), mL * lambda_ws_n<EQ, DIM>(wl, wr, hL, ph));
+    }
+  } else {
+    lam = lambda_ws<EQ, DIM, K>(wl, wr, ph);
+  }
   if constexpr (K == 0) lds[D::LX + C::ox(i, j)] = lam;
   else lds[D::LY + C::oy(i, j)] = lam;
 }
 
 // the minimum of one tile into *out
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, const Tables& T, const Bnd& bnd,
                                            int tile, double* out) {
   using C = Cfg<EQ, DIM, P, TX, TY>;
-  using D = DtCfg<EQ, DIM, P, TX, TY>;
+  using D = DtCfg<EQ, DIM, P, TX, TY, CURV>;
   constexpr int NC = C::NC, NP = C::NP, N1 = C::N1, GX = C::GX;
   const int tid = threadIdx.x;
   const int nx = A.nx, ny = A.ny;
@@ -1495,14 +1784,22 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   const long long g = ((long long)(tg.ey0 + ley) * nx + tg.ex0 + lex) * NP + (DIM == 2 ? b * N1 + a : a);
   Halo hs;
   const bool halo = tid < C::NH && halo_of<DIM, P, TX, TY>(tid, tg, nx, ny, bnd.open, &hs);
-  double Uo[NC], V[NC];
+  double Uo[NC], V[NC], Mo[CURV ? 9 : 1], Mh[CURV ? 8 : 1];
   if (own) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) Uo[c] = A.u[c * A.nn + g];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Mo[q] = A.metric[q * A.nn + g];
+    }
   }
   if (halo) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) V[c] = A.u[c * A.nn + hs.g];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Mh[q] = A.metric[q * A.nn + hs.g];
+    }
   }
   if (own) {
     double ws[D::NWS1];
@@ -1510,6 +1807,10 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
     const int t = C::sl(i, j);
 #pragma unroll
     for (int x = 0; x < D::NWS; ++x) lds[D::WS + x * C::CSU + t] = ws[x];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) lds[D::WM + q * C::CSU + t] = Mo[q];
+    }
   }
   if (halo) {
     if (hs.ext)   // exterior state of an open side
@@ -1519,14 +1820,18 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
     const int t = C::sl(hs.hi, hs.hj);
 #pragma unroll
     for (int x = 0; x < D::NWS; ++x) lds[D::WS + x * C::CSU + t] = ws[x];
+    if constexpr (CURV) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) lds[D::WM + q * C::CSU + t] = Mh[q];
+    }
   }
   if (tid < N1) lds[D::W + tid] = wt;
   __syncthreads();
   // wave-uniform chunks of 64 faces of one direction
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   for (int ch = wv; ch < D::CX + D::CY; ch += C::NW) {
-    if (ch < D::CX) dt_face<EQ, DIM, P, TX, TY, 0>(lds, A.ph, ch * 64 + lane, tg);
-    else if constexpr (DIM == 2) dt_face<EQ, DIM, P, TX, TY, 1>(lds, A.ph, (ch - D::CX) * 64 + lane, tg);
+    if (ch < D::CX) dt_face<EQ, DIM, P, TX, TY, 0, CURV>(lds, A.ph, ch * 64 + lane, tg);
+    else if constexpr (DIM == 2) dt_face<EQ, DIM, P, TX, TY, 1, CURV>(lds, A.ph, (ch - D::CX) * 64 + lane, tg);
   }
   __syncthreads();
   double dti = INFINITY;
@@ -1534,12 +1839,14 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
     const double wa = lds[D::W + a];
     const double wb = DIM == 2 ? lds[D::W + b] : 1.0;
     const int o = C::ox(i, j);
-    double den = (lds[D::LX + o] + lds[D::LX + o + 1]) * (DIM == 2 ? wb * A.hy : 1.0);
+    // curved: the wave speeds carry the metric scale; the line weight is
+    // w_b (x-faces) or w_a (y-faces) and m = w_a w_b det(J)
+    double den = (lds[D::LX + o] + lds[D::LX + o + 1]) * (DIM == 2 ? (CURV ? wb : wb * A.hy) : 1.0);
     if constexpr (DIM == 2) {
       const int oy = C::oy(i, j);
-      den += (lds[D::LY + oy] + lds[D::LY + oy + GX]) * (wa * A.hx);
+      den += (lds[D::LY + oy] + lds[D::LY + oy + GX]) * (CURV ? wa : wa * A.hx);
     }
-    const double m = DIM == 2 ? wa * wb * A.hx * A.hy : wa * A.hx;
+    const double m = CURV ? wa * wb * Mo[8] : DIM == 2 ? wa * wb * A.hx * A.hy : wa * A.hx;
     dti = den > 0.0 ? m / den : INFINITY;
   }
   for (int off = 32; off > 0; off >>= 1) dti = fmin(dti, __shfl_xor(dti, off));
@@ -1552,10 +1859,11 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
   }
 }
 
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void maxdt_kernel(MaxDtArgs A) {
-  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY>::LDS];
-  maxdt_tile<EQ, DIM, P, TX, TY>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x), A.partial + blockIdx.x);
+  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY, CURV>::LDS];
+  maxdt_tile<EQ, DIM, P, TX, TY, CURV>(lds, A, A.T, A.bnd, xcd_tile(blockIdx.x, gridDim.x),
+                                       A.partial + blockIdx.x);
 }
 
 // ----------------------------------------------------------------------
@@ -1685,6 +1993,37 @@ hipError_t launch_maxdt_v(int variant, const MaxDtArgs& a, hipStream_t s) {
   return launch_maxdt_t<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0)>(a, s);
 }
 
+// Curved meshes: one kernel per degree, on the first tile shape.
+template <int EQ, int DIM, int P>
+hipError_t launch_stage_curved_t(const StageArgs& a, hipStream_t s) {
+  if constexpr (DIM == 2 && EQ != EQ_ADVV) {
+    constexpr int TX = tile_x_for(DIM, P, 0), TY = tile_y_for(DIM, P, 0);
+    using C = Cfg<EQ, DIM, P, TX, TY, true>;
+    const int nb = num_tiles(a.S.nx, a.S.ny, TX, TY);
+    hipLaunchKernelGGL((stage_kernel<EQ, DIM, P, TX, TY, true>), dim3(nb), dim3(C::BS), 0, s, a);
+    return hipGetLastError();
+  } else {
+    (void)a;
+    (void)s;
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int EQ, int DIM, int P>
+hipError_t launch_maxdt_curved_t(const MaxDtArgs& a, hipStream_t s) {
+  if constexpr (DIM == 2 && EQ != EQ_ADVV) {
+    constexpr int TX = tile_x_for(DIM, P, 0), TY = tile_y_for(DIM, P, 0);
+    using C = Cfg<EQ, DIM, P, TX, TY>;
+    const int nb = num_tiles(a.nx, a.ny, TX, TY);
+    hipLaunchKernelGGL((maxdt_kernel<EQ, DIM, P, TX, TY, true>), dim3(nb), dim3(C::BS), 0, s, a);
+    return hipGetLastError();
+  } else {
+    (void)a;
+    (void)s;
+    return hipErrorInvalidValue;
+  }
+}
+
 #define IDP_DEFINE_LAUNCHERS(NAME, EQ, DIM)                                              \
   hipError_t launch_stage_##NAME(int p, int variant, const StageArgs& a, hipStream_t s) { \
     switch (p) {                                                                         \
@@ -1709,6 +2048,32 @@ hipError_t launch_maxdt_v(int variant, const MaxDtArgs& a, hipStream_t s) {
       case 6: return launch_maxdt_v<EQ, DIM, 6>(variant, a, s);                          \
       case 7: return launch_maxdt_v<EQ, DIM, 7>(variant, a, s);                          \
       case 8: return launch_maxdt_v<EQ, DIM, 8>(variant, a, s);                          \
+    }                                                                                    \
+    return hipErrorInvalidValue;                                                         \
+  }                                                                                      \
+  hipError_t launch_stage_curved_##NAME(int p, const StageArgs& a, hipStream_t s) {       \
+    switch (p) {                                                                         \
+      case 1: return launch_stage_curved_t<EQ, DIM, 1>(a, s);                            \
+      case 2: return launch_stage_curved_t<EQ, DIM, 2>(a, s);                            \
+      case 3: return launch_stage_curved_t<EQ, DIM, 3>(a, s);                            \
+      case 4: return launch_stage_curved_t<EQ, DIM, 4>(a, s);                            \
+      case 5: return launch_stage_curved_t<EQ, DIM, 5>(a, s);                            \
+      case 6: return launch_stage_curved_t<EQ, DIM, 6>(a, s);                            \
+      case 7: return launch_stage_curved_t<EQ, DIM, 7>(a, s);                            \
+      case 8: return launch_stage_curved_t<EQ, DIM, 8>(a, s);                            \
+    }                                                                                    \
+    return hipErrorInvalidValue;                                                         \
+  }                                                                                      \
+  hipError_t launch_maxdt_curved_##NAME(int p, const MaxDtArgs& a, hipStream_t s) {       \
+    switch (p) {                                                                         \
+      case 1: return launch_maxdt_curved_t<EQ, DIM, 1>(a, s);                            \
+      case 2: return launch_maxdt_curved_t<EQ, DIM, 2>(a, s);                            \
+      case 3: return launch_maxdt_curved_t<EQ, DIM, 3>(a, s);                            \
+      case 4: return launch_maxdt_curved_t<EQ, DIM, 4>(a, s);                            \
+      case 5: return launch_maxdt_curved_t<EQ, DIM, 5>(a, s);                            \
+      case 6: return launch_maxdt_curved_t<EQ, DIM, 6>(a, s);                            \
+      case 7: return launch_maxdt_curved_t<EQ, DIM, 7>(a, s);                            \
+      case 8: return launch_maxdt_curved_t<EQ, DIM, 8>(a, s);                            \
     }                                                                                    \
     return hipErrorInvalidValue;                                                         \
   }                                                                                      \

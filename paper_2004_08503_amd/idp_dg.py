@@ -67,6 +67,7 @@ def _declare(lib):
         "idp_dg_batch_tune": (ctypes.c_int, [H, ctypes.POINTER(_VP), ctypes.c_double, ctypes.c_int]),
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
         "idp_dg_set_boundary": (ctypes.c_int, [H, ctypes.c_int, _VP, _VP]),
+        "idp_dg_set_mesh": (ctypes.c_int, [H, _VP]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
         "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
         "idp_dg_batch_destroy": (None, [H]),
@@ -203,6 +204,8 @@ class Solver:
         self.nc = lib.idp_dg_num_comp(self._h)
         self.nn = lib.idp_dg_num_nodes(self._h)
         self._bnd = {}
+        if getattr(prob, "coords", None) is not None:   # curved mesh: node coordinates (2, Nn)
+            self.set_mesh(prob.coords)
         bnd = getattr(prob, "bnd", None)
         if bnd is not None:   # the problem's own boundary data, copied to the device
             for side in range(4):
@@ -259,6 +262,15 @@ class Solver:
             sp = ctypes.c_void_p(state_t.data_ptr())
         self._check(lib.idp_dg_set_boundary(self._h, int(side), ctypes.c_void_p(type_t.data_ptr()), sp))
         self._bnd[side] = (type_t, state_t)
+
+    def set_mesh(self, coords):
+        """idp_dg_set_mesh: host float64 node coordinates of shape (2, Nn),
+        x then y, in state order."""
+        import numpy as np
+        xy = np.ascontiguousarray(coords, dtype=np.float64)
+        if xy.shape != (2, self.nn):
+            raise ValueError("coords must have shape (2, %d)" % self.nn)
+        self._check(lib.idp_dg_set_mesh(self._h, ctypes.c_void_p(xy.ctypes.data)))
 
     def empty(self):
         torch = _torch()

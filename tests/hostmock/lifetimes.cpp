@@ -9,6 +9,8 @@
 //  2. The plain path: device-timestepped steps whose graph is re-captured
 //     whenever the state pointer or the CFL number changes, then destroyed
 //     with launches pending.
+//  3. A curved mesh: idp_dg_set_mesh between queued steps.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -141,6 +143,35 @@ int main(int argc, char** argv) {
   hipFree(u[0]);
   hipFree(u[1]);
   printf("plain path done\n");
+
+  // 3. curved mesh: metric set-up, replaced while steps are queued; the
+  // rejected cases leave the handle usable
+  d.nx = 5; d.ny = 4; d.p = 3;
+  if (idp_dg_create(&d, nullptr, &h)) { fprintf(stderr, "create: %s\n", idp_dg_last_error(nullptr)); return 1; }
+  const long nn = idp_dg_num_nodes(h);
+  std::vector<double> xy(2 * nn, 0.0);
+  if (idp_dg_set_mesh(h, xy.data()) != IDP_DG_EINVAL) { fprintf(stderr, "degenerate mesh accepted\n"); return 1; }
+  hipMalloc((void**)&u[0], sizeof(double) * idp_dg_num_comp(h) * nn);
+  for (int rep = 0; rep < 3; ++rep) {
+    const double amp = 0.01 * (rep + 1);
+    for (int e = 0; e < d.nx * d.ny; ++e)
+      for (int b = 0; b <= d.p; ++b)
+        for (int a = 0; a <= d.p; ++a) {
+          const long g = (long)e * (d.p + 1) * (d.p + 1) + b * (d.p + 1) + a;
+          const double X = ((e % d.nx) + a / (double)d.p) / d.nx, Y = ((e / d.nx) + b / (double)d.p) / d.ny;
+          const double s2 = std::sin(6.283185307179586 * X) * std::sin(6.283185307179586 * Y);
+          xy[g] = X + amp * s2;
+          xy[nn + g] = Y + amp * s2;
+        }
+    if (idp_dg_set_mesh(h, xy.data())) { fprintf(stderr, "set_mesh: %s\n", idp_dg_last_error(h)); return 1; }
+    for (int it = 0; it < 4; ++it)
+      if (idp_dg_step_cfl(h, u[0], 0.4)) { fprintf(stderr, "curved step_cfl: %s\n", idp_dg_last_error(h)); return 1; }
+  }
+  idp_dg_batch* cb = nullptr;
+  if (idp_dg_batch_create(&h, 1, nullptr, &cb) != IDP_DG_EINVAL) { fprintf(stderr, "curved batch accepted\n"); return 1; }
+  idp_dg_destroy(h);
+  hipFree(u[0]);
+  printf("curved path done\n");
   mock_report();
   return 0;
 }

@@ -63,4 +63,5 @@ def test_serving_and_plain_lifetimes(driver, seed):
     r = subprocess.run([driver, "60", "16", str(seed)], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr[-6000:]
     assert "served 60 requests" in r.stdout and "plain path done" in r.stdout
+    assert "curved path done" in r.stdout
     assert "live device allocations 0, pinned 0, graph execs 0" in r.stderr
