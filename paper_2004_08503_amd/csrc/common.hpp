@@ -186,6 +186,32 @@ __device__ inline double strided_min(const double* __restrict__ partial, int b, 
   return v[0];
 }
 
+// One step of a wave-wide minimum of doubles by data-parallel-primitive
+// lane moves: x = min(x, x of the lane the DPP control CTRL selects), the
+// move done on the two 32-bit halves; lanes of rows outside ROWS (and lanes
+// whose source is outside the row) keep x.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_min(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  return fmin(x, __hiloint2double(hi2, lo2));
+}
+
+// Minimum over the 64 lanes of a wave, valid in lane 63: quad permutations
+// [1,0,3,2] and [2,3,0,1], the half-row and row mirrors (every lane then
+// holds the minimum of its row of 16), lane 15 of each row broadcast into
+// rows 1 and 3, then lane 31 into rows 2 and 3.
+__device__ inline double wave_min63(double x) {
+  x = dpp_min<0xB1, 0xF>(x);
+  x = dpp_min<0x4E, 0xF>(x);
+  x = dpp_min<0x141, 0xF>(x);
+  x = dpp_min<0x140, 0xF>(x);
+  x = dpp_min<0x142, 0xA>(x);
+  x = dpp_min<0x143, 0xC>(x);
+  return x;
+}
+
 // min over partial[0..n) -> out[0] (one workgroup of 1024 threads)
 __global__ void min_reduce_kernel(const double* partial, int n, double* out);
 // per solve s: min over partial[range[2s]..range[2s+1]) -> out[s] (one workgroup per solve)

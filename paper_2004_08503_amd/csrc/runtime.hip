@@ -409,20 +409,19 @@ __global__ __launch_bounds__(256) void segmented_min_kernel(const double* partia
                                                              double* out) {
   __shared__ double red[4];
   const int s = blockIdx.x;
-  double v = strided_min<256>(partial, range[2 * s], range[2 * s + 1]);
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  double v = wave_min63(strided_min<256>(partial, range[2 * s], range[2 * s + 1]));
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) out[s] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
 __global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial, int n, double* out) {
   __shared__ double red[16];
-  double v = strided_min<1024>(partial, 0, n);
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  double v = wave_min63(strided_min<1024>(partial, 0, n));
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
+    v = red[0];
     for (int i = 1; i < 16; ++i) v = fmin(v, red[i]);
     out[0] = v;
   }

@@ -1647,8 +1647,8 @@ struct DtCfg {
   static constexpr int LX = WM + (CURV ? 8 * C::CSU : 0);  // wave speeds of the x-faces [NOX]
   static constexpr int LY = LX + C::NOX;                   // of the y-faces [NOY]
   static constexpr int W = LY + C::NOY;                    // Gauss-Lobatto weights
-  static constexpr int R = W + C::N1;
-  static constexpr int LDS = R + C::NW;
+  static constexpr int R = W + C::N1;                      // per-thread bounds [BS]
+  static constexpr int LDS = R + C::BS;
   static constexpr int CX = (C::NOX + 63) / 64;            // chunks of x-faces
   static constexpr int CY = (C::NOY + 63) / 64;
   static constexpr int NWS1 = NWS > 0 ? NWS : 1;
@@ -1849,13 +1849,16 @@ __device__ __forceinline__ void maxdt_tile(double* lds, const MaxDtArgs& A, cons
     const double m = CURV ? wa * wb * Mo[8] : DIM == 2 ? wa * wb * A.hx * A.hy : wa * A.hx;
     dti = den > 0.0 ? m / den : INFINITY;
   }
-  for (int off = 32; off > 0; off >>= 1) dti = fmin(dti, __shfl_xor(dti, off));
-  if ((tid & 63) == 0) lds[D::R + (tid >> 6)] = dti;
+  // every thread's bound to LDS; the first wave folds them, then across
+  // its lanes
+  lds[D::R + tid] = dti;
   __syncthreads();
-  if (tid == 0) {
-    double v = lds[D::R];
-    for (int w = 1; w < C::NW; ++w) v = fmin(v, lds[D::R + w]);
-    *out = v;
+  if (tid < 64) {
+    double v = lds[D::R + tid];
+#pragma unroll
+    for (int w = 1; w < C::NW; ++w) v = fmin(v, lds[D::R + tid + 64 * w]);
+    v = wave_min63(v);
+    if (tid == 63) *out = v;
   }
 }
 
