@@ -109,6 +109,33 @@ def test_stage_parity_rotated(theta):
 
 
 @pytest.mark.parametrize("kind", ["euler", "burgers"])
+def test_limiter_intermediates(kind):
+    """Bounds, entropy bound and the nodal coefficients on a curved mesh:
+    the bounds at 1e-14, the coefficients' effect on the update at 1e-12."""
+    idp_dg = _gpu()
+    from test_gpu_parity import alpha_effect
+    prob, u = case(kind, 4, 9, 7, seed=11)
+    dt = 0.5 * oracle.max_dt(prob, u)
+    ref, tr = oracle.fe(prob, u, dt, trace=True)
+    sv = idp_dg.Solver(prob)
+    out = sv.empty()
+    g = sv.stage_trace(None, dev(u), out, dt, 0).cpu().numpy()
+    sc = np.abs(u[0]).max()
+    np.testing.assert_allclose(g[0], tr["umin"], rtol=0, atol=1e-14 * sc)
+    np.testing.assert_allclose(g[1], tr["umax"], rtol=0, atol=1e-14 * sc)
+    if kind == "euler":
+        np.testing.assert_allclose(g[2], tr["kmin"], rtol=1e-14, atol=0)
+    _, w = oracle.gl(prob.p)
+    m = np.tile(np.outer(w, w).reshape(-1), prob.nx * prob.ny) * ometric.metric_terms(prob)[8]
+    for q, key in ((3, "alpha_z"), (4, "alpha")):
+        eff = alpha_effect(prob, tr, dt, g[q] - tr[key], m) / np.abs(u).max(axis=1)[:, None]
+        assert eff.max() <= 1e-12, (key, eff.max())
+    assert (tr["alpha"] < 1).any()
+    assert rel_err(out.cpu().numpy(), ref) <= 1e-12
+    sv.close()
+
+
+@pytest.mark.parametrize("kind", ["euler", "burgers"])
 def test_max_dt_parity(kind):
     idp_dg = _gpu()
     prob, u = case(kind, 4, 13, 9, seed=5)

@@ -35,6 +35,39 @@ def rel_err(a, b):
     return (np.abs(a - b).max(axis=1) / scale).max()
 
 
+def alpha_effect(prob, tr, dt, da, m=None):
+    """Largest change that nodal-coefficient differences da can make in an
+    updated state: per node |da_i| dt/m_i times the sum of |rbar| over its
+    subcell faces (its face coefficients are min(alpha_i, alpha_j)), per
+    component relative to that component's largest stage input.  The
+    coefficient of a node whose corrections are tiny is ill-conditioned
+    (a ratio of rounding-size terms) while its effect is not, so this is
+    what parity fixes at the state tolerance."""
+    n1 = prob.p + 1
+    _, w = oracle.gl(prob.p)
+    ne = prob.nx * prob.ny
+    hx = prob.lx / prob.nx
+    if prob.dim == 2:
+        hy = prob.ly / prob.ny
+        if m is None:   # Cartesian masses (a curved mesh passes its own)
+            m = np.tile((np.outer(w, w) * hx * hy).reshape(-1), ne)   # node (a, b) -> w_b w_a
+        shape = (-1, ne, n1, n1)
+    else:
+        m = np.tile(w * hx, ne)
+        shape = (-1, ne, 1, n1)
+    rb = np.abs(tr["rbar"])                              # [k][c][node]
+    tot = np.zeros(rb.shape[1:])
+    for k in range(prob.dim):
+        plus = rb[k].reshape(shape)
+        minus = np.zeros_like(plus)
+        if k == 0:
+            minus[..., 1:] = plus[..., :-1]
+        else:
+            minus[:, :, 1:, :] = plus[:, :, :-1, :]
+        tot += (plus + minus).reshape(rb.shape[1:])
+    return np.abs(da)[None, :] * dt / m[None, :] * tot
+
+
 def to_dev(u):
     return torch.from_numpy(np.ascontiguousarray(u)).to("cuda")
 
@@ -257,6 +290,11 @@ def test_limiter_intermediates_match_oracle(wl):
         np.testing.assert_allclose(g[2], tr["kmin"], rtol=1e-14, atol=0)
     np.testing.assert_allclose(g[3], tr["alpha_z"], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
+    # the coefficients' effect on the update, at the state tolerance
+    scale = np.abs(wl.u0).max(axis=1)[:, None]
+    for q, key in ((3, "alpha_z"), (4, "alpha")):
+        eff = alpha_effect(prob, tr, dt, g[q] - tr[key]) / scale
+        assert eff.max() <= 1e-12, (key, eff.max())
     assert (tr["alpha"] < 1).any()
     sv.close()
 
@@ -334,6 +372,8 @@ def test_smoothness_indicator_relaxed_bounds_match_oracle(wl):
     np.testing.assert_allclose(g[0], tr["umin"], rtol=0, atol=1e-14 * sc)
     np.testing.assert_allclose(g[1], tr["umax"], rtol=0, atol=1e-14 * sc)
     np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
+    eff = alpha_effect(prob, tr, dt, g[4] - tr["alpha"]) / np.abs(wl.u0).max(axis=1)[:, None]
+    assert eff.max() <= 1e-12, eff.max()
     # the relaxation changed the bounds somewhere (elements that are not
     # rough): they are not the strict local ones
     _, trs = oracle.fe(wl.prob, wl.u0, dt, trace=True)
@@ -384,6 +424,12 @@ def test_elementwise_intermediates_match_oracle():
     g = sv.stage_trace(None, to_dev(wl.u0), out, dt, 0).cpu().numpy()
     np.testing.assert_allclose(g[3], tr["alpha_z"], rtol=0, atol=1e-9)
     np.testing.assert_allclose(g[4], tr["alpha"], rtol=0, atol=1e-9)
+    # elementwise: the element's coefficient scales its nodes' whole
+    # corrections u^H - u^L
+    corr = np.abs(tr["uH"] - tr["uL"]).reshape(prob.nc, -1, 25).max(axis=2)
+    da = np.abs(g[4] - tr["alpha"]).reshape(-1, 25).max(axis=1)
+    eff = (da[None, :] * corr) / np.abs(wl.u0).max(axis=1)[:, None]
+    assert eff.max() <= 1e-12, eff.max()
     a = g[4].reshape(-1, 25)
     assert np.all(a == a[:, :1]) and (a < 1).any()
     assert rel_err(out.cpu().numpy(), ref) <= 1e-12
