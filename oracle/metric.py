@@ -20,9 +20,16 @@ reference square [0,1]^2):
   the reference operator, once per degree), as the paper describes.
 
 Returns the (9, Nn) array of idp_ref_desc.metric: the four high-order
-terms, the four modified terms det(J) J^-1 + C, and det(J).
+terms, the four modified terms det(J) J^-1 + C, and det(J).  The last two
+results are kept (read-only) and returned again for the same degree, mesh
+and coordinates, so that stepping a large curved mesh does not recompute
+them for every oracle call.
 """
+import hashlib
+
 import numpy as np
+
+_CACHE = []   # [(key, array)], most recent last, at most two entries
 
 
 def _tables(p):
@@ -51,6 +58,19 @@ def _lo_operator(p, Dh, w):
 
 def metric_terms(prob):
     """The (9, Nn) metric array of a 2-D curved mesh given by prob.coords."""
+    xy = np.ascontiguousarray(prob.coords, dtype=np.float64)
+    key = (prob.p, prob.nx, prob.ny, xy.shape, hashlib.sha1(xy.tobytes()).hexdigest())
+    for k, a in _CACHE:
+        if k == key:
+            return a
+    out = _metric_terms(prob)
+    out.setflags(write=False)
+    _CACHE.append((key, out))
+    del _CACHE[:-2]
+    return out
+
+
+def _metric_terms(prob):
     p, n1 = prob.p, prob.p + 1
     D, Dh, w = _tables(p)
     Dn = D / w[:, None]                      # plain derivative matrix l_c'(xi_a)

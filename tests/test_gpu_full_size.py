@@ -10,6 +10,10 @@
 - 2-D Burgers on a 128^2 mesh, p = 3 (262 144 nodes), 100 device-timestepped
   SSP-RK3 steps at CFL 1/2 against the oracle stepped with the same time
   steps, on every node, to 1e-9;
+- the same Euler workload on the bench's curved mesh (the nodes moved by
+  0.05 sin 2 pi x sin 2 pi y), 10 device-timestepped steps against the
+  oracle stepped with the device's time steps (each to 1e-12, every node
+  after 10 steps to 1e-10);
 - the batched mix of 64 independent Euler solves (32^2 to 256^2 elements,
   p = 2..6, 49.6 M nodes), too large for the oracle: one batched step
   must equal every solve's own plain step bitwise (a property that holds
@@ -81,6 +85,31 @@ def test_euler_256_p4_full_run():
     err = rel_err(u.cpu().numpy(), ref)
     print("Euler 256^2 p = 4, 50 steps: max relative error %.2e" % err)
     assert err <= 1e-9, err
+
+
+def test_euler_256_p4_curved_steps():
+    idp_dg = _gpu()
+    import os
+    wl = W.euler_2d()
+    prob = wl.prob.replace(coords=W.perturbed_coords(wl.prob, 0.05))
+    assert (prob.nx, prob.ny, prob.p) == (256, 256, 4)
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(prob)
+        u = torch.from_numpy(wl.u0.copy()).cuda()
+        ref = wl.u0.copy()
+        for n in range(10):
+            sv.step_cfl(u, wl.cfl)
+            dt = sv.last_dt()
+            assert dt == pytest.approx(wl.cfl * oracle.max_dt(prob, ref), rel=1e-12)
+            ref = oracle.step(prob, ref, dt)
+            print("curved Euler 256^2 p = 4: step %d of 10" % (n + 1), flush=True)
+        sv.close()
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(u.cpu().numpy(), ref)
+    print("curved Euler 256^2 p = 4, 10 steps: max relative error %.2e" % err)
+    assert err <= 1e-10, err
 
 
 def test_batched_64_solve_mix_one_step():
