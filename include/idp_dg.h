@@ -322,6 +322,12 @@ int idp_dg_diagnostics(idp_dg* h, idp_dg_diag* out);
  * NULL).  Never NULL. */
 const char* idp_dg_last_error(const idp_dg* h);
 
+/* Provenance: the first 16 hex digits of the SHA-256 of the sources this
+ * library was built from (every file of its source directory and this
+ * header, in name order), or "unknown" for a build that did not set it.
+ * Static string, never NULL. */
+const char* idp_dg_build_hash(void);
+
 /* ------------------------------------------------------------------ */
 /* Batched execution: many independent solves of uneven mesh size and  */
 /* degree advance together.  Per degree present, one work-list launch  */

@@ -874,4 +874,9 @@ const char* idp_dg_last_error(const idp_dg* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }
 
+#ifndef IDP_DG_SOURCE_HASH
+#define IDP_DG_SOURCE_HASH "unknown"
+#endif
+const char* idp_dg_build_hash(void) { return IDP_DG_SOURCE_HASH; }
+
 }  // extern "C"

@@ -69,6 +69,7 @@ def _declare(lib):
         "idp_dg_set_boundary": (ctypes.c_int, [H, ctypes.c_int, _VP, _VP]),
         "idp_dg_set_mesh": (ctypes.c_int, [H, _VP]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
+        "idp_dg_build_hash": (ctypes.c_char_p, []),
         "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
         "idp_dg_batch_destroy": (None, [H]),
         "idp_dg_batch_update": (ctypes.c_int, [H, ctypes.POINTER(H), ctypes.c_int]),
@@ -95,6 +96,18 @@ import torch  # noqa: E402,F401
 if not os.path.exists(LIB_PATH):
     raise ImportError("libidp_dg.so is not built (run python -m paper_2004_08503_amd.build)")
 lib = _declare(ctypes.CDLL(LIB_PATH))
+
+
+def build_hash():
+    """The source hash the loaded library was built from."""
+    return lib.idp_dg_build_hash().decode()
+
+
+# a library built from other sources than the ones beside it is refused
+from . import build as _build  # noqa: E402
+if build_hash() != _build.source_hash():
+    raise ImportError("libidp_dg.so was built from other sources (library %s, sources %s): rebuild it "
+                      "(python -m paper_2004_08503_amd.build)" % (build_hash(), _build.source_hash()))
 
 
 def header_symbols():

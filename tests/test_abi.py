@@ -21,6 +21,14 @@ def test_exports_every_declared_symbol():
         assert hasattr(idp_dg.lib, n)
 
 
+def test_library_built_from_these_sources():
+    """The loaded library carries the hash of the sources it was built from
+    (the binding refuses to load one built from other sources)."""
+    from paper_2004_08503_amd import build
+    h = idp_dg.build_hash()
+    assert len(h) == 16 and h == build.source_hash()
+
+
 @pytest.mark.parametrize("bad", [
     dict(p=0), dict(p=9), dict(dim=3), dict(nx=0), dict(eq=5), dict(gamma=1.0),
     dict(gamma=1.8), dict(limiter=-1), dict(dim=1, ny=3), dict(lx=0.0), dict(lx=float("nan")),
