@@ -199,7 +199,8 @@ int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const doub
  * direction (curved meshes are periodic), a handle created in a caller
  * workspace (which must not allocate), or a node with det(J) not positive
  * or a non-finite coordinate.  Handles on curved meshes cannot join a
- * batch. */
+ * batch, and a batch refuses to step (IDP_DG_EINVAL) a member that was
+ * given a curved mesh after joining it. */
 int idp_dg_set_mesh(idp_dg* h, const double* coords);
 
 /* Release the handle and the buffers it allocated.  NULL-safe. */

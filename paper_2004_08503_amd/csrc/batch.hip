@@ -293,6 +293,7 @@ int check_states(idp_dg_batch* b, double* const* u) {
     idp_dg* h = b->s[i];
     const long long ni = (long long)h->nc * h->nn;
     if (!u[i]) return bfail(b, IDP_DG_EINVAL, "u[i] is NULL");
+    if (h->metric) return bfail(b, IDP_DG_EINVAL, "a solve was given a curved mesh after joining the batch");
     if (!bnd_ready(h)) return bfail(b, IDP_DG_EINVAL, "a solve has an open side without boundary conditions");
     for (idp_dg* o : b->s) {
       const long long no = (long long)o->nc * o->nn;

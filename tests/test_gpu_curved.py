@@ -227,6 +227,16 @@ def test_rejected_meshes_and_handles():
     sv.step_cfl(ud, 0.5)
     with pytest.raises(idp_dg.IdpError):
         idp_dg.Batch([sv])
+    # a member given a curved mesh after joining: the batch refuses to step it
+    flat = idp_dg.Solver(prob.replace(coords=None))
+    batch = idp_dg.Batch([flat])
+    uf = dev(u)
+    batch.step_cfl([uf], 0.5)
+    flat.set_mesh(prob.coords)
+    with pytest.raises(idp_dg.IdpError):
+        batch.step_cfl([uf], 0.5)
+    batch.close()
+    flat.close()
     with pytest.raises(idp_dg.IdpError):   # a caller workspace must not allocate
         idp_dg.Solver(prob, workspace=True)
     with pytest.raises(idp_dg.IdpError):   # periodic directions only
