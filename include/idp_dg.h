@@ -301,7 +301,9 @@ int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s,
  * synchronises that stream.  A cached idp_dg_step_cfl graph is rebuilt on
  * its next call if the shape changed.  Returns 0, IDP_DG_EINVAL (NULL u,
  * bad cfl or reps, u overlapping the handle's buffers, an open side
- * without conditions) or IDP_DG_EHIP.
+ * without conditions) or IDP_DG_EHIP.  On a curved mesh (idp_dg_set_mesh),
+ * which runs the first shape whatever the setting, it times nothing and
+ * reports the current setting.
  *
  * idp_dg_tile_shape: the current shape (-1 for NULL).
  * idp_dg_set_tile_shape: 0 <= shape < IDP_DG_NUM_TILE_SHAPES, else

@@ -785,6 +785,10 @@ int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape) {
   const long long n = (long long)h->nc * h->nn;
   if (overlaps(u, h->buf1, n) || overlaps(u, h->buf2, n))
     return fail(h, IDP_DG_EINVAL, "u overlaps the handle's buffers");
+  if (h->metric) {   // curved meshes run one tile shape: nothing to choose
+    if (shape) *shape = h->variant;
+    return 0;
+  }
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = hipEventCreate(&ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&ev[1]);

@@ -225,6 +225,7 @@ def test_rejected_meshes_and_handles():
     sv.set_mesh(prob.coords)          # the handle is still usable
     ud = dev(u)
     sv.step_cfl(ud, 0.5)
+    assert sv.tune(ud) == sv.tile_shape   # one tile shape on a curved mesh: nothing timed
     with pytest.raises(idp_dg.IdpError):
         idp_dg.Batch([sv])
     # a member given a curved mesh after joining: the batch refuses to step it
