@@ -158,3 +158,49 @@ def test_bounds_hold_on_a_curved_mesh(kind):
         pr = (g - 1) * (out[3] - 0.5 * (out[1] ** 2 + out[2] ** 2) / out[0])
         K = pr * out[0] ** -g
         assert (out[0] > 0).all() and (K >= tr["kmin"] * (1 - 1e-12)).all()
+
+
+def test_correction_is_the_minimum_norm_solution():
+    """The oracle's corrected terms solve eq. metric-perturbation and the
+    correction C is its minimum-norm solution.  Per element and physical
+    direction j, with A = [W (x) Dhat^T, Dhat^T (x) W] (eq. kronecker, node
+    (a, b) at b (p+1) + a, the first factor acting on b):
+    - A [Jidp_xi,j; Jidp_eta,j] equals the boundary term sum_e B_e n_ej 1
+      assembled from the face values of the high-order terms;
+    - C is orthogonal to the null space of A (the minimum-norm solution lies
+      in the range of A^T).  Null vectors are built by hand: for any nodal
+      phi, z = [(M (x) I) phi; -(I (x) M) phi] with M = W^-1 Dhat^T gives
+      A z = (Dhat^T (x) Dhat^T) phi - (Dhat^T (x) Dhat^T) phi = 0."""
+    prob = curved(W.Problem(dim=2, nx=4, ny=3, p=3, eq=W.EULER), amp=0.05)
+    p, n1 = prob.p, prob.p + 1
+    _, w = oracle.gl(p)
+    Dt = oracle.dhat(p).T                       # Dhat^T
+    Wm = np.diag(w)
+    M = np.diag(1.0 / w) @ Dt
+    A = np.hstack([np.kron(Wm, Dt), np.kron(Dt, Wm)])
+    met = ometric.metric_terms(prob).reshape(9, -1, n1, n1)    # [q][e][b][a]
+    rng = np.random.default_rng(3)
+    phis = rng.standard_normal((6, n1, n1))
+    for phi in phis:   # the hand-built null vectors are null vectors
+        z = np.concatenate([(M @ phi).reshape(-1), (-(phi @ M.T)).reshape(-1)])
+        assert np.abs(A @ z).max() <= 1e-13 * np.abs(z).max()
+    worst_eq, worst_orth = 0.0, 0.0
+    for e in range(met.shape[1]):
+        for j in range(2):
+            J_xi, J_eta = met[j, e], met[2 + j, e]
+            G_xi, G_eta = met[4 + j, e], met[6 + j, e]
+            bnd = np.zeros((n1, n1))
+            bnd[:, 0] -= w * J_xi[:, 0]
+            bnd[:, p] += w * J_xi[:, p]
+            bnd[0, :] -= w * J_eta[0, :]
+            bnd[p, :] += w * J_eta[p, :]
+            lhs = A @ np.concatenate([G_xi.reshape(-1), G_eta.reshape(-1)])
+            scale = np.abs(J_xi).max() + np.abs(J_eta).max()
+            worst_eq = max(worst_eq, np.abs(lhs - bnd.reshape(-1)).max() / scale)
+            C = np.concatenate([(G_xi - J_xi).reshape(-1), (G_eta - J_eta).reshape(-1)])
+            assert np.abs(C).max() > 1e-6 * scale          # a real correction on this mesh
+            for phi in phis:
+                z = np.concatenate([(M @ phi).reshape(-1), (-(phi @ M.T)).reshape(-1)])
+                worst_orth = max(worst_orth, abs(C @ z) / (np.linalg.norm(C) * np.linalg.norm(z)))
+    assert worst_eq <= 1e-13, worst_eq
+    assert worst_orth <= 1e-12, worst_orth
