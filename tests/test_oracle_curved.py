@@ -204,3 +204,27 @@ def test_correction_is_the_minimum_norm_solution():
                 worst_orth = max(worst_orth, abs(C @ z) / (np.linalg.norm(C) * np.linalg.norm(z)))
     assert worst_eq <= 1e-13, worst_eq
     assert worst_orth <= 1e-12, worst_orth
+
+
+def test_high_order_terms_meet_the_discrete_metric_identities():
+    """eq. metric for the high-order terms: per element and physical
+    direction j, d/dxi (J_xi,j) + d/deta (J_eta,j) = 0 at every node, the
+    derivatives by the Gauss-Lobatto derivative matrix (so that a constant
+    state's high-order residual vanishes); and det(J) from the cross
+    product of the same derivatives (the Cartesian cell area on a Cartesian
+    mesh)."""
+    for p in (2, 4, 6):
+        prob = curved(W.Problem(dim=2, nx=3, ny=4, p=p, eq=W.EULER), amp=0.05)
+        n1 = p + 1
+        _, w = oracle.gl(p)
+        Dn = oracle.dmat(p) / w[:, None]             # l_c'(xi_a)
+        met = ometric.metric_terms(prob).reshape(9, -1, n1, n1)   # [q][e][b][a]
+        scale = np.abs(met[:4]).max()
+        for j in range(2):
+            d_xi = np.einsum("ac,ebc->eba", Dn, met[j])          # along a (xi)
+            d_eta = np.einsum("bc,eca->eba", Dn, met[2 + j])     # along b (eta)
+            assert np.abs(d_xi + d_eta).max() <= 1e-12 * scale, (p, j)
+            assert np.abs(d_xi).max() > 1e-3 * scale             # the terms do vary
+        cart = cartesian_coords(prob.replace(coords=None))
+        det = ometric.metric_terms(cart)[8]
+        assert np.allclose(det, (prob.lx / prob.nx) * (prob.ly / prob.ny), rtol=1e-13, atol=0)
