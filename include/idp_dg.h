@@ -203,6 +203,16 @@ int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const doub
  * given a curved mesh after joining it. */
 int idp_dg_set_mesh(idp_dg* h, const double* coords);
 
+/* The metric array idp_dg_set_mesh computes, written to the host array
+ * metric (9 * Nn doubles, caller-owned): metric[q * Nn + node] with
+ * q = 0..3 the high-order terms det(J) J^-1 (rows xi, eta; columns x, y),
+ * q = 4..7 the corrected terms (eq. metric-perturbation), q = 8 det(J).
+ * Host only: no device, no handle.  coords as for idp_dg_set_mesh.
+ * IDP_DG_EINVAL for a bad desc, a desc a curved mesh does not support, NULL
+ * arrays or a mesh idp_dg_set_mesh would refuse (idp_dg_last_error(NULL)
+ * gives the message). */
+int idp_dg_mesh_metric(const idp_dg_desc* desc, const double* coords, double* metric);
+
 /* Release the handle and the buffers it allocated.  NULL-safe. */
 void idp_dg_destroy(idp_dg* h);
 

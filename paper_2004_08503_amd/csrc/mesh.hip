@@ -16,6 +16,7 @@
 #include "handle.hpp"
 
 using namespace idp;
+using idp_host::desc_ok;
 using idp_host::fail;
 
 namespace {
@@ -166,27 +167,53 @@ bool element_metric(const LoOperator& lo, const double* w, const double* Dn, con
   return true;
 }
 
+// The metric array of a mesh of ne elements of degree p into met (9 nn
+// doubles); on failure the message goes to *why.
+bool mesh_metric(int p, long long ne, long long nn, const double* coords, double* met, std::string* why) {
+  double w[MAXP + 1], Dn[(MAXP + 1) * (MAXP + 1)];
+  idp_host::gl_derivative(p, w, Dn);
+  LoOperator lo;
+  if (!lo.build(p, w)) {
+    *why = "curved meshes: singular correction system";
+    return false;
+  }
+  for (long long e = 0; e < ne; ++e)
+    if (!element_metric(lo, w, Dn, coords, nn, e, met)) {
+      *why = "curved meshes: det(J) not positive or a non-finite value in element " + std::to_string(e);
+      return false;
+    }
+  return true;
+}
+
+// The problems a curved mesh supports; false with the reason otherwise.
+bool curved_ok(const idp_dg_desc* d, std::string* why) {
+  if (d->dim != 2) *why = "curved meshes: 2-D problems only";
+  else if (d->eq == IDP_DG_ADVECTION_FIELD) *why = "curved meshes: not with an advection velocity field";
+  else if (d->bc[0] != IDP_DG_BC_PERIODIC || d->bc[1] != IDP_DG_BC_PERIODIC)
+    *why = "curved meshes: periodic directions only";
+  else return true;
+  return false;
+}
+
 }  // namespace
+
+extern "C" int idp_dg_mesh_metric(const idp_dg_desc* desc, const double* coords, double* metric) {
+  std::string why;
+  if (!desc_ok(desc, &why) || !curved_ok(desc, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  if (!coords || !metric) return fail(nullptr, IDP_DG_EINVAL, "coords or metric is NULL");
+  const long long n1 = desc->p + 1, ne = (long long)desc->nx * desc->ny;
+  if (!mesh_metric(desc->p, ne, ne * n1 * n1, coords, metric, &why)) return fail(nullptr, IDP_DG_EINVAL, why);
+  return 0;
+}
 
 extern "C" int idp_dg_set_mesh(idp_dg* h, const double* coords) {
   if (!h) return IDP_DG_EINVAL;
   if (!coords) return fail(h, IDP_DG_EINVAL, "coords is NULL");
-  if (h->d.dim != 2) return fail(h, IDP_DG_EINVAL, "curved meshes: 2-D problems only");
-  if (h->d.eq == IDP_DG_ADVECTION_FIELD)
-    return fail(h, IDP_DG_EINVAL, "curved meshes: not with an advection velocity field");
-  if (h->bnd.open) return fail(h, IDP_DG_EINVAL, "curved meshes: periodic directions only");
+  std::string why;
+  if (!curved_ok(&h->d, &why)) return fail(h, IDP_DG_EINVAL, why);
   if (!h->owns) return fail(h, IDP_DG_EINVAL, "curved meshes: the handle lives in a caller workspace");
-  const int p = h->d.p;
-  const long long nn = h->nn;
-  double w[MAXP + 1], Dn[(MAXP + 1) * (MAXP + 1)];
-  idp_host::gl_derivative(p, w, Dn);
-  LoOperator lo;
-  if (!lo.build(p, w)) return fail(h, IDP_DG_EINVAL, "curved meshes: singular correction system");
-  std::vector<double> met((size_t)9 * nn);
-  for (long long e = 0; e < h->ne; ++e)
-    if (!element_metric(lo, w, Dn, coords, nn, e, met.data()))
-      return fail(h, IDP_DG_EINVAL,
-                  "curved meshes: det(J) not positive or a non-finite value in element " + std::to_string(e));
+  std::vector<double> met((size_t)9 * h->nn);
+  if (!mesh_metric(h->d.p, h->ne, h->nn, coords, met.data(), &why)) return fail(h, IDP_DG_EINVAL, why);
   hipError_t err = hipStreamSynchronize(h->stream);   // queued work may read the previous mesh
   if (err == hipSuccess && !h->metric) err = hipMalloc(&h->metric, sizeof(double) * met.size());
   if (err == hipSuccess)

@@ -68,6 +68,7 @@ def _declare(lib):
         "idp_dg_diagnostics": (ctypes.c_int, [H, ctypes.POINTER(Diag)]),
         "idp_dg_set_boundary": (ctypes.c_int, [H, ctypes.c_int, _VP, _VP]),
         "idp_dg_set_mesh": (ctypes.c_int, [H, _VP]),
+        "idp_dg_mesh_metric": (ctypes.c_int, [ctypes.POINTER(Desc), _VP, _VP]),
         "idp_dg_last_error": (ctypes.c_char_p, [H]),
         "idp_dg_build_hash": (ctypes.c_char_p, []),
         "idp_dg_batch_create": (ctypes.c_int, [ctypes.POINTER(H), ctypes.c_int, _VP, ctypes.POINTER(H)]),
@@ -96,6 +97,22 @@ import torch  # noqa: E402,F401
 if not os.path.exists(LIB_PATH):
     raise ImportError("libidp_dg.so is not built (run python -m paper_2004_08503_amd.build)")
 lib = _declare(ctypes.CDLL(LIB_PATH))
+
+
+def mesh_metric(prob, coords=None):
+    """idp_dg_mesh_metric: the (9, Nn) metric array the library computes for
+    a curved mesh (host only, no GPU needed)."""
+    import numpy as np
+    xy = np.ascontiguousarray(prob.coords if coords is None else coords, dtype=np.float64)
+    desc = make_desc(prob)
+    out = np.empty((9, prob.num_nodes))
+    if xy.shape != (2, prob.num_nodes):
+        raise ValueError("coords must have shape (2, %d)" % prob.num_nodes)
+    rc = lib.idp_dg_mesh_metric(ctypes.byref(desc), ctypes.c_void_p(xy.ctypes.data),
+                                ctypes.c_void_p(out.ctypes.data))
+    if rc:
+        raise IdpError(rc, lib.idp_dg_last_error(None).decode())
+    return out
 
 
 def build_hash():
