@@ -210,7 +210,7 @@ int idp_dg_set_mesh(idp_dg* h, const double* coords);
  * Host only: no device, no handle.  coords as for idp_dg_set_mesh.
  * IDP_DG_EINVAL for a bad desc, a desc a curved mesh does not support, NULL
  * arrays or a mesh idp_dg_set_mesh would refuse (idp_dg_last_error(NULL)
- * gives the message). */
+ * gives the message; metric is then partly written). */
 int idp_dg_mesh_metric(const idp_dg_desc* desc, const double* coords, double* metric);
 
 /* Release the handle and the buffers it allocated.  NULL-safe. */
