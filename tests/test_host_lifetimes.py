@@ -1,7 +1,8 @@
 """Host-side memory safety and API lifetimes of the library.
 
 Every source of libidp_dg is compiled for the host only (kernel launches
-become runtime calls), with AddressSanitizer on the host code, and linked
+become runtime calls), with AddressSanitizer and UndefinedBehaviorSanitizer
+(fatal) on the host code, and linked
 against a stand-in for the HIP runtime (tests/hostmock/hip_mock.cpp) that
 keeps queued work pending until the host synchronises and aborts on
 misuse: a graph exec destroyed with a launch pending, double frees, pinned
@@ -34,6 +35,7 @@ def driver(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("hostmock"))
     srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
     host_only = ["--offload-host-only", "-O1", "-g", "-std=c++17", "-fPIC", "-Xarch_host", "-fsanitize=address",
+                 "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined",
                  "-Wno-unused-result", "-I", CSRC, "-I", os.path.join(ROOT, "include")]
     procs = [subprocess.Popen([HIPCC] + host_only + ["-c", os.path.join(CSRC, f), "-o", f + ".o"], cwd=d,
                               stdout=subprocess.PIPE, stderr=subprocess.PIPE) for f in srcs]
@@ -47,12 +49,13 @@ def driver(tmp_path_factory):
     with open(os.path.join(d, "blobs.cpp"), "w") as f:
         for s in blobs:
             f.write('extern "C" { char %s[16]; }\n' % s)
-    asan = ["-fsanitize=address", "-fno-omit-frame-pointer", "-O1", "-g", "-std=c++17"]
+    asan = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-O1",
+            "-g", "-std=c++17"]
     _run([CLANG] + asan + ["-c", os.path.join(MOCK, "hip_mock.cpp"), "-o", "hip_mock.o"], d)
     _run([CLANG] + asan + ["-c", "blobs.cpp", "-o", "blobs.o"], d)
     _run([CLANG] + asan + ["-I", os.path.join(ROOT, "include"), "-c", os.path.join(MOCK, "lifetimes.cpp"),
                            "-o", "lifetimes.o"], d)
-    _run([CLANG, "-fsanitize=address", "-o", "lifetimes", "lifetimes.o", "hip_mock.o", "blobs.o"] + objs, d)
+    _run([CLANG, "-fsanitize=address,undefined", "-o", "lifetimes", "lifetimes.o", "hip_mock.o", "blobs.o"] + objs, d)
     yield os.path.join(d, "lifetimes")
     shutil.rmtree(d, ignore_errors=True)
 
