@@ -313,6 +313,7 @@ int check_states(idp_dg_batch* b, double* const* u) {
 extern "C" {
 
 int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_batch** out) {
+  const idp_host::Range trace_range("idp_dg_batch_create");
   if (!out) return bfail(nullptr, IDP_DG_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = check_members(solves, n, nullptr);
@@ -339,6 +340,7 @@ int idp_dg_batch_create(idp_dg* const* solves, int n, void* hip_stream, idp_dg_b
 }
 
 int idp_dg_batch_update(idp_dg_batch* b, idp_dg* const* solves, int n) {
+  const idp_host::Range trace_range("idp_dg_batch_update");
   if (!b) return IDP_DG_EINVAL;
   int rc = check_members(solves, n, b);
   if (rc) return rc;
@@ -368,6 +370,7 @@ void idp_dg_batch_destroy(idp_dg_batch* b) {
 int idp_dg_batch_num_items(const idp_dg_batch* b) { return b ? b->nitems : -1; }
 
 int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt) {
+  const idp_host::Range trace_range("idp_dg_batch_step");
   if (!b) return IDP_DG_EINVAL;
   if (!dt) return bfail(b, IDP_DG_EINVAL, "dt is NULL");
   for (int i = 0; i < b->n; ++i)
@@ -392,6 +395,7 @@ int idp_dg_batch_step(idp_dg_batch* b, double* const* u, const double* dt) {
 }
 
 int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl) {
+  const idp_host::Range trace_range("idp_dg_batch_step_cfl");
   if (!b) return IDP_DG_EINVAL;
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return bfail(b, IDP_DG_EINVAL, "cfl must be finite and > 0");
   int rc = check_states(b, u);
@@ -404,6 +408,7 @@ int idp_dg_batch_step_cfl(idp_dg_batch* b, double* const* u, double cfl) {
 }
 
 int idp_dg_batch_tune(idp_dg_batch* b, double* const* u, double cfl, int reps) {
+  const idp_host::Range trace_range("idp_dg_batch_tune");
   if (!b) return IDP_DG_EINVAL;
   int rc = check_states(b, u);
   if (rc) return rc;

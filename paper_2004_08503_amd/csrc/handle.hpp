@@ -1,6 +1,7 @@
 // Private host-side definitions shared by the translation units of the
 // runtime (plain and batched paths).
 #pragma once
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -47,6 +48,14 @@ struct idp_dg {
 
 
 namespace idp_host {
+// A roctx range over one C-ABI call (visible to rocprofv3 --marker-trace;
+// a few tens of nanoseconds when no tool is attached).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 int family(const idp_dg* h);
 int tile_elems(const idp_dg* h);
 void tile_dims(const idp_dg* h, int* tx, int* ty);

@@ -207,6 +207,7 @@ extern "C" int idp_dg_mesh_metric(const idp_dg_desc* desc, const double* coords,
 }
 
 extern "C" int idp_dg_set_mesh(idp_dg* h, const double* coords) {
+  const idp_host::Range trace_range("idp_dg_set_mesh");
   if (!h) return IDP_DG_EINVAL;
   if (!coords) return fail(h, IDP_DG_EINVAL, "coords is NULL");
   std::string why;

@@ -459,6 +459,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
 }  // namespace
 
 int idp_dg_create(const idp_dg_desc* desc, void* hip_stream, idp_dg** out) {
+  const idp_host::Range trace_range("idp_dg_create");
   return create_impl(desc, hip_stream, nullptr, 0, out);
 }
 
@@ -470,6 +471,7 @@ long long idp_dg_workspace_bytes(const idp_dg_desc* desc) {
 
 int idp_dg_create_in(const idp_dg_desc* desc, void* hip_stream, void* workspace, long long bytes,
                      idp_dg** out) {
+  const idp_host::Range trace_range("idp_dg_create_in");
   if (!out) return fail(nullptr, IDP_DG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kWsAlign)
@@ -621,6 +623,7 @@ int idp_dg_num_comp(const idp_dg* h) { return h ? h->nc : -1; }
 
 int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s, double* u_out, double dt,
                  int stage) {
+  const idp_host::Range trace_range("idp_dg_stage");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
@@ -637,6 +640,7 @@ int idp_dg_stage(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
 
 int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
                        double dt, int stage, double* trace) {
+  const idp_host::Range trace_range("idp_dg_stage_trace");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!trace) return fail(h, IDP_DG_EINVAL, "NULL trace pointer");
@@ -655,6 +659,7 @@ int idp_dg_stage_trace(idp_dg* h, const double* u_n, const double* u_s, double* 
 }
 
 int idp_dg_step(idp_dg* h, double* u, double dt) {
+  const idp_host::Range trace_range("idp_dg_step");
   if (!h) return IDP_DG_EINVAL;
   if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
   const long long n = (long long)h->nc * h->nn;
@@ -667,6 +672,7 @@ int idp_dg_step(idp_dg* h, double* u, double dt) {
 }
 
 int idp_dg_step_cfl(idp_dg* h, double* u, double cfl) {
+  const idp_host::Range trace_range("idp_dg_step_cfl");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
@@ -715,6 +721,7 @@ int idp_dg_last_dt(idp_dg* h, double* dt) {
 }
 
 int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
+  const idp_host::Range trace_range("idp_dg_max_dt");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u || !dt) return fail(h, IDP_DG_EINVAL, "NULL pointer");
@@ -729,6 +736,7 @@ int idp_dg_max_dt(idp_dg* h, const double* u, double* dt) {
 }
 
 int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev) {
+  const idp_host::Range trace_range("idp_dg_max_dt_async");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u || !dt_dev) return fail(h, IDP_DG_EINVAL, "NULL pointer");
@@ -740,6 +748,7 @@ int idp_dg_max_dt_async(idp_dg* h, const double* u, double* dt_dev) {
 
 int idp_dg_stage_dt(idp_dg* h, const double* u_n, const double* u_s, double* u_out,
                     const double* dt_dev, double cfl, int stage) {
+  const idp_host::Range trace_range("idp_dg_stage_dt");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (stage < 0 || stage > 2) return fail(h, IDP_DG_EINVAL, "stage must be 0, 1 or 2");
@@ -777,6 +786,7 @@ int idp_dg_set_tile_shape(idp_dg* h, int shape) {
 }
 
 int idp_dg_tune(idp_dg* h, const double* u, double cfl, int reps, int* shape) {
+  const idp_host::Range trace_range("idp_dg_tune");
   if (!h) return IDP_DG_EINVAL;
   if (!bnd_ready(h)) return fail(h, IDP_DG_EINVAL, "an open side has no boundary conditions (idp_dg_set_boundary)");
   if (!u) return fail(h, IDP_DG_EINVAL, "NULL state pointer");
