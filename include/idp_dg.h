@@ -198,9 +198,10 @@ int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const doub
  * IDP_DG_EINVAL: NULL coords, a non-2-D problem, an advection field, an open
  * direction (curved meshes are periodic), a handle created in a caller
  * workspace (which must not allocate), or a node with det(J) not positive
- * or a non-finite coordinate.  Handles on curved meshes cannot join a
- * batch, and a batch refuses to step (IDP_DG_EINVAL) a member that was
- * given a curved mesh after joining it. */
+ * or a non-finite coordinate.  A batch may mix curved and Cartesian
+ * solves (its curved members step with the curved work-list kernels); a
+ * member given a new mesh after joining is picked up at the batch's next
+ * step. */
 int idp_dg_set_mesh(idp_dg* h, const double* coords);
 
 /* The metric array idp_dg_set_mesh computes, written to the host array

@@ -71,6 +71,7 @@ struct idp_dg_batch {
   // what the device blob currently describes
   std::vector<double*> cur_u;
   std::vector<unsigned> cur_bv;    // the solves' boundary versions
+  std::vector<unsigned> cur_mv;    // the solves' mesh versions
   double cur_scale = -1.0;
   int cur_mode = -1;               // 0: host time steps, 1: device bounds
   std::string err = "no error";
@@ -96,19 +97,27 @@ bool overlap(const double* a, long long na, const double* c, long long nc) {
 template <class T>
 T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
 
-// Work lists and blob layout for the current membership.
+// the work-list kernels of member h: its degree's tile shape, or on a
+// curved mesh the curved kernels of the first shape
+int member_kernels(const idp_dg_batch* b, const idp_dg* h, BatchKernels* k) {
+  return h->metric ? batch_kernels_curved(b->fam, h->d.p, k) : batch_kernels(b->fam, h->d.p, b->shape[h->d.p], k);
+}
+
+// Work lists and blob layout for the current membership: one group per
+// degree and mesh kind (Cartesian, curved).
 int plan(idp_dg_batch* b, std::vector<int>* isolve, std::vector<int>* itile, std::vector<int>* range) {
   b->groups.clear();
   isolve->clear();
   itile->clear();
   range->assign(2 * b->n, 0);
-  for (int p = 1; p <= MAXP; ++p) {
+  for (int p = 1; p <= MAXP; ++p)
+  for (int curved = 0; curved < 2; ++curved) {
     BatchGroup gr;
     gr.p = p;
     gr.ofs = (int)isolve->size();
     for (int i = 0; i < b->n; ++i) {
-      if (b->s[i]->d.p != p) continue;
-      if (batch_kernels(b->fam, p, b->shape[p], &gr.k))
+      if (b->s[i]->d.p != p || (b->s[i]->metric != nullptr) != (curved == 1)) continue;
+      if (member_kernels(b, b->s[i], &gr.k))
         return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
       const int nt = ((b->s[i]->d.nx + gr.k.tile_x - 1) / gr.k.tile_x) *
                      ((b->s[i]->d.ny + gr.k.tile_y - 1) / gr.k.tile_y);
@@ -188,7 +197,7 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
     // the tiles are those of the degree's batched kernels, whose shape may
     // differ from the member's own
     BatchKernels k;
-    if (batch_kernels(b->fam, hd->d.p, b->shape[hd->d.p], &k)) return bfail(b, IDP_DG_EINVAL, "no batched kernel");
+    if (member_kernels(b, hd, &k)) return bfail(b, IDP_DG_EINVAL, "no batched kernel");
     const int ntx = (hd->d.nx + k.tile_x - 1) / k.tile_x;
     const int nt = ntx * ((hd->d.ny + k.tile_y - 1) / k.tile_y);
     for (int st = 0; st < 3; ++st) {
@@ -208,7 +217,11 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
   if (e != hipSuccess) return bhip(b, e, "batch upload");
   b->cur_u.assign(u, u + b->n);
   b->cur_bv.resize(b->n);
-  for (int i = 0; i < b->n; ++i) b->cur_bv[i] = b->s[i]->bnd_version;
+  b->cur_mv.resize(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    b->cur_bv[i] = b->s[i]->bnd_version;
+    b->cur_mv[i] = b->s[i]->mesh_version;
+  }
   b->cur_mode = mode;
   b->cur_scale = scale;
   b->dirty = false;
@@ -217,7 +230,8 @@ int upload(idp_dg_batch* b, double* const* u, int mode, double scale) {
 
 int prepare(idp_dg_batch* b, double* const* u, int mode, double scale) {
   bool same = !b->dirty && b->cur_mode == mode && b->cur_scale == scale;
-  for (int i = 0; same && i < b->n; ++i) same = b->cur_u[i] == u[i] && b->cur_bv[i] == b->s[i]->bnd_version;
+  for (int i = 0; same && i < b->n; ++i)
+    same = b->cur_u[i] == u[i] && b->cur_bv[i] == b->s[i]->bnd_version && b->cur_mv[i] == b->s[i]->mesh_version;
   if (same) return 0;
   return upload(b, u, mode, scale);
 }
@@ -277,7 +291,6 @@ int check_members(idp_dg* const* solves, int n, idp_dg_batch* b) {
   if (!solves || n < 1) return bfail(b, IDP_DG_EINVAL, "need at least one solve");
   for (int i = 0; i < n; ++i) {
     if (!solves[i]) return bfail(b, IDP_DG_EINVAL, "NULL solve handle");
-    if (solves[i]->metric) return bfail(b, IDP_DG_EINVAL, "curved-mesh solves cannot join a batch");
     for (int j = 0; j < i; ++j)
       if (solves[j] == solves[i]) return bfail(b, IDP_DG_EINVAL, "a handle appears twice");
   }
@@ -293,7 +306,6 @@ int check_states(idp_dg_batch* b, double* const* u) {
     idp_dg* h = b->s[i];
     const long long ni = (long long)h->nc * h->nn;
     if (!u[i]) return bfail(b, IDP_DG_EINVAL, "u[i] is NULL");
-    if (h->metric) return bfail(b, IDP_DG_EINVAL, "a solve was given a curved mesh after joining the batch");
     if (!bnd_ready(h)) return bfail(b, IDP_DG_EINVAL, "a solve has an open side without boundary conditions");
     for (idp_dg* o : b->s) {
       const long long no = (long long)o->nc * o->nn;
@@ -420,7 +432,7 @@ int idp_dg_batch_tune(idp_dg_batch* b, double* const* u, double cfl, int reps) {
   for (int p = 1; p <= MAXP; ++p) {
     int big = -1;
     for (int i = 0; i < b->n; ++i)
-      if (b->s[i]->d.p == p && (big < 0 || b->s[i]->nn > b->s[big]->nn)) big = i;
+      if (b->s[i]->d.p == p && !b->s[i]->metric && (big < 0 || b->s[i]->nn > b->s[big]->nn)) big = i;
     if (big < 0) continue;
     idp_dg* h = b->s[big];
     const int keep = h->variant;

@@ -153,7 +153,8 @@ struct RetiredGraph {
   hipError_t launch_maxdt_curved_##NAME(int p, const MaxDtArgs& a, hipStream_t s); \
   void tile_dims_##NAME(int p, int variant, int* tx, int* ty);                    \
   int num_variants_##NAME(int p);                                                 \
-  int batch_kernels_##NAME(int p, int variant, BatchKernels* k);
+  int batch_kernels_##NAME(int p, int variant, BatchKernels* k);                  \
+  int batch_kernels_curved_##NAME(int p, BatchKernels* k);
 
 IDP_DECLARE_LAUNCHERS(adv1)
 IDP_DECLARE_LAUNCHERS(adv2)

@@ -32,6 +32,7 @@ struct idp_dg {
   double* partial = nullptr;   // per-workgroup minima of the time-step kernel
   double* vel = nullptr;       // IDP_DG_ADVECTION_FIELD: row then column velocities
   double* metric = nullptr;    // curved meshes (idp_dg_set_mesh): [9][nn] metric terms
+  unsigned mesh_version = 0;   // bumped by every idp_dg_set_mesh
   idp::Bnd bnd{};              // open sides: per-node conditions (idp_dg_set_boundary)
   unsigned bnd_version = 0;    // bumped by every idp_dg_set_boundary
   // cached graph of one device-timestepped step
@@ -76,6 +77,8 @@ hipError_t launch_stage(const idp_dg* h, const idp::StageArgs& a, hipStream_t s)
 bool bnd_ready(const idp_dg* h);
 // the work-list kernels of family fam, degree p, tile shape `variant`
 int batch_kernels(int fam, int p, int variant, idp::BatchKernels* k);
+// the curved-mesh work-list kernels of family fam and degree p (first tile shape)
+int batch_kernels_curved(int fam, int p, idp::BatchKernels* k);
 // tile shapes compiled per degree
 constexpr int kNumVariants = 2;
 // Retire (graph, exec, event) and destroy retired graphs whose launches

@@ -222,5 +222,6 @@ extern "C" int idp_dg_set_mesh(idp_dg* h, const double* coords) {
   if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
   if (err != hipSuccess) return fail(h, IDP_DG_EHIP, std::string("idp_dg_set_mesh: ") + hipGetErrorString(err));
   idp_host::drop_graph(h);   // a captured step holds the Cartesian kernels
+  ++h->mesh_version;         // a batch holding the handle re-plans its groups
   return 0;
 }

@@ -365,6 +365,17 @@ int batch_kernels(int fam, int p, int variant, BatchKernels* k) {
   return -1;
 }
 
+int batch_kernels_curved(int fam, int p, BatchKernels* k) {
+  switch (fam) {
+    case 1: return batch_kernels_curved_adv2(p, k);
+    case 3: return batch_kernels_curved_burg2(p, k);
+    case 5: return batch_kernels_curved_euler2(p, k);
+    case 7: return batch_kernels_curved_euler53_2(p, k);
+    case 9: return batch_kernels_curved_euler75_2(p, k);
+  }
+  return -1;
+}
+
 void drop_graph(idp_dg* h) {
   retire_graph(&h->retired, &h->graph, &h->exec, &h->g_done);
   h->g_u = nullptr;

@@ -1895,9 +1895,9 @@ constexpr int tile_y_for(int dim, int p, int variant) {
 // in scalar registers; the degree tables go straight from global memory to
 // LDS.
 // ----------------------------------------------------------------------
-template <int EQ, int DIM, int P, int TX, int TY>
-__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_stage_kernel(BatchArgs B) {
-  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY>::LDS];
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
+__global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY, CURV>::BS)) void batch_stage_kernel(BatchArgs B) {
+  __shared__ double lds[Cfg<EQ, DIM, P, TX, TY, CURV>::LDS];
   const int it = xcd_tile(blockIdx.x, gridDim.x);
   if (it >= B.nitems) return;
   const StageArgs* pa = B.args + B.item_solve[it];
@@ -1914,12 +1914,12 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_stage_ker
   A.gmax = pa->gmax;
   // the boundary arrays are indexed at run time: read them where they are
   // (a copy in this local struct would move it to scratch memory)
-  stage_tile<EQ, DIM, P, TX, TY>(lds, A, pa->T, pa->bnd, B.item_tile[it]);
+  stage_tile<EQ, DIM, P, TX, TY, CURV>(lds, A, pa->T, pa->bnd, B.item_tile[it]);
 }
 
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_maxdt_kernel(BatchDtArgs B) {
-  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY>::LDS];
+  __shared__ double lds[DtCfg<EQ, DIM, P, TX, TY, CURV>::LDS];
   const int it = xcd_tile(blockIdx.x, gridDim.x);
   if (it >= B.nitems) return;
   const MaxDtArgs* pa = B.args + B.item_solve[it];
@@ -1936,13 +1936,14 @@ __global__ __launch_bounds__((Cfg<EQ, DIM, P, TX, TY>::BS)) void batch_maxdt_ker
   A.hx = pa->hx;
   A.hy = pa->hy;
   A.ph = pa->ph;
-  maxdt_tile<EQ, DIM, P, TX, TY>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
+  A.metric = pa->metric;
+  maxdt_tile<EQ, DIM, P, TX, TY, CURV>(lds, A, pa->T, pa->bnd, B.item_tile[it], B.partial + it);
 }
 
-template <int EQ, int DIM, int P, int TX, int TY>
+template <int EQ, int DIM, int P, int TX, int TY, bool CURV = false>
 void batch_kernels_e(BatchKernels* k) {
-  k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, TX, TY>);
-  k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, TX, TY>);
+  k->stage = reinterpret_cast<const void*>(&batch_stage_kernel<EQ, DIM, P, TX, TY, CURV>);
+  k->maxdt = reinterpret_cast<const void*>(&batch_maxdt_kernel<EQ, DIM, P, TX, TY, CURV>);
   k->block = Cfg<EQ, DIM, P, TX, TY>::BS;
   k->tile_x = TX;
   k->tile_y = DIM == 2 ? TY : 1;
@@ -1956,6 +1957,18 @@ void batch_kernels_t(int variant, BatchKernels* k) {
 #endif
   (void)variant;
   batch_kernels_e<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0)>(k);
+}
+
+// curved meshes: the work-list kernels of the first tile shape
+template <int EQ, int DIM, int P>
+int batch_kernels_curved_t(BatchKernels* k) {
+  if constexpr (DIM == 2 && EQ != EQ_ADVV) {
+    batch_kernels_e<EQ, DIM, P, tile_x_for(DIM, P, 0), tile_y_for(DIM, P, 0), true>(k);
+    return 0;
+  } else {
+    (void)k;
+    return -1;
+  }
 }
 
 // tiles of a mesh of nx x ny elements
@@ -2093,6 +2106,19 @@ hipError_t launch_maxdt_curved_t(const MaxDtArgs& a, hipStream_t s) {
       case 6: batch_kernels_t<EQ, DIM, 6>(variant, k); return 0;                         \
       case 7: batch_kernels_t<EQ, DIM, 7>(variant, k); return 0;                         \
       case 8: batch_kernels_t<EQ, DIM, 8>(variant, k); return 0;                         \
+    }                                                                                    \
+    return -1;                                                                           \
+  }                                                                                      \
+  int batch_kernels_curved_##NAME(int p, BatchKernels* k) {                             \
+    switch (p) {                                                                         \
+      case 1: return batch_kernels_curved_t<EQ, DIM, 1>(k);                              \
+      case 2: return batch_kernels_curved_t<EQ, DIM, 2>(k);                              \
+      case 3: return batch_kernels_curved_t<EQ, DIM, 3>(k);                              \
+      case 4: return batch_kernels_curved_t<EQ, DIM, 4>(k);                              \
+      case 5: return batch_kernels_curved_t<EQ, DIM, 5>(k);                              \
+      case 6: return batch_kernels_curved_t<EQ, DIM, 6>(k);                              \
+      case 7: return batch_kernels_curved_t<EQ, DIM, 7>(k);                              \
+      case 8: return batch_kernels_curved_t<EQ, DIM, 8>(k);                              \
     }                                                                                    \
     return -1;                                                                           \
   }                                                                                      \

@@ -167,8 +167,15 @@ int main(int argc, char** argv) {
     for (int it = 0; it < 4; ++it)
       if (idp_dg_step_cfl(h, u[0], 0.4)) { fprintf(stderr, "curved step_cfl: %s\n", idp_dg_last_error(h)); return 1; }
   }
+  // a batch holding the curved handle, and the mesh replaced between its
+  // unsynchronised steps
   idp_dg_batch* cb = nullptr;
-  if (idp_dg_batch_create(&h, 1, nullptr, &cb) != IDP_DG_EINVAL) { fprintf(stderr, "curved batch accepted\n"); return 1; }
+  if (idp_dg_batch_create(&h, 1, nullptr, &cb)) { fprintf(stderr, "curved batch: %s\n", idp_dg_batch_last_error(nullptr)); return 1; }
+  for (int it = 0; it < 4; ++it) {
+    if (idp_dg_batch_step_cfl(cb, &u[0], 0.4)) { fprintf(stderr, "curved batch step: %s\n", idp_dg_batch_last_error(cb)); return 1; }
+    if (it == 1 && idp_dg_set_mesh(h, xy.data())) { fprintf(stderr, "set_mesh: %s\n", idp_dg_last_error(h)); return 1; }
+  }
+  idp_dg_batch_destroy(cb);
   idp_dg_destroy(h);
   hipFree(u[0]);
   printf("curved path done\n");

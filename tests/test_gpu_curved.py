@@ -226,24 +226,54 @@ def test_rejected_meshes_and_handles():
     ud = dev(u)
     sv.step_cfl(ud, 0.5)
     assert sv.tune(ud) == sv.tile_shape   # one tile shape on a curved mesh: nothing timed
-    with pytest.raises(idp_dg.IdpError):
-        idp_dg.Batch([sv])
-    # a member given a curved mesh after joining: the batch refuses to step it
-    flat = idp_dg.Solver(prob.replace(coords=None))
-    batch = idp_dg.Batch([flat])
-    uf = dev(u)
-    batch.step_cfl([uf], 0.5)
-    flat.set_mesh(prob.coords)
-    with pytest.raises(idp_dg.IdpError):
-        batch.step_cfl([uf], 0.5)
-    batch.close()
-    flat.close()
     with pytest.raises(idp_dg.IdpError):   # a caller workspace must not allocate
         idp_dg.Solver(prob, workspace=True)
     with pytest.raises(idp_dg.IdpError):   # periodic directions only
         idp_dg.Solver(prob.replace(bc=(1, 0)))
     torch.cuda.synchronize()
     sv.close()
+
+
+def test_curved_and_cartesian_solves_in_one_batch():
+    """A batch mixing curved and Cartesian Euler solves of several degrees
+    (one work-list group per degree and mesh kind): every solve equals its
+    own plain steps bitwise; a member given a curved mesh after joining is
+    stepped with the curved kernels from the next batch step on."""
+    idp_dg = _gpu()
+    rng = np.random.default_rng(31)
+    cases = []
+    for k, p in enumerate([2, 3, 3, 4, 5, 4]):
+        prob = W.Problem(dim=2, nx=int(rng.integers(4, 12)), ny=int(rng.integers(3, 10)), p=p, eq=W.EULER)
+        u = W.euler_quadrants(prob, np.random.default_rng([31, k]))
+        if k % 2 == 0:
+            prob = prob.replace(coords=W.perturbed_coords(prob, 0.04))
+        cases.append((prob, u))
+    solvers = [idp_dg.Solver(p) for p, _ in cases]
+    ub = [dev(u) for _, u in cases]
+    up = [dev(u) for _, u in cases]
+    batch = idp_dg.Batch(solvers)
+    late = cases[1][0]                  # Cartesian at first
+    late_coords = W.perturbed_coords(late, 0.05)
+    for step in range(4):
+        if step == 2:
+            solvers[1].set_mesh(late_coords)
+        batch.step_cfl(ub, 0.5)
+        for sv, u in zip(solvers, up):
+            sv.step_cfl(u, 0.5)
+        assert batch.last_dt() == [sv.last_dt() for sv in solvers]
+    torch.cuda.synchronize()
+    for a, b in zip(ub, up):
+        assert torch.equal(a, b)
+    # and a curved member of the batch against the oracle for one step
+    prob, u0 = cases[0]
+    sv0 = idp_dg.Solver(prob)
+    one = idp_dg.Batch([sv0])
+    u = dev(u0)
+    one.step_cfl([u], 0.5)
+    ref = oracle.step(prob, u0, one.last_dt()[0])
+    assert rel_err(u.cpu().numpy(), ref) <= 1e-12
+    for obj in [batch, one, sv0] + solvers:
+        obj.close()
 
 
 def test_mesh_replaced_between_steps():
