@@ -10,6 +10,8 @@
 - 2-D Burgers on a 128^2 mesh, p = 3 (262 144 nodes), 100 device-timestepped
   SSP-RK3 steps at CFL 1/2 against the oracle stepped with the same time
   steps, on every node, to 1e-9;
+- the same Euler set-up at 512^2 (6.6 M nodes): one device-timestepped
+  step against the oracle, every node to 1e-12;
 - the same Euler workload on the bench's curved mesh (the nodes moved by
   0.05 sin 2 pi x sin 2 pi y), 10 device-timestepped steps against the
   oracle stepped with the device's time steps (each to 1e-12, every node
@@ -85,6 +87,30 @@ def test_euler_256_p4_full_run():
     err = rel_err(u.cpu().numpy(), ref)
     print("Euler 256^2 p = 4, 50 steps: max relative error %.2e" % err)
     assert err <= 1e-9, err
+
+
+def test_euler_512_p4_one_step():
+    """The benchmark's Euler set-up at 512^2 (6.6 M nodes, the bench's
+    HBM-resident leg): one device-timestepped step against the oracle
+    stepped with the device's time step, every node to 1e-12."""
+    idp_dg = _gpu()
+    import os
+    wl = W.euler_2d(n=512, p=4)
+    prob = wl.prob
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(prob)
+        u = torch.from_numpy(wl.u0.copy()).cuda()
+        sv.step_cfl(u, wl.cfl)
+        dt = sv.last_dt()
+        assert dt == pytest.approx(wl.cfl * oracle.max_dt(prob, wl.u0), rel=1e-12)
+        ref = oracle.step(prob, wl.u0, dt)
+        sv.close()
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(u.cpu().numpy(), ref)
+    print("Euler 512^2 p = 4, one step: max relative error %.2e" % err)
+    assert err <= 1e-12, err
 
 
 def test_euler_256_p4_curved_steps():
