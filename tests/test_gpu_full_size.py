@@ -12,6 +12,9 @@
   steps, on every node, to 1e-9;
 - the same Euler set-up at 512^2 (6.6 M nodes): one device-timestepped
   step against the oracle, every node to 1e-12;
+- the bench's other workload legs at full size (solid body 512^2, the
+  double Mach set-up at 2400 x 600, 1-D Euler with 2^20 elements), one
+  step each, every node to 1e-12;
 - the same Euler workload on the bench's curved mesh (the nodes moved by
   0.05 sin 2 pi x sin 2 pi y), 10 device-timestepped steps against the
   oracle stepped with the device's time steps (each to 1e-12, every node
@@ -110,6 +113,43 @@ def test_euler_512_p4_one_step():
         oracle.set_threads(1)
     err = rel_err(u.cpu().numpy(), ref)
     print("Euler 512^2 p = 4, one step: max relative error %.2e" % err)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("leg", ["solid_body_512", "double_mach_2400x600", "euler_1d_2e20"])
+def test_bench_workload_legs_one_step(leg):
+    """The bench's other workload legs at their full sizes: the solid-body
+    rotation at 512^2, p = 3 (velocity field), the double Mach reflection
+    set-up at 2400 x 600, p = 3 (23 M nodes, open boundaries) and 1-D Euler
+    with 2^20 elements, p = 3: one device-timestepped step each against the
+    oracle stepped with the device's time step, every node to 1e-12."""
+    idp_dg = _gpu()
+    import os
+    import sys
+    if leg == "solid_body_512":
+        wl = W.solid_body(n=512, p=3)
+        prob, u0, cfl = wl.prob, wl.u0, wl.cfl
+    elif leg == "euler_1d_2e20":
+        wl = W.euler_1d(n=1 << 20, p=3)
+        prob, u0, cfl = wl.prob, wl.u0, wl.cfl
+    else:
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import bench
+        prob, u0 = bench.double_mach_state()
+        cfl = 0.5
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(prob)
+        u = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+        sv.step_cfl(u, cfl)
+        dt = sv.last_dt()
+        assert dt == pytest.approx(cfl * oracle.max_dt(prob, u0), rel=1e-12)
+        ref = oracle.step(prob, u0, dt)
+        sv.close()
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(u.cpu().numpy(), ref)
+    print("%s, one step: max relative error %.2e" % (leg, err))
     assert err <= 1e-12, err
 
 
