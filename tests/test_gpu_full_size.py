@@ -12,6 +12,8 @@
   steps, on every node, to 1e-9;
 - the same Euler set-up at 512^2 (6.6 M nodes): one device-timestepped
   step against the oracle, every node to 1e-12;
+- the bench's limiter-mode legs (the same 256^2 state in the four other
+  limiter modes), one step each, every node to 1e-12;
 - the bench's other workload legs at full size (solid body 512^2, the
   double Mach set-up at 2400 x 600, 1-D Euler with 2^20 elements), one
   step each, every node to 1e-12;
@@ -113,6 +115,35 @@ def test_euler_512_p4_one_step():
         oracle.set_threads(1)
     err = rel_err(u.cpu().numpy(), ref)
     print("Euler 512^2 p = 4, one step: max relative error %.2e" % err)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("mode", ["subcell_si", "elementwise", "target_only", "low_only"])
+def test_euler_256_p4_limiter_modes_one_step(mode):
+    """The bench's limiter-mode legs at full size (the 256^2 p = 4 Euler
+    state; the smoothness-indicator mode with the initial density range as
+    global bounds): one device-timestepped step against the oracle, every
+    node to 1e-12."""
+    idp_dg = _gpu()
+    import os
+    wl = W.euler_2d()
+    rho0 = wl.u0[0]
+    prob = {"subcell_si": wl.prob.replace(limiter=W.SUBCELL_SI, gmin=float(rho0.min()), gmax=float(rho0.max())),
+            "elementwise": wl.prob.replace(limiter=W.ELEMENTWISE),
+            "target_only": wl.prob.replace(limiter=W.TARGET),
+            "low_only": wl.prob.replace(limiter=W.LOW)}[mode]
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(prob)
+        u = torch.from_numpy(wl.u0.copy()).cuda()
+        sv.step_cfl(u, wl.cfl)
+        dt = sv.last_dt()
+        ref = oracle.step(prob, wl.u0, dt)
+        sv.close()
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(u.cpu().numpy(), ref)
+    print("Euler 256^2 p = 4 %s, one step: max relative error %.2e" % (mode, err))
     assert err <= 1e-12, err
 
 
