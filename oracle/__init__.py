@@ -33,9 +33,17 @@ SUBCELL, TARGET, LOW, SUBCELL_SI, ELEMENTWISE = 0, 1, 2, 3, 4
 
 def build():
     """Compile the oracle with gcc (plain FP64, no FMA contraction)."""
+    # written under a temporary name and renamed into place, so that a
+    # process loading the library never sees a partly written file
+    tmp = "%s.%d.tmp" % (_LIB_PATH, os.getpid())
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
-           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH, _SRC, "-lm"]
-    subprocess.check_call(cmd)
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+    try:
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    finally:
+        if os.path.exists(tmp):
+            os.remove(tmp)
     global _lib
     _lib = None
 
