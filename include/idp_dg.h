@@ -194,7 +194,8 @@ int idp_dg_set_boundary(idp_dg* h, int side, const signed char* type, const doub
  * a device array of 9 Nn doubles that the handle allocates (hipMalloc) and
  * frees at idp_dg_destroy; every later stage and time-step launch uses the
  * curved operators (one tile shape; idp_dg_set_tile_shape has no effect).
- * A second call replaces the mesh.  Waits for the handle's stream.
+ * A second call replaces the mesh in place.  Waits for all work queued on
+ * the device (a batch holding the handle may run on another stream).
  * IDP_DG_EINVAL: NULL coords, a non-2-D problem, an advection field, an open
  * direction (curved meshes are periodic), a handle created in a caller
  * workspace (which must not allocate), or a node with det(J) not positive

@@ -215,7 +215,9 @@ extern "C" int idp_dg_set_mesh(idp_dg* h, const double* coords) {
   if (!h->owns) return fail(h, IDP_DG_EINVAL, "curved meshes: the handle lives in a caller workspace");
   std::vector<double> met((size_t)9 * h->nn);
   if (!mesh_metric(h->d.p, h->ne, h->nn, coords, met.data(), &why)) return fail(h, IDP_DG_EINVAL, why);
-  hipError_t err = hipStreamSynchronize(h->stream);   // queued work may read the previous mesh
+  // queued work may read the previous mesh: the handle's own, and a
+  // batch's that holds the handle on another stream
+  hipError_t err = hipDeviceSynchronize();
   if (err == hipSuccess && !h->metric) err = hipMalloc(&h->metric, sizeof(double) * met.size());
   if (err == hipSuccess)
     err = hipMemcpyAsync(h->metric, met.data(), sizeof(double) * met.size(), hipMemcpyHostToDevice, h->stream);

@@ -117,6 +117,10 @@ hipError_t hipMemset(void* d, int v, size_t n) { memset(d, v, n); return hipSucc
 hipError_t hipStreamCreateWithFlags(void** s, unsigned) { Stream* st = new Stream; g_streams.insert(st); *s = st; return hipSuccess; }
 hipError_t hipStreamDestroy(void* s) { Stream* st = S(s); drain(st, ~0ull); st->live = false; return hipSuccess; }
 hipError_t hipStreamSynchronize(void* s) { Stream* st = S(s); drain(st, ~0ull); return hipSuccess; }
+hipError_t hipDeviceSynchronize() {
+  drain(&g_null, ~0ull);
+  for (auto* st : g_streams) if (st->live) drain(st, ~0ull);
+  return hipSuccess; }
 hipError_t hipEventCreateWithFlags(void** e, unsigned) { Event* ev = new Event; g_events.insert(ev); *e = ev; return hipSuccess; }
 static Event* E(void* e) { Event* ev = (Event*)e; if (!g_events.count(ev) || !ev->live) FAIL("use of a destroyed or unknown event %p", e); return ev; }
 hipError_t hipEventRecord(void* e, void* s) {
