@@ -29,8 +29,13 @@
  *     Burgers) or d+2 (Euler: rho, rho v, rho E).  Nn = nx*ny*(p+1)^d.
  *   - Device pointers are caller-owned; the library never frees them.
  *   - Work is enqueued asynchronously on the HIP stream given at creation
- *     (borrowed, not owned); only idp_dg_max_dt, idp_dg_last_dt and
- *     idp_dg_diagnostics synchronise that stream.
+ *     (borrowed, not owned); of the calls on a created handle only
+ *     idp_dg_max_dt, idp_dg_last_dt, idp_dg_diagnostics and idp_dg_tune
+ *     synchronise that stream, and idp_dg_set_mesh the whole device.
+ *   - A batch (below) steps its handles on the batch's stream, in the
+ *     handles' own stage buffers: while such work is queued, the caller
+ *     orders any other work on those handles after it (stream events or
+ *     a synchronisation).
  *   - Return codes: 0 success; IDP_DG_EINVAL (-1) bad argument, state left
  *     untouched; IDP_DG_ENOMEM (-2) allocation failure; IDP_DG_EHIP (-3) a
  *     HIP runtime error.  No call aborts or throws; idp_dg_last_error gives
