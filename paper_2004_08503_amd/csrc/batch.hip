@@ -121,6 +121,8 @@ int plan(idp_dg_batch* b, std::vector<int>* isolve, std::vector<int>* itile, std
         return bfail(b, IDP_DG_EINVAL, "no batched kernel for this degree");
       const int nt = ((b->s[i]->d.nx + gr.k.tile_x - 1) / gr.k.tile_x) *
                      ((b->s[i]->d.ny + gr.k.tile_y - 1) / gr.k.tile_y);
+      if ((long long)isolve->size() + nt > 0x7fffffffLL)   // item indices and grids are int
+        return bfail(b, IDP_DG_EINVAL, "batch too large: more than 2^31 - 1 work items");
       (*range)[2 * i] = (int)isolve->size();
       for (int t = 0; t < nt; ++t) {
         isolve->push_back(i);

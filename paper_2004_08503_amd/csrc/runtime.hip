@@ -594,7 +594,7 @@ int create_impl(const idp_dg_desc* desc, void* hip_stream, char* ws, long long w
   if (e == hipSuccess) e = hipMalloc(&h->buf2, bytes);
   if (e == hipSuccess) e = hipMalloc(&h->diag, sizeof(Diag) + 64);
   if (e == hipSuccess) e = hipMalloc(&h->dtdev, 64);
-  if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * (h->ne + 64));
+  if (e == hipSuccess) e = hipMalloc(&h->partial, sizeof(double) * ((size_t)h->ne + 64));
   if (e == hipSuccess && desc->eq == IDP_DG_ADVECTION_FIELD)
     e = hipMalloc(&h->vel, sizeof(double) * n1 * (desc->nx + desc->ny));
   if (e == hipSuccess) e = hipMemset(h->diag, 0, sizeof(Diag));
