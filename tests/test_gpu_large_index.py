@@ -7,7 +7,8 @@ tile or workgroup runs it, or how many elements the mesh has (the element
 size lx/nx is the same correctly rounded number).  So one device-timestepped
 SSP-RK3 step on the large mesh must equal, bitwise, the step of the small
 pattern mesh repeated, and its time step must equal the pattern's (a
-minimum over the same values).  The pattern's own step is checked against
+minimum over the same values); the same holds for the large mesh stepped
+in a batch beside the pattern.  The pattern's own step is checked against
 the oracle.  Two cases:
 
 - 2-D Euler at p = 4 on 4640^2 elements (538 M nodes): the flattened state
@@ -68,21 +69,45 @@ def test_repeated_pattern_beyond_2_31(name):
     assert err <= 1e-12, err
     assert dt_small == pytest.approx(wl.cfl * oracle.max_dt(small, wl.u0), rel=1e-12)
 
-    # the pattern repeated rep x rep times (state order u[c][ey][ex][node])
-    u0 = torch.from_numpy(wl.u0).cuda().view(nc, small.ny, small.nx, npe)
-    ub = u0.repeat(1, rep, rep, 1).reshape(nc, n_big)
-    del u0
+    def repeated():
+        # the pattern repeated rep x rep times (state order u[c][ey][ex][node])
+        u0 = torch.from_numpy(wl.u0).cuda().view(nc, small.ny, small.nx, npe)
+        return u0.repeat(1, rep, rep, 1).reshape(nc, n_big)
+
+    def differing(ub):
+        got = ub.view(nc, rep, small.ny, rep, small.nx, npe)
+        want = us.view(nc, 1, small.ny, 1, small.nx, npe)
+        return int((got != want).sum().item())
+
     print("%s: %d x %d elements, %d nodes, %d doubles per state" % (name, big.nx, big.ny, n_big, nc * n_big),
           flush=True)
+    ub = repeated()
     sv = idp_dg.Solver(big)
     sv.step_cfl(ub, wl.cfl)
     dt_big = sv.last_dt()
     sv.close()
     assert dt_big == dt_small, (dt_big, dt_small)
-    got = ub.view(nc, rep, small.ny, rep, small.nx, npe)
-    want = us.view(nc, 1, small.ny, 1, small.nx, npe)
-    ndiff = int((got != want).sum().item())
-    del ub, got
+    ndiff = differing(ub)
+    del ub
     torch.cuda.empty_cache()
-    print("%s: one step, nodes differing from the repeated pattern: %d" % (name, ndiff))
+    print("%s: one step, nodes differing from the repeated pattern: %d" % (name, ndiff), flush=True)
+    assert ndiff == 0
+
+    # the same step of the large mesh in a batch beside the pattern itself
+    # (one work list over both solves' tiles)
+    ub = repeated()
+    u1 = torch.from_numpy(wl.u0.copy()).cuda()
+    sb, ss = idp_dg.Solver(big), idp_dg.Solver(small)
+    bt = idp_dg.Batch([sb, ss])
+    bt.step_cfl([ub, u1], wl.cfl)
+    dts = bt.last_dt()
+    bt.close()
+    sb.close()
+    ss.close()
+    assert dts == [dt_small, dt_small], dts
+    assert torch.equal(u1, us)
+    ndiff = differing(ub)
+    del ub
+    torch.cuda.empty_cache()
+    print("%s: batched step, nodes differing from the repeated pattern: %d" % (name, ndiff))
     assert ndiff == 0
