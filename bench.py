@@ -215,7 +215,10 @@ def mode_leg(wl, prob, steps, u0=None):
     import torch
     from paper_2004_08503_amd import idp_dg
     sv = idp_dg.Solver(prob)
-    u = torch.from_numpy((wl.u0 if u0 is None else u0).copy()).to("cuda")
+    if torch.is_tensor(u0):   # a device state, stepped in place
+        u = u0
+    else:
+        u = torch.from_numpy((wl.u0 if u0 is None else u0).copy()).to("cuda")
     b1, b2 = sv.empty(), sv.empty()
     dtd = torch.empty(1, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -244,6 +247,31 @@ def mode_leg(wl, prob, steps, u0=None):
                                           / (ms.mean() * 1e-3) / 1e9),
             "limited_node_fraction": d["limited_nodes"] / (3.0 * nn * steps),
             "entropy_node_fraction": d["entropy_nodes"] / (3.0 * nn * steps), "steps": steps}
+
+
+def repeated_leg(wl, rep, steps):
+    """mode_leg on the workload's periodic state repeated rep x rep times
+    (the domain grown with it, so the elements keep their size): the same
+    per-node work on a mesh rep^2 times larger, built on the device.  It
+    needs about five state arrays of device memory (the state, the leg's
+    two stage buffers and the handle's two); skipped where that is not
+    free."""
+    import torch
+    pr = wl.prob
+    big = pr.replace(nx=pr.nx * rep, ny=pr.ny * rep, lx=pr.lx * rep, ly=pr.ly * rep)
+    state_bytes = 8 * pr.nc * big.num_nodes
+    free, _ = torch.cuda.mem_get_info()
+    if free < 5.5 * state_bytes:
+        return {"skipped": "needs %.0f GB of free device memory" % (5.5 * state_bytes / 1e9)}
+    npe = pr.nodes_per_element
+    u0 = torch.from_numpy(wl.u0).to("cuda").view(pr.nc, pr.ny, pr.nx, npe)
+    u = u0.repeat(1, rep, rep, 1).reshape(pr.nc, big.num_nodes)
+    del u0
+    out = mode_leg(wl, big, steps, u0=u)
+    del u
+    torch.cuda.empty_cache()
+    out["nodes"] = big.num_nodes
+    return out
 
 
 def double_mach_state(nx=2400, ny=600, p=3):
@@ -278,10 +306,11 @@ def workload_legs(wl):
     HBM-resident point), the paper's solid-body rotation (velocity field,
     64^2 and 512^2, p = 3), its double Mach reflection set-up at the paper's
     own resolution (open boundaries, 2400 x 600, p = 3, 23 M nodes) and a
-    large 1-D Euler problem (2^20 elements, p = 3, the Sod path), and the
+    large 1-D Euler problem (2^20 elements, p = 3, the Sod path), the
     benchmark set-up on a smoothly curved mesh (the Cartesian nodes moved
     by 0.05 sin(2 pi x) sin(2 pi y): metric terms and the corrected
-    low-order terms per node)."""
+    low-order terms per node), and the benchmark's state repeated 18 x 18
+    times (4608^2 elements, 531 M nodes, 17 GB per state)."""
     from paper_2004_08503_amd import workloads as W
     out = {}
     curved = wl.prob.replace(coords=W.perturbed_coords(wl.prob, 0.05))
@@ -290,6 +319,7 @@ def workload_legs(wl):
     big = W.euler_2d(n=512, p=4)
     out["euler_2d_512x512_p4"] = mode_leg(big, big.prob, 20)
     del big
+    out["euler_2d_4608x4608_p4"] = repeated_leg(wl, 18, 5)
     for n in (64, 512):
         sb = W.solid_body(n=n, p=3)
         out["solid_body_%dx%d_p3" % (n, n)] = mode_leg(sb, sb.prob, 30)

@@ -17,6 +17,9 @@
 - the bench's other workload legs at full size (solid body 512^2, the
   double Mach set-up at 2400 x 600, 1-D Euler with 2^20 elements), one
   step each, every node to 1e-12;
+- the bench's 4608^2 leg (the 256^2 state repeated 18 x 18 times, 531 M
+  nodes), too large for the oracle: one step bitwise equal to the 256^2
+  step repeated, which is checked against the oracle;
 - the same Euler workload on the bench's curved mesh (the nodes moved by
   0.05 sin 2 pi x sin 2 pi y), 10 device-timestepped steps against the
   oracle stepped with the device's time steps (each to 1e-12, every node
@@ -182,6 +185,50 @@ def test_bench_workload_legs_one_step(leg):
     err = rel_err(u.cpu().numpy(), ref)
     print("%s, one step: max relative error %.2e" % (leg, err))
     assert err <= 1e-12, err
+
+
+def test_bench_repeated_leg_one_step():
+    """The bench's 4608^2 leg (the 256^2 p = 4 Euler state repeated 18 x 18
+    times, 531 M nodes), too large for the oracle: its device-timestepped
+    step equals, bitwise, the 256^2 step repeated (a node's arithmetic does
+    not depend on its position, tile or mesh size; the elements keep their
+    size), with the same time step, and the 256^2 step is checked against
+    the oracle."""
+    idp_dg = _gpu()
+    import os
+    wl = W.euler_2d()
+    small, rep = wl.prob, 18
+    big = small.replace(nx=small.nx * rep, ny=small.ny * rep, lx=small.lx * rep, ly=small.ly * rep)
+    nc, npe = small.nc, small.nodes_per_element
+    free, _ = torch.cuda.mem_get_info()
+    if free < 3.3 * 8 * nc * big.num_nodes:
+        pytest.skip("needs %.0f GB of free device memory" % (3.3 * 8 * nc * big.num_nodes / 1e9))
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        sv = idp_dg.Solver(small)
+        us = torch.from_numpy(wl.u0.copy()).cuda()
+        sv.step_cfl(us, wl.cfl)
+        dt = sv.last_dt()
+        sv.close()
+        ref = oracle.step(small, wl.u0, dt)
+    finally:
+        oracle.set_threads(1)
+    err = rel_err(us.cpu().numpy(), ref)
+    assert err <= 1e-12, err
+    u0 = torch.from_numpy(wl.u0).cuda().view(nc, small.ny, small.nx, npe)
+    ub = u0.repeat(1, rep, rep, 1).reshape(nc, big.num_nodes)
+    del u0
+    sv = idp_dg.Solver(big)
+    sv.step_cfl(ub, wl.cfl)
+    assert sv.last_dt() == dt
+    sv.close()
+    ndiff = int((ub.view(nc, rep, small.ny, rep, small.nx, npe)
+                 != us.view(nc, 1, small.ny, 1, small.nx, npe)).sum().item())
+    del ub
+    torch.cuda.empty_cache()
+    print("Euler 4608^2 p = 4 (256^2 repeated), one step: %d nodes differ from the repeated 256^2 step "
+          "(256^2 against the oracle: %.2e)" % (ndiff, err))
+    assert ndiff == 0
 
 
 def test_euler_256_p4_curved_steps():
