@@ -391,13 +391,33 @@ bool overlaps(const double* a, const double* b, long long n) {
   return a < b + n && b < a + n;
 }
 
-// the low-order CFL bound of u into out[0] (device), two launches
+}  // namespace
+namespace idp {
+// per workgroup b of the grid: min over its contiguous chunk of
+// partial[0..n) -> out[b] (1024 threads)
+__global__ void chunk_min_kernel(const double* partial, int n, double* out);
+}  // namespace idp
+namespace {
+
+// Minima per workgroup that one 1024-thread workgroup folds (256 KB, a few
+// microseconds); past that a first launch of kChunks workgroups folds
+// contiguous chunks into the kChunks slots that follow the minima (the
+// array holds ne + 64 >= tiles + 64 doubles), and one workgroup folds
+// those.  The minimum does not depend on the grouping.
+constexpr int kOneGroupMinima = 32768, kChunks = 64;
+
+// the low-order CFL bound of u into out[0] (device), two or three launches
 hipError_t enqueue_max_dt(const idp_dg* h, const double* u, double* out, hipStream_t s) {
   hipError_t e = launch_maxdt(h, make_dt_args(h, u), s);
   if (e != hipSuccess) return e;
   int ntx;
   const int nb = tiles_of(h, &ntx);
-  hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(1024), 0, s, h->partial, nb, out);
+  if (nb <= kOneGroupMinima) {
+    hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(1024), 0, s, h->partial, nb, out);
+  } else {
+    hipLaunchKernelGGL(chunk_min_kernel, dim3(kChunks), dim3(1024), 0, s, h->partial, nb, h->partial + nb);
+    hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(1024), 0, s, h->partial + nb, kChunks, out);
+  }
   return hipGetLastError();
 }
 
@@ -424,6 +444,20 @@ __global__ __launch_bounds__(256) void segmented_min_kernel(const double* partia
   if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) out[s] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(1024) void chunk_min_kernel(const double* partial, int n, double* out) {
+  __shared__ double red[16];
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int b = (int)blockIdx.x * chunk, e = min(n, b + chunk);
+  double v = wave_min63(strided_min<1024>(partial, b, e));
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = red[0];
+    for (int i = 1; i < 16; ++i) v = fmin(v, red[i]);
+    out[blockIdx.x] = v;
+  }
 }
 
 __global__ __launch_bounds__(1024) void min_reduce_kernel(const double* partial, int n, double* out) {
