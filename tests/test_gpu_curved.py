@@ -333,9 +333,9 @@ def random_curved_case(rng):
     return prob, u
 
 
-# 60 cases from seed 7000 in the suite; a longer sweep with other seeds:
+# 200 cases from seed 7000 in the suite; a longer sweep with other seeds:
 # IDP_CURVED_CASES=<n> IDP_CURVED_SEED=<first seed> pytest -m gpu tests/test_gpu_curved.py
-CURVED_CASES = int(os.environ.get("IDP_CURVED_CASES", "60"))
+CURVED_CASES = int(os.environ.get("IDP_CURVED_CASES", "200"))
 CURVED_SEED0 = int(os.environ.get("IDP_CURVED_SEED", "7000"))
 
 

@@ -18,9 +18,9 @@ from paper_2004_08503_amd import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-# 120 cases from seed 5000 in the suite; a longer sweep with other seeds:
+# 500 cases from seed 5000 in the suite; a longer sweep with other seeds:
 # IDP_SWEEP_CASES=<n> IDP_SWEEP_SEED=<first seed> pytest -m gpu tests/test_gpu_sweep.py
-CASES = int(os.environ.get("IDP_SWEEP_CASES", "120"))
+CASES = int(os.environ.get("IDP_SWEEP_CASES", "500"))
 SEED0 = int(os.environ.get("IDP_SWEEP_SEED", "5000"))
 
 
