@@ -747,6 +747,7 @@ __device__ inline void load_tile(double* lds, const double* __restrict__ u, long
     for (int q = 0; q < NXW; ++q) lds[C::A_X + q * C::CSU + t] = X[q];
     if constexpr (FLUX && is_euler(EQ)) lds[C::S_AL + t] = X[4];
     if constexpr (CURV) {
+#pragma clang fp contract(off)
       double Fx[NC], Fy[NC];
       flux_k<EQ, DIM>(0, Uown, X, pr, ph, Fx);
       flux_k<EQ, DIM>(1, Uown, X, pr, ph, Fy);
@@ -959,12 +960,17 @@ __device__ inline int chunk_dir(int ch) {
 // ----------------------------------------------------------------------
 // curved meshes (Sec. 2.3 metric terms, Sec. 3.1 corrected terms)
 // ----------------------------------------------------------------------
+// The curved-only code below (and the curved blocks of load_tile and
+// dt_face) is compiled without multiply-add contraction: the compiler
+// otherwise fuses its products of metric terms and fluxes differently in
+// the plain and the batched kernels, whose results must agree bitwise.
 
 // The flux along a (scaled) normal n, F(U) . n.  X: the auxiliaries (Euler
 // 1/rho first).
 template <int EQ, int DIM>
 __device__ inline void flux_dot(const double* U, const double* X, const Phys& ph, const double* n,
                                 double* Fn) {
+#pragma clang fp contract(off)
   if constexpr (EQ == EQ_ADV) {
     Fn[0] = (ph.vel0 * n[0] + ph.vel1 * n[1]) * U[0];
   } else if constexpr (EQ == EQ_BURG) {
@@ -985,6 +991,7 @@ __device__ inline void flux_dot(const double* U, const double* X, const Phys& ph
 template <int EQ, int DIM>
 __device__ inline double lambda_n(const double* UL, const double* XL, const double* UR, const double* XR,
                                   const double* nh, const Phys& ph) {
+#pragma clang fp contract(off)
   if constexpr (EQ == EQ_ADV) {
     return fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
   } else if constexpr (EQ == EQ_BURG) {
@@ -999,6 +1006,7 @@ __device__ inline double lambda_n(const double* UL, const double* XL, const doub
 // vector (the momentum for Euler).
 template <int EQ>
 __device__ inline void flux_diff0(const double* UL, const double* UR, const Phys& ph, double* d) {
+#pragma clang fp contract(off)
   if constexpr (is_euler(EQ)) {
     d[0] = UR[1] - UL[1];
     d[1] = UR[2] - UL[2];
@@ -1027,6 +1035,7 @@ __device__ inline void flux_diff0(const double* UL, const double* UR, const Phys
 template <int EQ, int DIM, int P, int TX, int TY, int K, bool INT>
 __device__ __forceinline__ void face_item_c(const double* lds, const Phys& ph, int q, const TileGeo& tg,
                                             double* FLo, double* RBo, double& UBo, double& UBo2, int& o) {
+#pragma clang fp contract(off)
   using C = Cfg<EQ, DIM, P, TX, TY, true>;
   constexpr int NC = C::NC, N1 = C::N1, GX = C::GX, NX = C::NAUX > 0 ? C::NAUX : 1;
   int i, j, f = 0, el;
@@ -1695,6 +1704,7 @@ __device__ inline double lambda_ws(const double* wl, const double* wr, const Phy
 // (gamma+1)/(2 gamma p)).
 template <int EQ, int DIM>
 __device__ inline double lambda_ws_n(const double* wl, const double* wr, const double* nh, const Phys& ph) {
+#pragma clang fp contract(off)
   if constexpr (EQ == EQ_ADV) {
     return fabs(ph.vel0 * nh[0] + ph.vel1 * nh[1]);
   } else if constexpr (EQ == EQ_BURG) {
@@ -1738,6 +1748,7 @@ __device__ __forceinline__ void dt_face(double* lds, const Phys& ph, int q, cons
   }
   double lam;
   if constexpr (CURV) {
+#pragma clang fp contract(off)
     const double* M = lds + D::WM;
     const bool elem = (K == 0 ? i : j) % N1 == 0;   // an element face
     if (elem) {
