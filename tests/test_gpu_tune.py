@@ -111,3 +111,57 @@ def test_batch_tune_keeps_bitwise_equality_with_plain():
     b.close()
     for sv in solvers:
         sv.close()
+
+
+FAMILIES = [("advection", W.ADVECTION, 1.4), ("burgers", W.BURGERS, 1.4), ("euler75", W.EULER, 1.4),
+            ("euler53", W.EULER, 5.0 / 3.0), ("euler13", W.EULER, 1.3), ("field", W.ADVECTION_FIELD, 1.4)]
+GRID = [(dim, name, eq, gamma, p) for dim in (2, 1) for name, eq, gamma in FAMILIES
+        for p in range(1, 9) if not (dim == 1 and eq == W.ADVECTION_FIELD)]
+
+
+def grid_case(dim, eq, gamma, p, lim, open_sides, seed):
+    """A ragged mesh (13 x 7 elements, 70 in 1-D) of the family with random
+    data, periodic or with random per-node conditions on every open side."""
+    rng = np.random.default_rng(seed)
+    prob = W.Problem(dim=dim, nx=13 if dim == 2 else 70, ny=7 if dim == 2 else 1, p=p, eq=eq, gamma=gamma,
+                     limiter=lim, vel=(0.7, -0.4), lx=1.3, ly=0.9,
+                     bc=((1, 1) if dim == 2 else (1, 0)) if open_sides else (0, 0))
+    if eq == W.ADVECTION_FIELD:
+        vr, vc = W.rotation_lines(prob, omega=3.0, centre=(0.6, 0.4))
+        prob = prob.replace(vrows=vr, vcols=vc)
+    u = W.euler_quadrants(prob, rng) if eq == W.EULER else rng.uniform(-1.0, 1.0, (1, prob.num_nodes))
+    if open_sides:
+        types, states = [None] * 4, [None] * 4
+        codes = np.array([W.BC_STATE, W.BC_OUTFLOW, W.BC_SLIP], dtype=np.int8)
+        for side in range(4):
+            if prob.bc[side // 2]:
+                n = W.side_nodes(prob, side)
+                types[side] = rng.choice(codes, n)
+                states[side] = np.ascontiguousarray(u[:, rng.integers(0, u.shape[1], n)])
+        prob = prob.replace(bnd=W.Boundary(types, states))
+    lo, hi = float(u[0].min()), float(u[0].max())
+    return prob.replace(gmin=lo - 0.1 * abs(lo), gmax=hi + 0.1 * abs(hi)), u
+
+
+@pytest.mark.parametrize("dim,name,eq,gamma,p", GRID, ids=["%dd-%s-p%d" % (g[0], g[1], g[4]) for g in GRID])
+def test_tile_shapes_bitwise_every_family_mode_and_side(dim, name, eq, gamma, p):
+    """Both tile shapes of every kernel family and degree, in every limiter
+    mode, periodic and with open sides: two device-timestepped steps equal
+    bitwise, with the same time steps (the kernels of the two shapes are
+    different instantiations, so this also checks that the compiler's
+    multiply-add fusion does not depend on the tile)."""
+    idp_dg = _gpu()
+    for lim in range(5):
+        for open_sides in (False, True):
+            prob, u0 = grid_case(dim, eq, gamma, p, lim, open_sides, 100 * p + 10 * lim + open_sides)
+            outs = []
+            for shape in range(idp_dg.Solver.NUM_TILE_SHAPES):
+                sv = idp_dg.Solver(prob)
+                sv.set_tile_shape(shape)
+                u = torch.from_numpy(u0.copy()).cuda()
+                for _ in range(2):
+                    sv.step_cfl(u, 0.5)
+                outs.append((u.cpu(), sv.last_dt()))
+                sv.close()
+            for o, d in outs[1:]:
+                assert torch.equal(o, outs[0][0]) and d == outs[0][1], (lim, open_sides)
