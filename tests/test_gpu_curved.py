@@ -300,6 +300,47 @@ def test_mesh_replaced_between_steps():
     sv.close()
 
 
+def test_set_mesh_waits_for_a_batch_on_another_stream():
+    """A mesh replaced while a batch holding the handle still has steps
+    queued on its own stream: idp_dg_set_mesh waits for the whole device
+    before it overwrites the metric array, so the queued steps use the old
+    mesh and the later ones the new mesh, exactly as when the caller
+    synchronises first (on a mesh large enough that the queued steps are
+    usually still running when the host reaches the call)."""
+    idp_dg = _gpu()
+    prob, u = case("euler", 4, 48, 40, seed=17, amp=0.03)
+    coords_b = W.perturbed_coords(prob.replace(coords=None), 0.06)
+    runs = []
+    for sync_first in (False, True):
+        sv = idp_dg.Solver(prob)
+        side = torch.cuda.Stream()
+        batch = idp_dg.Batch([sv], stream=side)
+        ud = dev(u)
+        torch.cuda.synchronize()
+        dts = []
+        for _ in range(6):
+            batch.step_cfl([ud], 0.5)
+        if sync_first:
+            torch.cuda.synchronize()
+        sv.set_mesh(coords_b)
+        dts.append(batch.last_dt())
+        for _ in range(6):
+            batch.step_cfl([ud], 0.5)
+        torch.cuda.synchronize()
+        dts.append(batch.last_dt())
+        runs.append((ud.cpu(), dts))
+        batch.close()
+        sv.close()
+    assert torch.equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+    # and the result is the oracle's on the two meshes
+    ref = u
+    prob_b = prob.replace(coords=coords_b)
+    for k in range(12):
+        pr = prob if k < 6 else prob_b
+        ref = oracle.step(pr, ref, 0.5 * oracle.max_dt(pr, ref))
+    assert rel_err(runs[0][0].numpy(), ref) <= 1e-10
+
+
 def random_curved_case(rng):
     """A seeded random curved configuration: equation (advection, Burgers,
     Euler with one of four gammas), degree 1..8, 1..10 x 1..8 elements with
